@@ -1,0 +1,200 @@
+/*
+ * pdg.h - C ABI of the MI355X (gfx950) implementation of the hot path of the
+ * Palindromic Discontinuous Galerkin kinetic scheme (Badwaik et al.,
+ * "Task-based parallelization of an implicit kinetic scheme", arXiv 1702.00169):
+ * the implicit upwind-DG transport sweep and the local BGK relaxation.
+ *
+ * Model (Sec. 2, eq. kin_bgk).  nv transport equations at constant velocities
+ * v_i, each carrying m components f_{i,k}, coupled by the relaxation
+ * f <- f + omega (f^eq(w) - f) with w_k = sum_i f_{i,k} (eq. micro_to_macro).
+ * Space: nodal DG on Gauss-Lobatto points of uniform Cartesian hexahedra
+ * (Sec. 3.1, eq. DG_reduit).  Time: the theta-scheme transport step
+ * (eq. transport_cn, theta = 1/2 gives T_2) and the collision update
+ * (eq. collision_cn).  The upwind flux makes the transport matrix block
+ * triangular in a topological order of the upwind dependency graph (Sec. 4.1),
+ * so each implicit step is solved by a downwind sweep.
+ *
+ * Supported here: D in {2, 3}, degree d in 1..4, velocity sets made of
+ * axis-aligned non-zero velocities (+-lambda e_k).  For such velocities the
+ * cell block I + theta dt Gamma_{L<-L} factorises as a Kronecker product of a
+ * (d+1) x (d+1) one-dimensional block with the identity, and the dependency
+ * graph splits into independent lines of cells along the velocity axis.
+ *
+ * Conventions used by every entry point:
+ *  - Status codes are returned synchronously; the library never aborts and no
+ *    exception crosses the ABI.  Argument and state errors are detected on the
+ *    host before anything is launched.  An asynchronous device error is
+ *    reported as PDG_EDEVICE by the next call that checks the device.
+ *  - Device pointers are plain HIP device allocations owned by the caller
+ *    (for example torch tensors on "cuda", passed by data_ptr()); the library
+ *    never frees them and never keeps them beyond the call, except that
+ *    pdg_step keeps a cached graph keyed by (f, fb) that it rebuilds when they
+ *    change.  Host pointers are read or written only during the call.
+ *  - `stream` is a hipStream_t (NULL = the legacy default stream); all device
+ *    work is enqueued on it in order.  A context is not thread safe.
+ *  - Layouts (element offsets within one instance; instances are
+ *    concatenated, offsets from pdg_layout):
+ *      node j   = jx + (d+1) jy + (d+1)^2 jz          (Gauss-Lobatto tensor index)
+ *      cell c   = x + nx y + nx ny z                   (lexicographic, x fastest)
+ *      f[v][k][j][c]      nv * m * Nd * Nc values, Nd = (d+1)^D, Nc = nx ny nz
+ *      w[k][j][c]         m * Nd * Nc values
+ *      fb[v][k][t][tau]   inflow boundary values of velocity v: for an axis-a
+ *                         velocity, t enumerates the node indices of the other
+ *                         axes (increasing axis order, first fastest) and tau
+ *                         the cell indices of the other axes (same order);
+ *                         (d+1)^(D-1) * Nc / n_a values per (v, k).
+ */
+#ifndef PDG_H
+#define PDG_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct pdg_ctx pdg_ctx; /* opaque, owned by the library */
+
+typedef enum {
+  PDG_OK = 0,
+  PDG_EINVAL = 1,       /* bad argument (null pointer, size, non-finite value) */
+  PDG_EUNSUPPORTED = 2, /* valid but outside what this build implements */
+  PDG_ENOTDAG = 3,      /* an upwind dependency graph has a cycle */
+  PDG_ESINGULAR = 4,    /* a cell block I + theta dt Gamma_LL is singular */
+  PDG_ENOMEM = 5,       /* host or device allocation failed */
+  PDG_EDEVICE = 6,      /* HIP runtime or kernel error */
+  PDG_ESTATE = 7        /* call out of order (e.g. sweep before prepare) */
+} pdg_status;
+
+typedef enum {
+  PDG_FP64 = 0,        /* state and arithmetic in binary64 */
+  PDG_FP32 = 1,        /* state and arithmetic in binary32 (moments in binary64) */
+  PDG_FP32_REFINE = 2  /* binary64 state; binary32 cell solves with one binary64
+                          residual correction per cell */
+} pdg_precision;
+
+typedef enum {
+  PDG_FEQ_ADVECTION = 0, /* q^k(w) = a_k w; feq_param = {a_1, .., a_D} */
+  PDG_FEQ_EULER = 1      /* compressible Euler, m = D + 2; feq_param = {gamma} */
+} pdg_feq_kind;
+
+typedef enum {
+  PDG_LIE = 0,             /* [T(dt) C]^N */
+  PDG_STRANG = 1,          /* [T(dt/2) C T(dt/2)]^N  (M_2, Sec. 3.2) */
+  PDG_STRANG_COLLAPSED = 2 /* T(dt/2) C [T(dt) C]^(N-1) T(dt/2)  (Sec. 5.1) */
+} pdg_scheme;
+
+/* One independent kinetic problem.  The equilibrium (Sec. 2: P f^eq = P f and
+ * q^k = P V^k f^eq, depending on w only) is taken as
+ *   f_i^eq = w / nv + v_i . Q(w) / (2 lambda^2),  Q = (q^1, .., q^D),
+ * which meets both moment conditions when the velocities are {+-lambda e_k}
+ * (nv = 2D).  Transport alone accepts any set of non-zero axis-aligned
+ * velocities; pdg_relax and the equilibrium helpers need the full
+ * {+-lambda e_k} set. */
+typedef struct {
+  int32_t dim;          /* D, 2 or 3 */
+  int32_t n[3];         /* cells per axis; n[2] is ignored when D = 2 */
+  int32_t degree;       /* d, 1..4 */
+  int32_t nv;           /* number of velocities, 1..27 */
+  int32_t m;            /* components per velocity, 1..8 */
+  double lo[3], hi[3];  /* box; uniform cells of size (hi - lo) / n */
+  const double *v;      /* host, nv * dim, row-major; copied */
+  int32_t feq;          /* pdg_feq_kind */
+  double feq_param[4];  /* see pdg_feq_kind */
+} pdg_instance_desc;
+
+/* Build a context for n_inst independent instances (Sec. 4.1): validate the
+ * descriptors, build each velocity's upwind dependency graph (edge L -> R when
+ * n_LR . v > 0 on the common face), order it by Kahn's algorithm into levels,
+ * reject cycles (PDG_ENOTDAG), and group the cells into lines along each
+ * velocity axis.  Host only: no device memory is touched.  *out receives a
+ * context to be released with pdg_destroy; it is untouched on error. */
+pdg_status pdg_setup_mesh(const pdg_instance_desc *inst, int32_t n_inst, pdg_ctx **out);
+
+/* Sizes (in elements) of the f, w and fb buffers for all instances, and the
+ * per-instance start offsets (arrays of n_inst + 1 entries each; the last is
+ * the total).  Any output pointer may be NULL. */
+pdg_status pdg_layout(const pdg_ctx *c, int64_t *f_elems, int64_t *w_elems, int64_t *fb_elems,
+                      int64_t *inst_f_offsets, int64_t *inst_w_offsets, int64_t *inst_fb_offsets);
+
+/* Physical coordinates of instance `inst` (host buffers, may be NULL):
+ * vol_xyz[D][j][c] of every Gauss-Lobatto point (eq. map_GL), and
+ * inflow_xyz[v][D][t][tau] of the inflow boundary points at which fb is read
+ * (one block of D * (d+1)^(D-1) * Nc/n_a values per velocity). */
+pdg_status pdg_node_coords(const pdg_ctx *c, int32_t inst, double *vol_xyz, double *inflow_xyz);
+
+/* Topological level (longest upwind path from the inflow boundary, Sec. 4.1)
+ * of every cell of instance `inst` for velocity `vel`; level[c], host. */
+pdg_status pdg_levels(const pdg_ctx *c, int32_t inst, int32_t vel, int32_t *level);
+
+/* Kahn layering of an arbitrary directed graph (host utility used by setup):
+ * level[i] = longest path length from a source; PDG_ENOTDAG on a cycle. */
+pdg_status pdg_topo_levels(int32_t n_nodes, int64_t n_edges, const int32_t *src, const int32_t *dst,
+                           int32_t *level);
+
+/* Host introspection of the cell operator used for (inst, vel): the
+ * one-dimensional block Gamma (row-major (d+1) x (d+1), downwind-local node
+ * order: node 0 on the inflow face) of eq. DG_reduit along the velocity axis,
+ * and the inflow coefficient kappa such that the upwind coupling
+ * Gamma_{L<-R} is -kappa at the inflow node.  The full cell block is the
+ * Kronecker product of this block with the identity on the transverse nodes.
+ * Host only; gamma holds (d+1)^2 values. */
+pdg_status pdg_line_operator(const pdg_ctx *c, int32_t inst, int32_t vel, double *gamma, double *kappa);
+
+/* Prepare the time step (Sec. 3.2): for every instance, velocity and
+ * sub-step size dt_sub in {dt, dt/2}, build on the host in binary64 the
+ * one-dimensional cell blocks A = I + theta dt_sub Gamma_{L<-L} and
+ * B = I - (1-theta) dt_sub Gamma_{L<-L} of eq. DG_reduit, invert A on the device
+ * in binary64 (Gauss-Jordan with partial pivoting, PDG_ESINGULAR on a pivot
+ * below 1e-300 times the block norm) and keep binary64 and binary32 copies.
+ * omega is the collision factor of eq. collision_cn (2 dt/(2 tau + dt); 2 is
+ * tau = 0).  Allocates the context's device tables; synchronises `stream`.
+ * theta in (0, 1], dt finite and non-zero (negative dt runs time backwards). */
+pdg_status pdg_prepare(pdg_ctx *c, double dt, double theta, double omega, pdg_scheme scheme,
+                       pdg_precision prec, void *stream);
+
+/* f = f^eq(w) at every node (device; w[k][j][c] binary64 per instance,
+ * f in the state precision).  Sets an initial state (Sec. 2). */
+pdg_status pdg_equilibrium(pdg_ctx *c, const double *w, void *f, void *stream);
+
+/* fb[v][k][t][tau] = f^eq_{v,k}(w_inflow[v][:][t][tau]) (device, binary64):
+ * w_inflow has the fb layout with m values per (v, t, tau) taken from the
+ * macroscopic field at the inflow points of velocity v. */
+pdg_status pdg_inflow_equilibrium(pdg_ctx *c, const double *w_inflow, double *fb, void *stream);
+
+/* One theta-scheme transport step of size dt_sub (dt or dt/2 as prepared) for
+ * every instance, velocity and component, in place on f (Sec. 4.1-4.2,
+ * eq. transport_cn): solves
+ *   (I - theta dt L_h) F^new = (I + (1-theta) dt L_h) F^old
+ *                              + dt (theta b(fb_new) + (1-theta) b(fb_old))
+ * cell by cell in downwind order.  fb_old/fb_new: inflow data at the old and
+ * new time (the same pointer for time-independent data).  PDG_ESTATE if
+ * dt_sub was not prepared. */
+pdg_status pdg_transport_sweep(pdg_ctx *c, void *f, const double *fb_old, const double *fb_new,
+                               double dt_sub, void *stream);
+
+/* Collision step (eq. collision_cn, Sec. 4.4): at every node
+ * w = sum_i f_i (compensated binary64 sum), then f_i <- f_i + omega (f_i^eq(w) - f_i).
+ * w_out (nullable, device binary64, w layout) receives w. */
+pdg_status pdg_relax(pdg_ctx *c, void *f, double *w_out, void *stream);
+
+/* n_steps time steps of the prepared scheme with time-independent inflow fb
+ * (Sec. 3.2 and Sec. 5.1).  The interior step (relax + full transport) is
+ * recorded once as a HIP graph per (f, fb) pair and replayed. */
+pdg_status pdg_step(pdg_ctx *c, void *f, const double *fb, int32_t n_steps, void *stream);
+
+/* For PDG_FP32_REFINE: max over nodes of |correction| / max |solution| seen by
+ * the most recent sweep (synchronises the stream of that sweep). */
+pdg_status pdg_last_refine_correction(const pdg_ctx *c, double *max_rel_correction);
+
+/* Human-readable name of a status code (static storage). */
+const char *pdg_status_string(pdg_status s);
+
+/* Release the context and its device tables (NULL is a no-op). */
+void pdg_destroy(pdg_ctx *c);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* PDG_H */

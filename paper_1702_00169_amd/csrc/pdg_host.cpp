@@ -1,0 +1,956 @@
+// Host runtime of the PDG transport sweep + relaxation library (C ABI in
+// include/pdg.h).
+//
+//  * setup (Sec. 4.1): per instance and velocity, the upwind dependency graph
+//    of the Cartesian mesh (edge L -> R when the face normal n_LR has
+//    n_LR . v > 0), its Kahn layering into levels, rejection of cycles, and the
+//    grouping of cells into chains (lines along the velocity axis);
+//  * prepare (Sec. 3.1-3.2): the one-dimensional cell blocks of eq. DG_reduit
+//    built in binary64 from the Gauss-Lobatto rule, the device inversion, the
+//    work items and launch groups of the sweep and relax kernels;
+//  * run: sweeps, relaxations and step compositions, with the interior step
+//    recorded once as a HIP graph and replayed.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <map>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "../../include/pdg.h"
+#include "pdg_internal.h"
+
+using namespace pdg;
+
+namespace {
+
+struct Instance {
+  pdg_instance_desc d;
+  std::vector<double> v;     // nv * dim
+  int64_t nc, nd, np;
+  int64_t f_off, w_off, fb_off;
+  std::vector<int64_t> fb_vel_off;  // per velocity, offset within the instance's fb block
+  std::vector<int> axis;            // per velocity: axis of the velocity, -1 if not axis-aligned
+  std::vector<int> sign;
+  double h[3];
+  int64_t n[3];
+};
+
+struct Group {
+  int np, S, C, x_kind;
+  int64_t first, count;  // range in the item array
+};
+
+struct RelaxGroup {
+  int nv, m;
+  int64_t first, count;
+};
+
+template <class T>
+struct DevBuf {
+  T *p = nullptr;
+  size_t n = 0;
+  void release() {
+    if (p) (void)hipFree(p);
+    p = nullptr;
+    n = 0;
+  }
+  hipError_t upload(const std::vector<T> &h) {
+    release();
+    if (h.empty()) return hipSuccess;
+    hipError_t e = hipMalloc(reinterpret_cast<void **>(&p), h.size() * sizeof(T));
+    if (e != hipSuccess) {
+      p = nullptr;
+      return e;
+    }
+    n = h.size();
+    return hipMemcpy(p, h.data(), h.size() * sizeof(T), hipMemcpyHostToDevice);
+  }
+};
+
+}  // namespace
+
+struct pdg_ctx {
+  std::vector<Instance> inst;
+  int64_t f_elems = 0, w_elems = 0, fb_elems = 0;
+  // prepared state
+  bool prepared = false;
+  double dt = 0, theta = 0, omega = 0;
+  int scheme = 0, prec = 0;
+  std::vector<OpEntry> ops_h;
+  DevBuf<OpEntry> ops;
+  DevBuf<SweepDesc> sdesc;
+  DevBuf<SweepItem> sitems;
+  std::vector<Group> groups;
+  DevBuf<RelaxDesc> rdesc;
+  DevBuf<RelaxItem> ritems;
+  std::vector<RelaxGroup> rgroups;
+  DevBuf<InflowDesc> idesc;
+  std::vector<RelaxGroup> igroups;  // (nv, m, first, count) over idesc
+  DevBuf<double> stats;             // 2 doubles per sweep workgroup
+  hipStream_t cap_stream = nullptr;
+  // graph cache of the interior step
+  hipGraphExec_t gexec = nullptr;
+  void *g_f = nullptr;
+  const double *g_fb = nullptr;
+  bool stats_valid = false;
+  hipStream_t last_stream = nullptr;
+
+  void release_device() {
+    if (gexec) (void)hipGraphExecDestroy(gexec);
+    gexec = nullptr;
+    g_f = nullptr;
+    g_fb = nullptr;
+    ops.release();
+    sdesc.release();
+    sitems.release();
+    rdesc.release();
+    ritems.release();
+    idesc.release();
+    stats.release();
+    if (cap_stream) (void)hipStreamDestroy(cap_stream);
+    cap_stream = nullptr;
+    groups.clear();
+    rgroups.clear();
+    igroups.clear();
+    prepared = false;
+    stats_valid = false;
+  }
+};
+
+namespace {
+
+// ---------------------------------------------------------------------------
+// one-dimensional Gauss-Lobatto rule (Sec. 3.1, eq. map_GL)
+// ---------------------------------------------------------------------------
+// Legendre P_k(x) by the three-term recurrence.
+double legendre(int k, double x) {
+  if (k == 0) return 1.0;
+  double p0 = 1.0, p1 = x;
+  for (int j = 2; j <= k; ++j) {
+    const double p2 = ((2.0 * j - 1.0) * x * p1 - (j - 1.0) * p0) / j;
+    p0 = p1;
+    p1 = p2;
+  }
+  return p1;
+}
+
+// Nodes: zeros of (1 - x^2) P_d'(x), found as the zeros of P_{d+1} - P_{d-1}
+// (whose derivative is (2d+1) P_d) by Newton iteration from the
+// Chebyshev-Lobatto points.  Weights 2 / (d (d+1) P_d(x)^2).
+void gauss_lobatto(int d, std::vector<double> &x, std::vector<double> &w) {
+  x.assign(d + 1, 0.0);
+  w.assign(d + 1, 0.0);
+  for (int j = 0; j <= d; ++j) {
+    double t = -std::cos(M_PI * j / d);
+    if (j > 0 && j < d) {
+      for (int it = 0; it < 100; ++it) {
+        const double fval = legendre(d + 1, t) - legendre(d - 1, t);
+        const double dval = (2.0 * d + 1.0) * legendre(d, t);
+        const double step = fval / dval;
+        t -= step;
+        if (std::fabs(step) < 1e-17) break;
+      }
+    }
+    x[j] = t;
+  }
+  x[0] = -1.0;
+  x[d] = 1.0;
+  if (d % 2 == 0) x[d / 2] = 0.0;
+  for (int j = 0; j <= d; ++j) {
+    const double p = legendre(d, x[j]);
+    w[j] = 2.0 / (d * (d + 1.0) * p * p);
+  }
+}
+
+// Dm[a][b] = l_b'(x_a) by the barycentric formula:
+// lam_b = 1 / prod_{k != b} (x_b - x_k); Dm[a][b] = (lam_b / lam_a) / (x_a - x_b) (a != b),
+// Dm[a][a] = -sum_{b != a} Dm[a][b].
+std::vector<double> derivative_matrix(const std::vector<double> &x) {
+  const int n = (int)x.size();
+  std::vector<double> lam(n, 1.0), dm(n * n, 0.0);
+  for (int b = 0; b < n; ++b) {
+    double prod = 1.0;
+    for (int k = 0; k < n; ++k)
+      if (k != b) prod *= x[b] - x[k];
+    lam[b] = 1.0 / prod;
+  }
+  for (int a = 0; a < n; ++a) {
+    double diag = 0.0;
+    for (int b = 0; b < n; ++b) {
+      if (a == b) continue;
+      dm[a * n + b] = (lam[b] / lam[a]) / (x[a] - x[b]);
+      diag -= dm[a * n + b];
+    }
+    dm[a * n + a] = diag;
+  }
+  return dm;
+}
+
+// One-dimensional block Gamma of eq. DG_reduit for speed V > 0 along the line
+// and cell length h, in downwind-local node order (node 0 on the inflow face):
+//   Gamma_ij = -(1/w_i) (2V/h) Dm[j][i] w_j              (volume term)
+//            + delta_{i,NP-1} (1/w_{NP-1}) (2V/h)          (outflow face, (v.n)^+)
+// and the inflow face coupling (1/w_0) (2V/h) (v.n)^- / V = -(2V/h)/w_0 at node 0.
+void line_block(int d, double V, double h, std::vector<double> &gam, double &inflow_coef) {
+  std::vector<double> x, w;
+  gauss_lobatto(d, x, w);
+  const std::vector<double> dm = derivative_matrix(x);
+  const int np = d + 1;
+  const double s = 2.0 * V / h;
+  gam.assign(np * np, 0.0);
+  for (int i = 0; i < np; ++i)
+    for (int j = 0; j < np; ++j) gam[i * np + j] = -(s * dm[j * np + i] * w[j]) / w[i];
+  gam[(np - 1) * np + (np - 1)] += s / w[np - 1];
+  inflow_coef = s / w[0];  // magnitude of -(Gamma_{L<-R}) at node 0
+}
+
+bool is_finite(double x) { return std::isfinite(x); }
+
+pdg_status from_hip(hipError_t e) {
+  if (e == hipSuccess) return PDG_OK;
+  if (e == hipErrorOutOfMemory) return PDG_ENOMEM;
+  return PDG_EDEVICE;
+}
+
+// ---------------------------------------------------------------------------
+// dependency graph of a velocity on a Cartesian mesh and its Kahn layering
+// ---------------------------------------------------------------------------
+// Faces are axis-aligned, the scaled normal from L to its +e_k neighbour is
+// a positive multiple of e_k, so the edge L -> L+e_k exists iff v_k > 0 and
+// L+e_k -> L iff v_k < 0 (the same sign at every GL point of the face).
+pdg_status mesh_levels(const Instance &in, int vel, std::vector<int32_t> &level) {
+  const int dim = in.d.dim;
+  const int64_t nc = in.nc;
+  const double *v = &in.v[(size_t)vel * dim];
+  std::vector<int32_t> indeg(nc, 0);
+  int64_t stride[3] = {1, in.n[0], in.n[0] * in.n[1]};
+  auto coord = [&](int64_t c, int k) { return (c / stride[k]) % in.n[k]; };
+  for (int64_t c = 0; c < nc; ++c)
+    for (int k = 0; k < dim; ++k) {
+      if (v[k] > 0 && coord(c, k) > 0) indeg[c]++;
+      if (v[k] < 0 && coord(c, k) < in.n[k] - 1) indeg[c]++;
+    }
+  level.assign(nc, -1);
+  std::vector<int64_t> frontier, next;
+  for (int64_t c = 0; c < nc; ++c)
+    if (indeg[c] == 0) frontier.push_back(c);
+  int32_t lev = 0;
+  int64_t done = 0;
+  while (!frontier.empty()) {
+    next.clear();
+    for (int64_t c : frontier) {
+      level[c] = lev;
+      ++done;
+      for (int k = 0; k < dim; ++k) {
+        int64_t r = -1;
+        if (v[k] > 0 && coord(c, k) < in.n[k] - 1) r = c + stride[k];
+        if (v[k] < 0 && coord(c, k) > 0) r = c - stride[k];
+        if (r >= 0 && --indeg[r] == 0) next.push_back(r);
+      }
+    }
+    frontier.swap(next);
+    ++lev;
+  }
+  return done == nc ? PDG_OK : PDG_ENOTDAG;
+}
+
+// ---------------------------------------------------------------------------
+// tile choice of the sweep (lanes per chain group C, cells per segment S)
+// ---------------------------------------------------------------------------
+int pow2_ceil(int x) {
+  int p = 1;
+  while (p < x) p <<= 1;
+  return p;
+}
+
+void choose_tile(int prec, int np, int n, int64_t ntc, int x_kind, int &C, int &S) {
+  if (const char *env = std::getenv("PDG_TILE")) {
+    // "C,S" override for tuning sweeps
+    int c2 = 0, s2 = 0;
+    if (std::sscanf(env, "%d,%d", &c2, &s2) == 2 && c2 > 0 && s2 > 0) {
+      if (!x_kind || (kBlock / c2) * s2 >= n) {
+        C = c2;
+        S = s2;
+        return;
+      }
+    }
+  }
+  if (x_kind) {
+    // one window covers the whole row: (kBlock / C) * S >= n and the LDS tile
+    // fits in 48 KiB; prefer the smallest S with at most 32 segments per row
+    int best = -1;
+    for (int s = 1; s <= 8; s <<= 1) {
+      if (sweep_lds_bytes(prec, np, s, 1) > 49152 || (int64_t)kBlock * s < n) continue;
+      best = s;
+      if ((n + s - 1) / s <= 32) break;
+    }
+    S = best < 0 ? 8 : best;
+    int P = std::min(kBlock, pow2_ceil((n + S - 1) / S));
+    C = kBlock / P;
+    return;
+  }
+  // strided axis: C consecutive chains per lane group, P = kBlock / C segments
+  C = (int)std::min<int64_t>(64, pow2_ceil((int)std::min<int64_t>(ntc, 64)));
+  C = std::max(C, 8);
+  int P = kBlock / C;
+  S = 1;
+  while (S < 8 && P * S < n) S <<= 1;
+}
+
+}  // namespace
+
+// ===========================================================================
+// C ABI
+// ===========================================================================
+extern "C" {
+
+const char *pdg_status_string(pdg_status s) {
+  switch (s) {
+    case PDG_OK: return "PDG_OK";
+    case PDG_EINVAL: return "PDG_EINVAL: invalid argument";
+    case PDG_EUNSUPPORTED: return "PDG_EUNSUPPORTED: not supported by this build";
+    case PDG_ENOTDAG: return "PDG_ENOTDAG: dependency graph has a cycle";
+    case PDG_ESINGULAR: return "PDG_ESINGULAR: singular cell block";
+    case PDG_ENOMEM: return "PDG_ENOMEM: out of memory";
+    case PDG_EDEVICE: return "PDG_EDEVICE: HIP device error";
+    case PDG_ESTATE: return "PDG_ESTATE: call out of order";
+  }
+  return "PDG_UNKNOWN";
+}
+
+pdg_status pdg_topo_levels(int32_t n_nodes, int64_t n_edges, const int32_t *src, const int32_t *dst,
+                           int32_t *level) {
+  if (n_nodes < 0 || n_edges < 0 || !level || (n_edges > 0 && (!src || !dst))) return PDG_EINVAL;
+  std::vector<int32_t> indeg(n_nodes, 0);
+  std::vector<int64_t> start(n_nodes + 1, 0);
+  for (int64_t e = 0; e < n_edges; ++e) {
+    if (src[e] < 0 || src[e] >= n_nodes || dst[e] < 0 || dst[e] >= n_nodes) return PDG_EINVAL;
+    indeg[dst[e]]++;
+    start[src[e] + 1]++;
+  }
+  for (int32_t i = 0; i < n_nodes; ++i) start[i + 1] += start[i];
+  std::vector<int32_t> adj(n_edges);
+  std::vector<int64_t> fill(start.begin(), start.end() - 1);
+  for (int64_t e = 0; e < n_edges; ++e) adj[fill[src[e]]++] = dst[e];
+  std::vector<int32_t> frontier, next;
+  for (int32_t i = 0; i < n_nodes; ++i) {
+    level[i] = -1;
+    if (indeg[i] == 0) frontier.push_back(i);
+  }
+  int32_t lev = 0, done = 0;
+  while (!frontier.empty()) {
+    next.clear();
+    for (int32_t i : frontier) {
+      level[i] = lev;
+      ++done;
+      for (int64_t e = start[i]; e < start[i + 1]; ++e)
+        if (--indeg[adj[e]] == 0) next.push_back(adj[e]);
+    }
+    frontier.swap(next);
+    ++lev;
+  }
+  return done == n_nodes ? PDG_OK : PDG_ENOTDAG;
+}
+
+pdg_status pdg_setup_mesh(const pdg_instance_desc *descs, int32_t n_inst, pdg_ctx **out) {
+  if (!descs || n_inst <= 0 || !out) return PDG_EINVAL;
+  pdg_ctx *c = new (std::nothrow) pdg_ctx();
+  if (!c) return PDG_ENOMEM;
+  int64_t f_off = 0, w_off = 0, fb_off = 0;
+  for (int32_t i = 0; i < n_inst; ++i) {
+    const pdg_instance_desc &d = descs[i];
+    Instance in;
+    in.d = d;
+    pdg_status err = PDG_OK;
+    if (d.dim < 2 || d.dim > 3) err = PDG_EINVAL;
+    else if (d.degree < 1 || d.nv < 1 || d.nv > kMaxNV || d.m < 1 || d.m > kMaxM || !d.v) err = PDG_EINVAL;
+    if (err == PDG_OK && d.degree > 4) err = PDG_EUNSUPPORTED;
+    if (err == PDG_OK) {
+      for (int k = 0; k < d.dim; ++k) {
+        if (d.n[k] < 1 || !is_finite(d.lo[k]) || !is_finite(d.hi[k]) || !(d.hi[k] > d.lo[k])) err = PDG_EINVAL;
+      }
+    }
+    if (err != PDG_OK) {
+      delete c;
+      return err;
+    }
+    in.d.v = nullptr;
+    in.v.assign(d.v, d.v + (size_t)d.nv * d.dim);
+    for (double x : in.v)
+      if (!is_finite(x)) {
+        delete c;
+        return PDG_EINVAL;
+      }
+    in.np = d.degree + 1;
+    in.nd = 1;
+    in.nc = 1;
+    for (int k = 0; k < 3; ++k) {
+      in.n[k] = k < d.dim ? d.n[k] : 1;
+      in.h[k] = k < d.dim ? (d.hi[k] - d.lo[k]) / d.n[k] : 1.0;
+    }
+    for (int k = 0; k < d.dim; ++k) {
+      in.nd *= in.np;
+      in.nc *= in.n[k];
+    }
+    if (in.nc > (int64_t)1 << 31) {
+      delete c;
+      return PDG_EUNSUPPORTED;
+    }
+    in.axis.assign(d.nv, -1);
+    in.sign.assign(d.nv, 0);
+    in.fb_vel_off.assign(d.nv + 1, 0);
+    int64_t fbo = 0;
+    for (int v = 0; v < d.nv; ++v) {
+      int nz = 0, ax = -1;
+      for (int k = 0; k < d.dim; ++k)
+        if (in.v[(size_t)v * d.dim + k] != 0.0) {
+          nz++;
+          ax = k;
+        }
+      if (nz == 1) {
+        in.axis[v] = ax;
+        in.sign[v] = in.v[(size_t)v * d.dim + ax] > 0 ? 1 : -1;
+      }
+      in.fb_vel_off[v] = fbo;
+      if (nz == 1) {
+        int64_t tnodes = 1;
+        for (int k = 0; k < d.dim - 1; ++k) tnodes *= in.np;
+        fbo += (int64_t)d.m * tnodes * (in.nc / in.n[ax]);
+      } else {
+        fbo += 0;  // non-axis-aligned velocities: transport not supported here
+      }
+      // the upwind dependency graph must be acyclic (Sec. 4.1)
+      std::vector<int32_t> lev;
+      pdg_status s = mesh_levels(in, v, lev);
+      if (s != PDG_OK) {
+        delete c;
+        return s;
+      }
+      if (nz == 1) {
+        // chains: the level of a cell is its downwind position along the axis
+        int64_t stride = ax == 0 ? 1 : (ax == 1 ? in.n[0] : in.n[0] * in.n[1]);
+        for (int64_t cc = 0; cc < in.nc; cc += std::max<int64_t>(1, in.nc / 997)) {
+          int64_t pos = (cc / stride) % in.n[ax];
+          int64_t want = in.sign[v] > 0 ? pos : in.n[ax] - 1 - pos;
+          if (lev[cc] != want) {
+            delete c;
+            return PDG_EDEVICE;  // internal inconsistency
+          }
+        }
+      }
+    }
+    in.fb_vel_off[d.nv] = fbo;
+    in.f_off = f_off;
+    in.w_off = w_off;
+    in.fb_off = fb_off;
+    f_off += (int64_t)d.nv * d.m * in.nd * in.nc;
+    w_off += (int64_t)d.m * in.nd * in.nc;
+    fb_off += fbo;
+    c->inst.push_back(std::move(in));
+  }
+  c->f_elems = f_off;
+  c->w_elems = w_off;
+  c->fb_elems = fb_off;
+  *out = c;
+  return PDG_OK;
+}
+
+pdg_status pdg_layout(const pdg_ctx *c, int64_t *f_elems, int64_t *w_elems, int64_t *fb_elems,
+                      int64_t *inst_f_offsets, int64_t *inst_w_offsets, int64_t *inst_fb_offsets) {
+  if (!c) return PDG_EINVAL;
+  if (f_elems) *f_elems = c->f_elems;
+  if (w_elems) *w_elems = c->w_elems;
+  if (fb_elems) *fb_elems = c->fb_elems;
+  const size_t n = c->inst.size();
+  for (size_t i = 0; i <= n; ++i) {
+    if (inst_f_offsets) inst_f_offsets[i] = i < n ? c->inst[i].f_off : c->f_elems;
+    if (inst_w_offsets) inst_w_offsets[i] = i < n ? c->inst[i].w_off : c->w_elems;
+    if (inst_fb_offsets) inst_fb_offsets[i] = i < n ? c->inst[i].fb_off : c->fb_elems;
+  }
+  return PDG_OK;
+}
+
+pdg_status pdg_node_coords(const pdg_ctx *c, int32_t inst, double *vol_xyz, double *inflow_xyz) {
+  if (!c || inst < 0 || inst >= (int32_t)c->inst.size()) return PDG_EINVAL;
+  const Instance &in = c->inst[inst];
+  const int dim = in.d.dim;
+  const int np = (int)in.np;
+  std::vector<double> x, w;
+  gauss_lobatto(in.d.degree, x, w);
+  auto pos = [&](int k, int64_t cell, int node) {
+    return in.d.lo[k] + ((double)cell + 0.5 * (x[node] + 1.0)) * in.h[k];
+  };
+  if (vol_xyz) {
+    for (int k = 0; k < dim; ++k)
+      for (int64_t j = 0; j < in.nd; ++j) {
+        int jk = (int)((j / (int64_t)std::pow(np, k)) % np);
+        for (int64_t cc = 0; cc < in.nc; ++cc) {
+          int64_t stride = k == 0 ? 1 : (k == 1 ? in.n[0] : in.n[0] * in.n[1]);
+          int64_t ck = (cc / stride) % in.n[k];
+          vol_xyz[((int64_t)k * in.nd + j) * in.nc + cc] = pos(k, ck, jk);
+        }
+      }
+  }
+  if (inflow_xyz) {
+    int64_t off = 0;
+    for (int v = 0; v < in.d.nv; ++v) {
+      const int ax = in.axis[v];
+      if (ax < 0) continue;
+      int other[2], no = 0;
+      for (int k = 0; k < dim; ++k)
+        if (k != ax) other[no++] = k;
+      const int64_t ntc = in.nc / in.n[ax];
+      int64_t tnodes = 1;
+      for (int k = 0; k < no; ++k) tnodes *= np;
+      for (int k = 0; k < dim; ++k)
+        for (int64_t t = 0; t < tnodes; ++t)
+          for (int64_t tau = 0; tau < ntc; ++tau) {
+            double val;
+            if (k == ax) {
+              val = in.sign[v] > 0 ? in.d.lo[k] : in.d.hi[k];
+            } else {
+              const int slot = (k == other[0]) ? 0 : 1;
+              const int node = slot == 0 ? (int)(t % np) : (int)(t / np);
+              const int64_t cell = slot == 0 ? tau % in.n[other[0]] : tau / in.n[other[0]];
+              val = pos(k, cell, node);
+            }
+            inflow_xyz[off + ((int64_t)k * tnodes + t) * ntc + tau] = val;
+          }
+      off += (int64_t)dim * tnodes * ntc;
+    }
+  }
+  return PDG_OK;
+}
+
+pdg_status pdg_levels(const pdg_ctx *c, int32_t inst, int32_t vel, int32_t *level) {
+  if (!c || !level || inst < 0 || inst >= (int32_t)c->inst.size()) return PDG_EINVAL;
+  const Instance &in = c->inst[inst];
+  if (vel < 0 || vel >= in.d.nv) return PDG_EINVAL;
+  std::vector<int32_t> lev;
+  pdg_status s = mesh_levels(in, vel, lev);
+  if (s != PDG_OK) return s;
+  std::memcpy(level, lev.data(), lev.size() * sizeof(int32_t));
+  return PDG_OK;
+}
+
+pdg_status pdg_line_operator(const pdg_ctx *c, int32_t inst, int32_t vel, double *gamma, double *kappa) {
+  if (!c || !gamma || !kappa || inst < 0 || inst >= (int32_t)c->inst.size()) return PDG_EINVAL;
+  const Instance &in = c->inst[inst];
+  if (vel < 0 || vel >= in.d.nv) return PDG_EINVAL;
+  const int ax = in.axis[vel];
+  if (ax < 0) return PDG_EUNSUPPORTED;
+  std::vector<double> gam;
+  line_block(in.d.degree, std::fabs(in.v[(size_t)vel * in.d.dim + ax]), in.h[ax], gam, *kappa);
+  std::memcpy(gamma, gam.data(), gam.size() * sizeof(double));
+  return PDG_OK;
+}
+
+pdg_status pdg_prepare(pdg_ctx *c, double dt, double theta, double omega, pdg_scheme scheme, pdg_precision prec,
+                       void *stream) {
+  if (!c) return PDG_EINVAL;
+  if (!is_finite(dt) || dt == 0.0 || !is_finite(theta) || !(theta > 0.0) || theta > 1.0 || !is_finite(omega))
+    return PDG_EINVAL;
+  if (scheme < PDG_LIE || scheme > PDG_STRANG_COLLAPSED) return PDG_EINVAL;
+  if (prec < PDG_FP64 || prec > PDG_FP32_REFINE) return PDG_EINVAL;
+  for (const Instance &in : c->inst)
+    for (int v = 0; v < in.d.nv; ++v)
+      if (in.axis[v] < 0) return PDG_EUNSUPPORTED;
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  c->release_device();
+
+  // ---- operator table: (instance, velocity, dt_sub in {dt, dt/2}) --------
+  std::vector<OpEntry> ops;
+  std::vector<SweepDesc> sdesc;
+  std::vector<std::vector<SweepItem>> by_group;
+  std::map<std::vector<int>, int> group_of;
+  std::vector<Group> groups;
+  for (size_t ii = 0; ii < c->inst.size(); ++ii) {
+    const Instance &in = c->inst[ii];
+    const int np = (int)in.np;
+    const int dim = in.d.dim;
+    for (int v = 0; v < in.d.nv; ++v) {
+      const int ax = in.axis[v];
+      const double V = std::fabs(in.v[(size_t)v * dim + ax]);
+      std::vector<double> gam;
+      double inflow = 0.0;
+      line_block(in.d.degree, V, in.h[ax], gam, inflow);
+      const int op_index = (int)ops.size();
+      for (int half = 0; half < 2; ++half) {
+        const double ds = half ? 0.5 * dt : dt;
+        OpEntry e;
+        std::memset(&e, 0, sizeof(e));
+        e.np = np;
+        e.theta = theta;
+        e.c0 = ds * inflow;
+        for (int i = 0; i < np; ++i)
+          for (int j = 0; j < np; ++j) {
+            const double id = i == j ? 1.0 : 0.0;
+            e.A[i * np + j] = id + theta * ds * gam[i * np + j];
+            e.B[i * np + j] = id - (1.0 - theta) * ds * gam[i * np + j];
+          }
+        ops.push_back(e);
+      }
+      // chain addressing
+      const int64_t nc = in.nc;
+      const int64_t cstride = ax == 0 ? 1 : (ax == 1 ? in.n[0] : in.n[0] * in.n[1]);
+      int64_t pstride = 1;
+      for (int k = 0; k < ax; ++k) pstride *= np;
+      pstride *= nc;
+      SweepDesc sd;
+      std::memset(&sd, 0, sizeof(sd));
+      sd.n_a = (int32_t)in.n[ax];
+      sd.cell_step = in.sign[v] > 0 ? cstride : -cstride;
+      sd.cell0 = in.sign[v] > 0 ? 0 : (in.n[ax] - 1) * cstride;
+      sd.plane_step = in.sign[v] > 0 ? pstride : -pstride;
+      sd.plane0 = in.sign[v] > 0 ? 0 : (int64_t)(np - 1) * pstride;
+      sd.op = op_index;
+      sd.x_kind = ax == 0 ? 1 : 0;
+      if (ax == 0) {
+        sd.nx = 1;
+        sd.hi_stride = in.n[0];
+      } else if (ax == 1) {
+        sd.nx = (int32_t)in.n[0];
+        sd.hi_stride = in.n[0] * in.n[1];
+      } else {
+        sd.nx = (int32_t)(in.n[0] * in.n[1]);
+        sd.hi_stride = 0;
+      }
+      const int desc_index = (int)sdesc.size();
+      sdesc.push_back(sd);
+      // work items: (k, transverse node, block of C chains)
+      const int64_t ntc = nc / in.n[ax];
+      int C = 64, S = 1;
+      choose_tile(prec, np, sd.n_a, ntc, sd.x_kind, C, S);
+      if (sd.x_kind && (int64_t)(kBlock / C) * S < sd.n_a) return PDG_EUNSUPPORTED;
+      std::vector<int> key = {np, S, C, sd.x_kind};
+      auto itg = group_of.find(key);
+      int gi;
+      if (itg == group_of.end()) {
+        gi = (int)groups.size();
+        group_of[key] = gi;
+        groups.push_back(Group{np, S, C, sd.x_kind, 0, 0});
+        by_group.emplace_back();
+      } else {
+        gi = itg->second;
+      }
+      int64_t tnodes = 1;
+      for (int k = 0; k < dim - 1; ++k) tnodes *= np;
+      int other[2] = {0, 0}, no = 0;
+      for (int k = 0; k < dim; ++k)
+        if (k != ax) other[no++] = k;
+      for (int k = 0; k < in.d.m; ++k)
+        for (int64_t t = 0; t < tnodes; ++t) {
+          // transverse node t -> plane offset
+          int64_t plane = 0;
+          int64_t rem = t;
+          for (int o = 0; o < no; ++o) {
+            int64_t jo = rem % np;
+            rem /= np;
+            int64_t ps = 1;
+            for (int kk = 0; kk < other[o]; ++kk) ps *= np;
+            plane += jo * ps;
+          }
+          const int64_t base = in.f_off + ((int64_t)(v * in.d.m + k) * in.nd + plane) * nc;
+          const int64_t fbb = in.fb_off + in.fb_vel_off[v] + ((int64_t)k * tnodes + t) * ntc;
+          for (int64_t tau0 = 0; tau0 < ntc; tau0 += C) {
+            SweepItem item;
+            item.base = base;
+            item.fb = fbb + tau0;
+            item.desc = desc_index;
+            item.tau0 = (int32_t)tau0;
+            item.count = (int32_t)std::min<int64_t>(C, ntc - tau0);
+            item.pad = sd.n_a;  // work estimate (cells per chain) for ordering
+            by_group[gi].push_back(item);
+          }
+        }
+    }
+  }
+  // longest chains first inside each group
+  std::vector<SweepItem> items;
+  for (size_t g = 0; g < groups.size(); ++g) {
+    std::stable_sort(by_group[g].begin(), by_group[g].end(),
+                     [](const SweepItem &a, const SweepItem &b) { return a.pad > b.pad; });
+    groups[g].first = (int64_t)items.size();
+    groups[g].count = (int64_t)by_group[g].size();
+    items.insert(items.end(), by_group[g].begin(), by_group[g].end());
+  }
+
+  // ---- relax tables --------------------------------------------------------
+  std::vector<RelaxDesc> rdesc;
+  std::map<std::pair<int, int>, std::vector<RelaxItem>> ritems_by;
+  std::vector<InflowDesc> idesc_all;
+  std::map<std::pair<int, int>, std::vector<InflowDesc>> iby;
+  bool relax_ok = true;
+  for (size_t ii = 0; ii < c->inst.size(); ++ii) {
+    const Instance &in = c->inst[ii];
+    RelaxDesc rd;
+    std::memset(&rd, 0, sizeof(rd));
+    rd.f_base = in.f_off;
+    rd.w_base = in.w_off;
+    rd.nodes = in.nd * in.nc;
+    for (int k = 0; k < 4; ++k) rd.param[k] = in.d.feq_param[k];
+    rd.nv = in.d.nv;
+    rd.m = in.d.m;
+    rd.dim = in.d.dim;
+    rd.feq = in.d.feq;
+    // the equilibrium needs the full {+-lambda e_k} set
+    double lam = std::fabs(in.v[(size_t)0 * in.d.dim + in.axis[0]]);
+    int seen[3][2] = {{0, 0}, {0, 0}, {0, 0}};
+    bool ok = in.d.nv == 2 * in.d.dim;
+    for (int v = 0; v < in.d.nv && ok; ++v) {
+      const double sp = std::fabs(in.v[(size_t)v * in.d.dim + in.axis[v]]);
+      if (sp != lam) ok = false;
+      rd.axis[v] = (int8_t)in.axis[v];
+      rd.sign[v] = (int8_t)in.sign[v];
+      seen[in.axis[v]][in.sign[v] > 0]++;
+    }
+    for (int k = 0; k < in.d.dim && ok; ++k)
+      if (seen[k][0] != 1 || seen[k][1] != 1) ok = false;
+    if (in.d.feq == PDG_FEQ_EULER && in.d.m != in.d.dim + 2) ok = false;
+    if (in.d.feq != PDG_FEQ_EULER && in.d.feq != PDG_FEQ_ADVECTION) ok = false;
+    rd.lambda = lam;
+    if (!ok) relax_ok = false;
+    const int di = (int)rdesc.size();
+    rdesc.push_back(rd);
+    const int64_t chunk = 4 * kBlock;
+    for (int64_t n0 = 0; n0 < rd.nodes; n0 += chunk) {
+      RelaxItem it;
+      it.node0 = n0;
+      it.desc = di;
+      it.count = (int32_t)std::min<int64_t>(chunk, rd.nodes - n0);
+      ritems_by[{rd.nv, rd.m}].push_back(it);
+    }
+    for (int v = 0; v < in.d.nv; ++v) {
+      InflowDesc idd;
+      int64_t tnodes = 1;
+      for (int k = 0; k < in.d.dim - 1; ++k) tnodes *= in.np;
+      idd.per_comp = tnodes * (in.nc / in.n[in.axis[v]]);
+      idd.fb_base = in.fb_off + in.fb_vel_off[v];
+      idd.relax_desc = di;
+      idd.vel = v;
+      iby[{rd.nv, rd.m}].push_back(idd);
+    }
+  }
+  std::vector<RelaxItem> ritems;
+  std::vector<RelaxGroup> rgroups, igroups;
+  if (relax_ok) {
+    for (auto &kv : ritems_by) {
+      rgroups.push_back(RelaxGroup{kv.first.first, kv.first.second, (int64_t)ritems.size(),
+                                   (int64_t)kv.second.size()});
+      ritems.insert(ritems.end(), kv.second.begin(), kv.second.end());
+    }
+    for (auto &kv : iby) {
+      igroups.push_back(RelaxGroup{kv.first.first, kv.first.second, (int64_t)idesc_all.size(),
+                                   (int64_t)kv.second.size()});
+      idesc_all.insert(idesc_all.end(), kv.second.begin(), kv.second.end());
+    }
+  }
+
+  // ---- upload + device inversion ----------------------------------------
+  hipError_t e;
+  if ((e = c->ops.upload(ops)) != hipSuccess || (e = c->sdesc.upload(sdesc)) != hipSuccess ||
+      (e = c->sitems.upload(items)) != hipSuccess || (e = c->rdesc.upload(rdesc)) != hipSuccess ||
+      (e = c->ritems.upload(ritems)) != hipSuccess || (e = c->idesc.upload(idesc_all)) != hipSuccess) {
+    c->release_device();
+    return from_hip(e);
+  }
+  std::vector<double> zeros(std::max<size_t>(2, 2 * items.size()), 0.0);
+  if ((e = c->stats.upload(zeros)) != hipSuccess) {
+    c->release_device();
+    return from_hip(e);
+  }
+  if ((e = launch_invert(c->ops.p, (int)ops.size(), st)) != hipSuccess ||
+      (e = hipStreamSynchronize(st)) != hipSuccess) {
+    c->release_device();
+    return from_hip(e);
+  }
+  c->ops_h.resize(ops.size());
+  if ((e = hipMemcpy(c->ops_h.data(), c->ops.p, ops.size() * sizeof(OpEntry), hipMemcpyDeviceToHost)) !=
+      hipSuccess) {
+    c->release_device();
+    return from_hip(e);
+  }
+  for (const OpEntry &o : c->ops_h)
+    if (o.singular) {
+      c->release_device();
+      return PDG_ESINGULAR;
+    }
+  if ((e = hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking)) != hipSuccess) {
+    c->release_device();
+    return from_hip(e);
+  }
+  c->groups = groups;
+  c->rgroups = rgroups;
+  c->igroups = igroups;
+  c->dt = dt;
+  c->theta = theta;
+  c->omega = omega;
+  c->scheme = scheme;
+  c->prec = prec;
+  c->prepared = true;
+  return PDG_OK;
+}
+
+}  // extern "C"
+
+namespace {
+
+pdg_status do_sweep(pdg_ctx *c, void *f, const double *fb_old, const double *fb_new, int dt_idx,
+                    hipStream_t st) {
+  for (const Group &g : c->groups) {
+    hipError_t e = launch_sweep(c->prec, g.np, g.S, g.C, g.x_kind, c->sitems.p + g.first, (int)g.count,
+                                c->sdesc.p, c->ops.p, dt_idx, f, fb_old, fb_new, c->stats.p + 2 * g.first, st);
+    if (e != hipSuccess) return from_hip(e);
+  }
+  c->stats_valid = c->prec == PDG_FP32_REFINE;
+  c->last_stream = st;
+  return PDG_OK;
+}
+
+pdg_status do_relax(pdg_ctx *c, void *f, double *w_out, hipStream_t st) {
+  if (c->rgroups.empty()) return PDG_EUNSUPPORTED;
+  for (const RelaxGroup &g : c->rgroups) {
+    hipError_t e = launch_relax(c->prec, g.nv, g.m, c->ritems.p + g.first, (int)g.count, c->rdesc.p, f, w_out,
+                                nullptr, c->omega, 0, st);
+    if (e != hipSuccess) return from_hip(e);
+  }
+  return PDG_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+pdg_status pdg_transport_sweep(pdg_ctx *c, void *f, const double *fb_old, const double *fb_new, double dt_sub,
+                               void *stream) {
+  if (!c || !f || (c->fb_elems > 0 && (!fb_old || !fb_new))) return PDG_EINVAL;
+  if (!c->prepared) return PDG_ESTATE;
+  int dt_idx;
+  if (dt_sub == c->dt)
+    dt_idx = 0;
+  else if (dt_sub == 0.5 * c->dt)
+    dt_idx = 1;
+  else
+    return PDG_ESTATE;
+  return do_sweep(c, f, fb_old, fb_new, dt_idx, static_cast<hipStream_t>(stream));
+}
+
+pdg_status pdg_relax(pdg_ctx *c, void *f, double *w_out, void *stream) {
+  if (!c || !f) return PDG_EINVAL;
+  if (!c->prepared) return PDG_ESTATE;
+  return do_relax(c, f, w_out, static_cast<hipStream_t>(stream));
+}
+
+pdg_status pdg_equilibrium(pdg_ctx *c, const double *w, void *f, void *stream) {
+  if (!c || !w || !f) return PDG_EINVAL;
+  if (!c->prepared) return PDG_ESTATE;
+  if (c->rgroups.empty()) return PDG_EUNSUPPORTED;
+  for (const RelaxGroup &g : c->rgroups) {
+    hipError_t e = launch_relax(c->prec, g.nv, g.m, c->ritems.p + g.first, (int)g.count, c->rdesc.p, f, nullptr, w,
+                                1.0, 1, static_cast<hipStream_t>(stream));
+    if (e != hipSuccess) return from_hip(e);
+  }
+  return PDG_OK;
+}
+
+pdg_status pdg_inflow_equilibrium(pdg_ctx *c, const double *w_inflow, double *fb, void *stream) {
+  if (!c || !w_inflow || !fb) return PDG_EINVAL;
+  if (!c->prepared) return PDG_ESTATE;
+  if (c->igroups.empty()) return PDG_EUNSUPPORTED;
+  for (const RelaxGroup &g : c->igroups) {
+    hipError_t e = launch_inflow_eq(g.nv, g.m, c->idesc.p + g.first, (int)g.count, c->rdesc.p, w_inflow, fb,
+                                    static_cast<hipStream_t>(stream));
+    if (e != hipSuccess) return from_hip(e);
+  }
+  return PDG_OK;
+}
+
+pdg_status pdg_step(pdg_ctx *c, void *f, const double *fb, int32_t n_steps, void *stream) {
+  if (!c || !f || n_steps < 0 || (c->fb_elems > 0 && !fb)) return PDG_EINVAL;
+  if (!c->prepared) return PDG_ESTATE;
+  if (c->rgroups.empty()) return PDG_EUNSUPPORTED;
+  if (n_steps == 0) return PDG_OK;
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  pdg_status s;
+  const bool use_graph = std::getenv("PDG_NO_GRAPH") == nullptr;
+  if (c->scheme == PDG_LIE || c->scheme == PDG_STRANG) {
+    const int idx = c->scheme == PDG_LIE ? 0 : 1;
+    for (int32_t i = 0; i < n_steps; ++i) {
+      if ((s = do_sweep(c, f, fb, fb, idx, st)) != PDG_OK) return s;
+      if ((s = do_relax(c, f, nullptr, st)) != PDG_OK) return s;
+      if (c->scheme == PDG_STRANG && (s = do_sweep(c, f, fb, fb, idx, st)) != PDG_OK) return s;
+    }
+    return PDG_OK;
+  }
+  // collapsed Strang: T(dt/2) C [T(dt) C]^(N-1) T(dt/2)
+  if ((s = do_sweep(c, f, fb, fb, 1, st)) != PDG_OK) return s;
+  if ((s = do_relax(c, f, nullptr, st)) != PDG_OK) return s;
+  if (n_steps > 1) {
+    if (use_graph && (c->gexec == nullptr || c->g_f != f || c->g_fb != fb)) {
+      if (c->gexec) (void)hipGraphExecDestroy(c->gexec);
+      c->gexec = nullptr;
+      hipGraph_t graph = nullptr;
+      hipError_t e = hipStreamBeginCapture(c->cap_stream, hipStreamCaptureModeThreadLocal);
+      if (e != hipSuccess) return from_hip(e);
+      pdg_status s1 = do_sweep(c, f, fb, fb, 0, c->cap_stream);
+      pdg_status s2 = s1 == PDG_OK ? do_relax(c, f, nullptr, c->cap_stream) : s1;
+      e = hipStreamEndCapture(c->cap_stream, &graph);
+      if (s2 != PDG_OK) {
+        if (graph) (void)hipGraphDestroy(graph);
+        return s2;
+      }
+      if (e != hipSuccess) return from_hip(e);
+      e = hipGraphInstantiate(&c->gexec, graph, nullptr, nullptr, 0);
+      (void)hipGraphDestroy(graph);
+      if (e != hipSuccess) {
+        c->gexec = nullptr;
+        return from_hip(e);
+      }
+      c->g_f = f;
+      c->g_fb = fb;
+    }
+    for (int32_t i = 1; i < n_steps; ++i) {
+      if (use_graph) {
+        hipError_t e = hipGraphLaunch(c->gexec, st);
+        if (e != hipSuccess) return from_hip(e);
+      } else {
+        if ((s = do_sweep(c, f, fb, fb, 0, st)) != PDG_OK) return s;
+        if ((s = do_relax(c, f, nullptr, st)) != PDG_OK) return s;
+      }
+    }
+    c->stats_valid = c->prec == PDG_FP32_REFINE;
+    c->last_stream = st;
+  }
+  return do_sweep(c, f, fb, fb, 1, st);
+}
+
+pdg_status pdg_last_refine_correction(const pdg_ctx *c, double *max_rel_correction) {
+  if (!c || !max_rel_correction) return PDG_EINVAL;
+  if (!c->prepared || !c->stats_valid) return PDG_ESTATE;
+  hipError_t e = hipStreamSynchronize(c->last_stream);
+  if (e != hipSuccess) return from_hip(e);
+  std::vector<double> h(c->stats.n);
+  e = hipMemcpy(h.data(), c->stats.p, h.size() * sizeof(double), hipMemcpyDeviceToHost);
+  if (e != hipSuccess) return from_hip(e);
+  double cm = 0.0, ym = 0.0;
+  for (size_t i = 0; i + 1 < h.size(); i += 2) {
+    cm = std::max(cm, h[i]);
+    ym = std::max(ym, h[i + 1]);
+  }
+  *max_rel_correction = ym > 0 ? cm / ym : 0.0;
+  return PDG_OK;
+}
+
+void pdg_destroy(pdg_ctx *c) {
+  if (!c) return;
+  c->release_device();
+  delete c;
+}
+
+}  // extern "C"

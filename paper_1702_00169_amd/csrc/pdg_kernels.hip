@@ -1,0 +1,671 @@
+// gfx950 kernels of the PDG transport sweep and relaxation.
+//
+// Transport (Sec. 4.1-4.2 of the paper, eq. transport_cn).  For an
+// axis-aligned velocity v = +-|v| e_a on a uniform Cartesian mesh, the cell
+// block Gamma_{L<-L} of eq. DG_reduit is the one-dimensional upwind operator
+// along axis a, repeated for every transverse node, and Gamma_{L<-R} couples
+// only the inflow node of a line to the outflow node of the upwind cell on the
+// same line.  The implicit step therefore splits into independent chains: a
+// line of n_a cells along axis a, each holding NP = d+1 nodes.  In downwind
+// order (local node 0 = inflow, NP-1 = outflow) cell l of a chain solves
+//
+//   A x_l = B f_l + c0 u_l e_0,   u_l = theta x_{l-1,out} + (1-theta) f_{l-1,out}
+//
+// (u_0 from the inflow data fb), i.e. x_l = M f_l + g u_l with M = A^{-1} B,
+// g = c0 A^{-1} e_0.  The scalar u obeys the affine recurrence
+//
+//   u_{l+1} = a u_l + (theta (M f_l)_out + (1-theta) f_{l,out}),  a = theta g_out,
+//
+// so a chain can be cut into segments that are solved in parallel: every
+// thread owns S consecutive cells of one chain, computes M f for them and the
+// affine map (alpha, beta) taking its inflow u to its outflow u, the maps of
+// the segments before it are composed in order (a sequential combine over at
+// most kBlock/C segments), and the thread finishes its cells with the exact
+// inflow.  The result is the block-triangular solve of the paper, with the
+// rounding order of the combine instead of cell after cell.
+//
+// Two staging paths share that arithmetic:
+//  * chains along a strided axis (y, z): a group of C consecutive chains
+//    reads consecutive addresses, so each thread loads its cells directly
+//    from HBM (C lanes per 8-byte row, fully coalesced);
+//  * chains along the contiguous axis x: the workgroup copies its C rows of
+//    all NP node planes into LDS with coalesced loads, threads read their
+//    segments from LDS in a thread-major layout (no bank conflicts on the
+//    read side), and results go back through LDS to coalesced stores.
+//
+// Relaxation (eq. collision_cn, Sec. 4.4): one thread per node reads the nv x m
+// values of that node (node-major layout: coalesced across threads), forms
+// w with a compensated (Neumaier) sum in a fixed velocity order, evaluates
+// f^eq(w) and applies f += omega (f^eq - f).
+#include <float.h>
+#include <math.h>
+
+#include "pdg_internal.h"
+
+namespace pdg {
+namespace {
+
+template <int PREC>
+struct Pol;
+template <>
+struct Pol<kF64> {
+  using St = double;  // state
+  using Rt = double;  // recurrence / arithmetic
+};
+template <>
+struct Pol<kF32> {
+  using St = float;
+  using Rt = float;
+};
+template <>
+struct Pol<kRefine> {
+  using St = double;
+  using Rt = double;
+};
+
+// Cell solve y = A^{-1} B f in the precision of the policy.
+template <int PREC, int NP>
+struct CellOp {
+  using Rt = typename Pol<PREC>::Rt;
+  Rt m[NP][NP];
+  Rt g[NP];
+  Rt a, theta;
+  __device__ void load(const OpEntry &op) {
+#pragma unroll
+    for (int i = 0; i < NP; ++i) {
+#pragma unroll
+      for (int j = 0; j < NP; ++j) m[i][j] = (PREC == kF32) ? (Rt)op.M32[i * NP + j] : (Rt)op.M[i * NP + j];
+      g[i] = (PREC == kF32) ? (Rt)op.g32[i] : (Rt)op.g[i];
+    }
+    a = (PREC == kF32) ? (Rt)op.a32 : (Rt)op.a;
+    theta = (Rt)op.theta;
+  }
+  __device__ void solve(const Rt (&f)[NP], Rt (&y)[NP], double &, double &) const {
+#pragma unroll
+    for (int i = 0; i < NP; ++i) {
+      Rt acc = m[i][0] * f[0];
+#pragma unroll
+      for (int j = 1; j < NP; ++j) acc = fma(m[i][j], f[j], acc);
+      y[i] = acc;
+    }
+  }
+};
+
+// binary32 cell solve with one binary64 residual correction:
+//   r = B f (fp64);  y1 = A32^{-1} r (fp32);  rho = r - A y1 (fp64);
+//   y = y1 + A32^{-1} rho (fp32 correction added in fp64).
+template <int NP>
+struct CellOp<kRefine, NP> {
+  using Rt = double;
+  double bm[NP][NP];
+  double am[NP][NP];
+  float ai[NP][NP];
+  double g[NP];
+  double a, theta;
+  __device__ void load(const OpEntry &op) {
+#pragma unroll
+    for (int i = 0; i < NP; ++i) {
+#pragma unroll
+      for (int j = 0; j < NP; ++j) {
+        bm[i][j] = op.B[i * NP + j];
+        am[i][j] = op.A[i * NP + j];
+        ai[i][j] = op.Ainv32[i * NP + j];
+      }
+      g[i] = op.g[i];
+    }
+    a = op.a;
+    theta = op.theta;
+  }
+  __device__ void solve(const double (&f)[NP], double (&y)[NP], double &cmax, double &ymax) const {
+    double r[NP];
+    float r32[NP];
+#pragma unroll
+    for (int i = 0; i < NP; ++i) {
+      double acc = bm[i][0] * f[0];
+#pragma unroll
+      for (int j = 1; j < NP; ++j) acc = fma(bm[i][j], f[j], acc);
+      r[i] = acc;
+      r32[i] = (float)acc;
+    }
+    float y1[NP];
+#pragma unroll
+    for (int i = 0; i < NP; ++i) {
+      float acc = ai[i][0] * r32[0];
+#pragma unroll
+      for (int j = 1; j < NP; ++j) acc = fmaf(ai[i][j], r32[j], acc);
+      y1[i] = acc;
+    }
+    float rho32[NP];
+#pragma unroll
+    for (int i = 0; i < NP; ++i) {
+      double acc = r[i];
+#pragma unroll
+      for (int j = 0; j < NP; ++j) acc = fma(-am[i][j], (double)y1[j], acc);
+      rho32[i] = (float)acc;
+    }
+#pragma unroll
+    for (int i = 0; i < NP; ++i) {
+      float acc = ai[i][0] * rho32[0];
+#pragma unroll
+      for (int j = 1; j < NP; ++j) acc = fmaf(ai[i][j], rho32[j], acc);
+      y[i] = (double)y1[i] + (double)acc;
+      cmax = fmax(cmax, fabs((double)acc));
+      ymax = fmax(ymax, fabs(y[i]));
+    }
+  }
+};
+
+template <int PREC, int NP, int S, bool XK>
+__global__ __launch_bounds__(kBlock) void sweep_kernel(const SweepItem *__restrict__ items,
+                                                      const SweepDesc *__restrict__ descs,
+                                                      const OpEntry *__restrict__ ops, int dt_idx, int C,
+                                                      typename Pol<PREC>::St *__restrict__ f,
+                                                      const double *__restrict__ fb_old,
+                                                      const double *__restrict__ fb_new,
+                                                      double *__restrict__ stats) {
+  using St = typename Pol<PREC>::St;
+  using Rt = typename Pol<PREC>::Rt;
+  __shared__ Rt xa[2][kBlock];
+  __shared__ Rt xb[2][kBlock];
+  extern __shared__ __align__(16) unsigned char lds_raw[];
+  St *tile = reinterpret_cast<St *>(lds_raw);
+  constexpr int kRow = kBlock + 1;  // padded LDS row (elements)
+
+  const SweepItem it = items[blockIdx.x];
+  const SweepDesc d = descs[it.desc];
+  CellOp<PREC, NP> op;
+  op.load(ops[d.op + dt_idx]);
+  const Rt theta = op.theta;
+  const Rt omt = (Rt)1 - theta;
+  const Rt gout = op.g[NP - 1];
+
+  const int t = threadIdx.x;
+  const int P = kBlock / C;
+  const int c = t % C;
+  const int p = t / C;
+  const bool active = c < it.count;
+  const int n = d.n_a;
+  const int window = P * S;
+  double cmax = 0.0, ymax = 0.0;
+
+  Rt u = 0;
+  if (active) u = theta * (Rt)fb_new[it.fb + c] + omt * (Rt)fb_old[it.fb + c];
+
+  const int tau = it.tau0 + c;
+  const int64_t chain = it.base + (int64_t)(tau % d.nx) + (int64_t)(tau / d.nx) * d.hi_stride + d.cell0 + d.plane0;
+
+  if (XK) {
+    // cooperative coalesced copy of count rows x n cells x NP planes into LDS
+    const int total = it.count * n;
+#pragma unroll
+    for (int q = 0; q < NP; ++q) {
+      const St *src = f + it.base + d.plane0 + q * d.plane_step + (int64_t)it.tau0 * d.hi_stride;
+      for (int e = t; e < total; e += kBlock) {
+        const int r = e / n;
+        const int x = e - r * n;
+        const int l = d.cell_step > 0 ? x : n - 1 - x;
+        const int ps = l / S;
+        const int s = l - ps * S;
+        tile[(q * S + s) * kRow + r + C * ps] = src[e];
+      }
+    }
+    __syncthreads();
+  }
+
+  int wpar = 0;
+  for (int w0 = 0; w0 < n; w0 += window, wpar ^= 1) {
+    const int lb = w0 + p * S;
+    const int cnt = active ? max(0, min(S, n - lb)) : 0;
+    Rt y[S][NP];
+    Rt fo[S];
+#pragma unroll
+    for (int s = 0; s < S; ++s) {
+      Rt fv[NP];
+      if (s < cnt) {
+#pragma unroll
+        for (int q = 0; q < NP; ++q) {
+          if (XK)
+            fv[q] = (Rt)tile[(q * S + s) * kRow + t];
+          else
+            fv[q] = (Rt)f[chain + (int64_t)(lb + s) * d.cell_step + q * d.plane_step];
+        }
+      } else {
+#pragma unroll
+        for (int q = 0; q < NP; ++q) fv[q] = 0;
+      }
+      fo[s] = fv[NP - 1];
+      op.solve(fv, y[s], cmax, ymax);
+    }
+    // affine map of this segment: u_out = alpha u_in + beta
+    Rt alpha = 1, beta = 0;
+#pragma unroll
+    for (int s = 0; s < S; ++s) {
+      if (s < cnt) {
+        beta = fma(op.a, beta, theta * y[s][NP - 1] + omt * fo[s]);
+        alpha *= op.a;
+      }
+    }
+    xa[wpar][t] = alpha;
+    xb[wpar][t] = beta;
+    __syncthreads();
+    Rt uin = u;
+    for (int q = 0; q < p; ++q) uin = fma(xa[wpar][c + C * q], uin, xb[wpar][c + C * q]);
+    Rt unext = uin;
+    for (int q = p; q < P; ++q) unext = fma(xa[wpar][c + C * q], unext, xb[wpar][c + C * q]);
+    // finish the segment with its exact inflow
+    Rt uu = uin;
+#pragma unroll
+    for (int s = 0; s < S; ++s) {
+      if (s < cnt) {
+        Rt xo = 0;
+#pragma unroll
+        for (int q = 0; q < NP; ++q) {
+          const Rt xv = fma(op.g[q], uu, y[s][q]);
+          if (q == NP - 1) xo = xv;
+          if (XK)
+            tile[(q * S + s) * kRow + t] = (St)xv;
+          else
+            f[chain + (int64_t)(lb + s) * d.cell_step + q * d.plane_step] = (St)xv;
+        }
+        uu = theta * xo + omt * fo[s];
+      }
+    }
+    (void)gout;
+    u = unext;
+  }
+
+  if (XK) {
+    __syncthreads();
+    const int total = it.count * n;
+#pragma unroll
+    for (int q = 0; q < NP; ++q) {
+      St *dst = f + it.base + d.plane0 + q * d.plane_step + (int64_t)it.tau0 * d.hi_stride;
+      for (int e = t; e < total; e += kBlock) {
+        const int r = e / n;
+        const int x = e - r * n;
+        const int l = d.cell_step > 0 ? x : n - 1 - x;
+        const int ps = l / S;
+        const int s = l - ps * S;
+        dst[e] = tile[(q * S + s) * kRow + r + C * ps];
+      }
+    }
+  }
+
+  if (PREC == kRefine) {
+    // block maxima of |correction| and |solution|, one pair per workgroup
+    __syncthreads();
+    double *red = reinterpret_cast<double *>(&xa[0][0]);
+    red[t] = cmax;
+    red[kBlock + t] = ymax;
+    __syncthreads();
+    for (int off = kBlock / 2; off > 0; off >>= 1) {
+      if (t < off) {
+        red[t] = fmax(red[t], red[t + off]);
+        red[kBlock + t] = fmax(red[kBlock + t], red[kBlock + t + off]);
+      }
+      __syncthreads();
+    }
+    if (t == 0) {
+      stats[2 * (int64_t)blockIdx.x] = red[0];
+      stats[2 * (int64_t)blockIdx.x + 1] = red[kBlock];
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// inversion of the cell blocks (binary64 Gauss-Jordan, partial pivoting)
+// ---------------------------------------------------------------------------
+__global__ void invert_kernel(OpEntry *ops, int n_ops) {
+  const int e = blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= n_ops) return;
+  OpEntry &op = ops[e];
+  const int np = op.np;
+  double a[kMaxNP][kMaxNP], inv[kMaxNP][kMaxNP];
+  double norm = 0.0;
+  for (int i = 0; i < kMaxNP; ++i)
+    for (int j = 0; j < kMaxNP; ++j) {
+      a[i][j] = (i < np && j < np) ? op.A[i * np + j] : 0.0;
+      inv[i][j] = (i == j) ? 1.0 : 0.0;
+      norm = fmax(norm, fabs(a[i][j]));
+    }
+  int singular = 0;
+  for (int col = 0; col < np; ++col) {
+    int piv = col;
+    for (int r = col + 1; r < np; ++r)
+      if (fabs(a[r][col]) > fabs(a[piv][col])) piv = r;
+    if (!(fabs(a[piv][col]) > 1e-300 * norm)) {
+      singular = 1;
+      break;
+    }
+    if (piv != col) {
+      for (int j = 0; j < np; ++j) {
+        double tmp = a[col][j];
+        a[col][j] = a[piv][j];
+        a[piv][j] = tmp;
+        tmp = inv[col][j];
+        inv[col][j] = inv[piv][j];
+        inv[piv][j] = tmp;
+      }
+    }
+    const double rp = 1.0 / a[col][col];
+    for (int j = 0; j < np; ++j) {
+      a[col][j] *= rp;
+      inv[col][j] *= rp;
+    }
+    for (int r = 0; r < np; ++r) {
+      if (r == col) continue;
+      const double fct = a[r][col];
+      if (fct == 0.0) continue;
+      for (int j = 0; j < np; ++j) {
+        a[r][j] = fma(-fct, a[col][j], a[r][j]);
+        inv[r][j] = fma(-fct, inv[col][j], inv[r][j]);
+      }
+    }
+  }
+  op.singular = singular;
+  if (singular) return;
+  for (int i = 0; i < np; ++i) {
+    for (int j = 0; j < np; ++j) {
+      double acc = 0.0;
+      for (int k = 0; k < np; ++k) acc = fma(inv[i][k], op.B[k * np + j], acc);
+      op.M[i * np + j] = acc;
+      op.M32[i * np + j] = (float)acc;
+      op.Ainv[i * np + j] = inv[i][j];
+      op.Ainv32[i * np + j] = (float)inv[i][j];
+    }
+    op.g[i] = op.c0 * inv[i][0];
+    op.g32[i] = (float)op.g[i];
+  }
+  op.a = op.theta * op.g[np - 1];
+  op.a32 = (float)op.theta * op.g32[np - 1];
+}
+
+// ---------------------------------------------------------------------------
+// equilibrium and relaxation
+// ---------------------------------------------------------------------------
+// f^eq_{i,k}(w) = w_k / nv + s_i q^{a_i}_k(w) / (2 lambda) for v_i = s_i lambda e_{a_i}.
+template <int M>
+__device__ inline void flux_dir(const RelaxDesc &d, const double (&w)[M], int axis, double (&q)[M]) {
+  if (d.feq == 0) {
+#pragma unroll
+    for (int k = 0; k < M; ++k) q[k] = d.param[axis] * w[k];
+  } else {
+    // compressible Euler, w = (rho, rho u_1..D, E), M = D + 2
+    const double gam = d.param[0];
+    const int dim = M - 2;
+    const double rho = w[0];
+    const double rinv = 1.0 / rho;
+    double ke = 0.0;
+#pragma unroll
+    for (int l = 0; l < M - 2; ++l) ke = fma(w[1 + l], w[1 + l] * rinv, ke);
+    const double pr = (gam - 1.0) * (w[M - 1] - 0.5 * ke);
+    const double ua = w[1 + axis] * rinv;
+    q[0] = w[1 + axis];
+#pragma unroll
+    for (int l = 0; l < M - 2; ++l) q[1 + l] = w[1 + axis] * (w[1 + l] * rinv) + (l == axis ? pr : 0.0);
+    q[M - 1] = (w[M - 1] + pr) * ua;
+    (void)dim;
+  }
+}
+
+template <int NV, int M>
+__device__ inline void equilibrium(const RelaxDesc &d, const double (&w)[M], double (&fe)[NV][M]) {
+  double qd[3][M];
+  const int dim = d.dim;
+#pragma unroll
+  for (int a = 0; a < 3; ++a)
+    if (a < dim) flux_dir<M>(d, w, a, qd[a]);
+  const double inv_nv = 1.0 / NV;
+  const double h2l = 0.5 / d.lambda;
+#pragma unroll
+  for (int i = 0; i < NV; ++i) {
+    const int ax = d.axis[i];
+    const double sg = d.sign[i] * h2l;
+#pragma unroll
+    for (int k = 0; k < M; ++k) {
+      double qv = 0.0;
+#pragma unroll
+      for (int a = 0; a < 3; ++a)
+        if (a == ax) qv = qd[a][k];
+      fe[i][k] = fma(sg, qv, w[k] * inv_nv);
+    }
+  }
+}
+
+// mode 0: relax (w from f);  mode 1: f = f^eq(w_in)
+template <int PREC, int NV, int M>
+__global__ __launch_bounds__(kBlock) void relax_kernel(const RelaxItem *__restrict__ items,
+                                                      const RelaxDesc *__restrict__ descs,
+                                                      typename Pol<PREC>::St *__restrict__ f,
+                                                      double *__restrict__ w_out,
+                                                      const double *__restrict__ w_in, double omega, int mode) {
+  using St = typename Pol<PREC>::St;
+  const RelaxItem it = items[blockIdx.x];
+  const RelaxDesc d = descs[it.desc];
+  const int64_t nodes = d.nodes;
+  St *fi = f + d.f_base;
+  for (int64_t node = it.node0 + threadIdx.x; node < it.node0 + it.count; node += kBlock) {
+    double w[M];
+    double fv[NV][M];
+    if (mode == 0) {
+#pragma unroll
+      for (int i = 0; i < NV; ++i)
+#pragma unroll
+        for (int k = 0; k < M; ++k) fv[i][k] = (double)fi[(int64_t)(i * M + k) * nodes + node];
+#pragma unroll
+      for (int k = 0; k < M; ++k) {
+        // Neumaier compensated sum over velocities, fixed order
+        double s = fv[0][k], comp = 0.0;
+#pragma unroll
+        for (int i = 1; i < NV; ++i) {
+          const double x = fv[i][k];
+          const double tt = s + x;
+          comp += (fabs(s) >= fabs(x)) ? ((s - tt) + x) : ((x - tt) + s);
+          s = tt;
+        }
+        w[k] = s + comp;
+      }
+    } else {
+#pragma unroll
+      for (int k = 0; k < M; ++k) w[k] = w_in[d.w_base + (int64_t)k * nodes + node];
+    }
+    double fe[NV][M];
+    equilibrium<NV, M>(d, w, fe);
+#pragma unroll
+    for (int i = 0; i < NV; ++i)
+#pragma unroll
+      for (int k = 0; k < M; ++k) {
+        const double nv = (mode == 0) ? fma(omega, fe[i][k] - fv[i][k], fv[i][k]) : fe[i][k];
+        fi[(int64_t)(i * M + k) * nodes + node] = (St)nv;
+      }
+    if (w_out != nullptr) {
+#pragma unroll
+      for (int k = 0; k < M; ++k) w_out[d.w_base + (int64_t)k * nodes + node] = w[k];
+    }
+  }
+}
+
+template <int NV, int M>
+__global__ __launch_bounds__(kBlock) void inflow_eq_kernel(const InflowDesc *__restrict__ items,
+                                                          const RelaxDesc *__restrict__ descs,
+                                                          const double *__restrict__ w_inflow,
+                                                          double *__restrict__ fb) {
+  const InflowDesc it = items[blockIdx.y];
+  const RelaxDesc d = descs[it.relax_desc];
+  for (int64_t e = (int64_t)blockIdx.x * kBlock + threadIdx.x; e < it.per_comp; e += (int64_t)gridDim.x * kBlock) {
+    double w[M];
+#pragma unroll
+    for (int k = 0; k < M; ++k) w[k] = w_inflow[it.fb_base + k * it.per_comp + e];
+    double fe[NV][M];
+    equilibrium<NV, M>(d, w, fe);
+#pragma unroll
+    for (int i = 0; i < NV; ++i)
+      if (i == it.vel) {
+#pragma unroll
+        for (int k = 0; k < M; ++k) fb[it.fb_base + k * it.per_comp + e] = fe[i][k];
+      }
+  }
+}
+
+__global__ void fill_kernel(double *p, int64_t n, double value) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    p[i] = value;
+}
+
+// ---------------------------------------------------------------------------
+// dispatch
+// ---------------------------------------------------------------------------
+template <int PREC, int NP, int S, bool XK>
+hipError_t go_sweep(int C, const SweepItem *items, int n_items, const SweepDesc *descs, const OpEntry *ops,
+                    int dt_idx, void *f, const double *fb_old, const double *fb_new, double *stats,
+                    hipStream_t st) {
+  using St = typename Pol<PREC>::St;
+  const size_t lds = XK ? (size_t)NP * S * (kBlock + 1) * sizeof(St) : 0;
+  hipLaunchKernelGGL((sweep_kernel<PREC, NP, S, XK>), dim3(n_items), dim3(kBlock), lds, st, items, descs, ops,
+                     dt_idx, C, static_cast<St *>(f), fb_old, fb_new, stats);
+  return hipGetLastError();
+}
+
+template <int PREC, int NP, int S>
+hipError_t go_sweep_x(int x_kind, int C, const SweepItem *items, int n_items, const SweepDesc *descs,
+                      const OpEntry *ops, int dt_idx, void *f, const double *fb_old, const double *fb_new,
+                      double *stats, hipStream_t st) {
+  if (x_kind)
+    return go_sweep<PREC, NP, S, true>(C, items, n_items, descs, ops, dt_idx, f, fb_old, fb_new, stats, st);
+  return go_sweep<PREC, NP, S, false>(C, items, n_items, descs, ops, dt_idx, f, fb_old, fb_new, stats, st);
+}
+
+template <int PREC, int NP>
+hipError_t go_sweep_s(int S, int x_kind, int C, const SweepItem *items, int n_items, const SweepDesc *descs,
+                      const OpEntry *ops, int dt_idx, void *f, const double *fb_old, const double *fb_new,
+                      double *stats, hipStream_t st) {
+  switch (S) {
+    case 1: return go_sweep_x<PREC, NP, 1>(x_kind, C, items, n_items, descs, ops, dt_idx, f, fb_old, fb_new, stats, st);
+    case 2: return go_sweep_x<PREC, NP, 2>(x_kind, C, items, n_items, descs, ops, dt_idx, f, fb_old, fb_new, stats, st);
+    case 4: return go_sweep_x<PREC, NP, 4>(x_kind, C, items, n_items, descs, ops, dt_idx, f, fb_old, fb_new, stats, st);
+    case 8: return go_sweep_x<PREC, NP, 8>(x_kind, C, items, n_items, descs, ops, dt_idx, f, fb_old, fb_new, stats, st);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+template <int PREC>
+hipError_t go_sweep_np(int np, int S, int x_kind, int C, const SweepItem *items, int n_items,
+                       const SweepDesc *descs, const OpEntry *ops, int dt_idx, void *f, const double *fb_old,
+                       const double *fb_new, double *stats, hipStream_t st) {
+  switch (np) {
+    case 2: return go_sweep_s<PREC, 2>(S, x_kind, C, items, n_items, descs, ops, dt_idx, f, fb_old, fb_new, stats, st);
+    case 3: return go_sweep_s<PREC, 3>(S, x_kind, C, items, n_items, descs, ops, dt_idx, f, fb_old, fb_new, stats, st);
+    case 4: return go_sweep_s<PREC, 4>(S, x_kind, C, items, n_items, descs, ops, dt_idx, f, fb_old, fb_new, stats, st);
+    case 5: return go_sweep_s<PREC, 5>(S, x_kind, C, items, n_items, descs, ops, dt_idx, f, fb_old, fb_new, stats, st);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+template <int PREC, int NV>
+hipError_t go_relax_m(int m, const RelaxItem *items, int n_items, const RelaxDesc *descs, void *f, double *w_out,
+                      const double *w_in, double omega, int mode, hipStream_t st) {
+  using St = typename Pol<PREC>::St;
+  St *fp = static_cast<St *>(f);
+  switch (m) {
+#define PDG_RELAX_CASE(MM)                                                                                   \
+  case MM:                                                                                                   \
+    hipLaunchKernelGGL((relax_kernel<PREC, NV, MM>), dim3(n_items), dim3(kBlock), 0, st, items, descs, fp, \
+                       w_out, w_in, omega, mode);                                                            \
+    return hipGetLastError();
+    PDG_RELAX_CASE(1)
+    PDG_RELAX_CASE(2)
+    PDG_RELAX_CASE(3)
+    PDG_RELAX_CASE(4)
+    PDG_RELAX_CASE(5)
+    PDG_RELAX_CASE(6)
+    PDG_RELAX_CASE(7)
+    PDG_RELAX_CASE(8)
+#undef PDG_RELAX_CASE
+    default: return hipErrorInvalidValue;
+  }
+}
+
+template <int NV>
+hipError_t go_inflow_m(int m, const InflowDesc *items, int n_items, const RelaxDesc *descs, const double *w_in,
+                       double *fb, hipStream_t st) {
+  const dim3 grid(64, n_items);
+  switch (m) {
+#define PDG_INFLOW_CASE(MM)                                                                                      \
+  case MM:                                                                                                       \
+    hipLaunchKernelGGL((inflow_eq_kernel<NV, MM>), grid, dim3(kBlock), 0, st, items, descs, w_in, fb);        \
+    return hipGetLastError();
+    PDG_INFLOW_CASE(1)
+    PDG_INFLOW_CASE(2)
+    PDG_INFLOW_CASE(3)
+    PDG_INFLOW_CASE(4)
+    PDG_INFLOW_CASE(5)
+    PDG_INFLOW_CASE(6)
+    PDG_INFLOW_CASE(7)
+    PDG_INFLOW_CASE(8)
+#undef PDG_INFLOW_CASE
+    default: return hipErrorInvalidValue;
+  }
+}
+
+}  // namespace
+
+hipError_t launch_invert(OpEntry *ops, int n_ops, hipStream_t st) {
+  if (n_ops <= 0) return hipSuccess;
+  hipLaunchKernelGGL(invert_kernel, dim3((n_ops + 63) / 64), dim3(64), 0, st, ops, n_ops);
+  return hipGetLastError();
+}
+
+hipError_t launch_sweep(int prec, int np, int S, int C, int x_kind, const SweepItem *items, int n_items,
+                        const SweepDesc *descs, const OpEntry *ops, int dt_idx, void *f, const double *fb_old,
+                        const double *fb_new, double *stats, hipStream_t st) {
+  if (n_items <= 0) return hipSuccess;
+  if (C <= 0 || kBlock % C != 0) return hipErrorInvalidValue;
+  switch (prec) {
+    case kF64: return go_sweep_np<kF64>(np, S, x_kind, C, items, n_items, descs, ops, dt_idx, f, fb_old, fb_new, stats, st);
+    case kF32: return go_sweep_np<kF32>(np, S, x_kind, C, items, n_items, descs, ops, dt_idx, f, fb_old, fb_new, stats, st);
+    case kRefine: return go_sweep_np<kRefine>(np, S, x_kind, C, items, n_items, descs, ops, dt_idx, f, fb_old, fb_new, stats, st);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+int sweep_lds_bytes(int prec, int np, int S, int x_kind) {
+  if (!x_kind) return 0;
+  const int es = prec == kF32 ? 4 : 8;
+  return np * S * (kBlock + 1) * es;
+}
+
+hipError_t launch_relax(int prec, int nv, int m, const RelaxItem *items, int n_items, const RelaxDesc *descs,
+                        void *f, double *w_out, const double *w_in, double omega, int mode, hipStream_t st) {
+  if (n_items <= 0) return hipSuccess;
+#define PDG_RELAX_NV(PR)                                                                            \
+  switch (nv) {                                                                                     \
+    case 4: return go_relax_m<PR, 4>(m, items, n_items, descs, f, w_out, w_in, omega, mode, st);    \
+    case 6: return go_relax_m<PR, 6>(m, items, n_items, descs, f, w_out, w_in, omega, mode, st);    \
+    default: return hipErrorInvalidValue;                                                           \
+  }
+  switch (prec) {
+    case kF64: PDG_RELAX_NV(kF64)
+    case kF32: PDG_RELAX_NV(kF32)
+    case kRefine: PDG_RELAX_NV(kRefine)
+    default: return hipErrorInvalidValue;
+  }
+#undef PDG_RELAX_NV
+}
+
+hipError_t launch_inflow_eq(int nv, int m, const InflowDesc *items, int n_items, const RelaxDesc *descs,
+                            const double *w_inflow, double *fb, hipStream_t st) {
+  if (n_items <= 0) return hipSuccess;
+  switch (nv) {
+    case 4: return go_inflow_m<4>(m, items, n_items, descs, w_inflow, fb, st);
+    case 6: return go_inflow_m<6>(m, items, n_items, descs, w_inflow, fb, st);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+hipError_t launch_fill(double *p, int64_t n, double value, hipStream_t st) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(fill_kernel, dim3(256), dim3(256), 0, st, p, n, value);
+  return hipGetLastError();
+}
+
+}  // namespace pdg

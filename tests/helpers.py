@@ -1,0 +1,113 @@
+"""Shared test plumbing: build matching GPU and oracle problems from a
+``workloads.Instance`` and move data between the two layouts.
+
+GPU layout (library):  f[v][k][j][c] per instance (node-major).
+Oracle layout:         f[v][k][c][j] per instance (cell-major).
+Both sides evaluate the seeded w_0(x) of ``workloads`` at their own
+Gauss-Lobatto points; nothing computed by one side is fed to the other.
+"""
+import numpy as np
+
+from oracle import step as ost
+
+
+def inst_dict(inst):
+    if inst.feq_kind == "advection":
+        par = list(inst.feq_param["a"])
+    else:
+        par = [inst.feq_param["gamma"]]
+    return dict(dim=inst.dim, n=list(inst.n), degree=inst.degree, v=np.asarray(inst.vel, float), m=inst.m,
+                lo=list(inst.lo), hi=list(inst.hi), feq=inst.feq_kind, feq_param=par)
+
+
+def oracle_problem(inst):
+    return ost.Problem(inst.n, inst.lo, inst.hi, inst.degree, inst.vel, inst.m, inst.feq_kind, inst.feq_param)
+
+
+def sizes(inst):
+    nc = int(np.prod(inst.n))
+    nd = (inst.degree + 1) ** inst.dim
+    return nc, nd
+
+
+def inflow_blocks(inst):
+    """[(v, axis, tnodes, ntc)] in fb order."""
+    out = []
+    nc, _ = sizes(inst)
+    for v in range(inst.vel.shape[0]):
+        ax = int(np.nonzero(inst.vel[v])[0][0])
+        out.append((v, ax, (inst.degree + 1) ** (inst.dim - 1), nc // inst.n[ax]))
+    return out
+
+
+def gpu_inflow_points(prob, i, inst):
+    """List per velocity of (npts, D) inflow coordinates in fb order."""
+    _, inflow = prob.node_coords(i)
+    pts = []
+    off = 0
+    for v, ax, tn, ntc in inflow_blocks(inst):
+        blk = inflow[off:off + inst.dim * tn * ntc].reshape(inst.dim, tn * ntc)
+        pts.append(blk.T.copy())
+        off += inst.dim * tn * ntc
+    return pts
+
+
+def gpu_fb_from_function(prob, insts, fn_of_inst_v):
+    """fb (numpy, fb layout) with value fn(i, v, pts) -> (m, npts)."""
+    fb = np.zeros(prob.layout["fb_elems"])
+    for i, inst in enumerate(insts):
+        off = prob.layout["fb_off"][i]
+        for (v, ax, tn, ntc), pts in zip(inflow_blocks(inst), gpu_inflow_points(prob, i, inst)):
+            vals = fn_of_inst_v(i, v, pts)
+            fb[off:off + vals.size] = vals.ravel()
+            off += vals.size
+    return fb
+
+
+def oracle_fb_from_function(oprob, i, fn_of_inst_v):
+    return [fn_of_inst_v(i, v, oprob.entries(v)["coords"]) for v in range(oprob.nv)]
+
+
+def gpu_to_oracle(f_flat, inst, f_off=0):
+    nc, nd = sizes(inst)
+    nv, m = inst.vel.shape[0], inst.m
+    blk = np.asarray(f_flat[f_off:f_off + nv * m * nd * nc]).reshape(nv, m, nd, nc)
+    return np.transpose(blk, (0, 1, 3, 2)).copy()
+
+
+def oracle_to_gpu(f_or):
+    return np.ascontiguousarray(np.transpose(f_or, (0, 1, 3, 2))).ravel()
+
+
+def rel_errors(got, want):
+    got = np.asarray(got, float)
+    want = np.asarray(want, float)
+    l2 = np.linalg.norm(got - want) / max(np.linalg.norm(want), 1e-300)
+    mx = np.max(np.abs(got - want)) / max(np.max(np.abs(want)), 1e-300)
+    return l2, mx
+
+
+def gpu_initial_state(prob, insts, torch, dtype):
+    """f = f^eq(w0), fb = f^eq(w0 on the inflow points), built by the library."""
+    w = np.zeros(prob.layout["w_elems"])
+    for i, inst in enumerate(insts):
+        vol, _ = prob.node_coords(i)
+        pts = vol.reshape(inst.dim, -1).T
+        vals = inst.w0(pts)                            # (m, nd*nc)
+        w[prob.layout["w_off"][i]:prob.layout["w_off"][i + 1]] = vals.ravel()
+    fbw = gpu_fb_from_function(prob, insts, lambda i, v, pts: insts[i].w0(pts))
+    dev = "cuda"
+    w_t = torch.tensor(w, device=dev)
+    fbw_t = torch.tensor(fbw, device=dev)
+    f = torch.empty(prob.layout["f_elems"], dtype=dtype, device=dev)
+    fb = torch.empty(prob.layout["fb_elems"], dtype=torch.float64, device=dev)
+    prob.equilibrium(w_t, f)
+    prob.inflow_equilibrium(fbw_t, fb)
+    torch.cuda.synchronize()
+    return f, fb
+
+
+def oracle_initial_state(oprob, inst):
+    x = oprob.mesh.node_coords().reshape(-1, oprob.mesh.dim)
+    w = inst.w0(x).reshape(oprob.m, oprob.mesh.nc, oprob.mesh.nd)
+    return oprob.feq(w), oprob.inflow_from_w(inst.w0)

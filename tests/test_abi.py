@@ -1,0 +1,188 @@
+"""CPU checks of the C ABI: the library loads, exports every declared
+symbol, validates its arguments, and its host logic (dependency-graph
+levels, layouts, coordinates, cell operator) agrees with the oracle.
+No device compute is called here."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+from conftest import ROOT, read_golden
+from oracle import mesh as omesh
+from oracle import transport as otr
+
+
+def _load_build_module():
+    import importlib.util
+    spec = importlib.util.spec_from_file_location(
+        "pdg_build", os.path.join(ROOT, "paper_1702_00169_amd", "build.py"))
+    mod = importlib.util.module_from_spec(spec)
+    spec.loader.exec_module(mod)
+    return mod
+
+
+@pytest.fixture(scope="module")
+def lib():
+    b = _load_build_module()
+    if not os.path.exists(b.LIB):
+        b.build()
+    import paper_1702_00169_amd as P
+    return P
+
+
+def _declared():
+    text = open(os.path.join(ROOT, "include", "pdg.h")).read()
+    return sorted(set(re.findall(r"\b(pdg_[a-z_]+)\s*\(", text)))
+
+
+def test_every_declared_symbol_is_exported(lib):
+    names = _declared()
+    assert "pdg_transport_sweep" in names and len(names) >= 14
+    so = ctypes.CDLL(lib.LIB_PATH)
+    for name in names:
+        assert hasattr(so, name), name
+    assert set(names) == set(lib.EXPORTED)
+
+
+def _desc(**kw):
+    d = dict(dim=2, n=[4, 3], degree=2, v=[[1.0, 0.0], [0.0, 1.0], [-1.0, 0.0], [0.0, -1.0]], m=1,
+             feq="advection", feq_param=[0.5, 0.25])
+    d.update(kw)
+    return d
+
+
+@pytest.mark.parametrize("kw,status", [
+    (dict(dim=1, n=[4]), 1), (dict(dim=4), 1), (dict(degree=0), 1), (dict(degree=5), 2),
+    (dict(n=[0, 3]), 1), (dict(hi=[1.0, -1.0]), 1), (dict(v=[[float("nan"), 0.0]]), 1),
+    (dict(m=0), 1), (dict(m=9), 1),
+])
+def test_setup_rejects_bad_descriptors(lib, kw, status):
+    with pytest.raises(lib.PdgError) as ei:
+        lib.pdg_setup_mesh([_desc(**kw)])
+    assert ei.value.status == status
+
+
+def test_null_arguments_are_rejected(lib):
+    so = lib._lib
+    out = ctypes.c_void_p()
+    assert so.pdg_setup_mesh(None, 1, ctypes.byref(out)) == lib.PDG_EINVAL
+    assert so.pdg_layout(None, None, None, None, None, None, None) == lib.PDG_EINVAL
+    assert so.pdg_transport_sweep(None, None, None, None, 0.1, None) == lib.PDG_EINVAL
+    assert so.pdg_relax(None, None, None, None) == lib.PDG_EINVAL
+    assert so.pdg_step(None, None, None, 1, None) == lib.PDG_EINVAL
+
+
+def test_calls_before_prepare_report_state_error(lib):
+    ctx = lib.pdg_setup_mesh([_desc()])
+    dummy = ctypes.c_void_p(16)
+    assert lib._lib.pdg_transport_sweep(ctx, dummy, dummy, dummy, 0.1, None) == lib.PDG_ESTATE
+    assert lib._lib.pdg_relax(ctx, dummy, None, None) == lib.PDG_ESTATE
+    assert lib._lib.pdg_step(ctx, dummy, dummy, 2, None) == lib.PDG_ESTATE
+    lib.pdg_destroy(ctx)
+
+
+def test_status_strings(lib):
+    for s in range(8):
+        assert lib.pdg_status_string(s).startswith("PDG_")
+
+
+def test_levels_of_the_paper_figure(lib):
+    ctx = lib.pdg_setup_mesh([_desc(n=[3, 3], degree=1, v=[[1.0, 1.0]])])
+    lev = np.zeros(9, np.int32)
+    lib.pdg_levels(ctx, 0, 0, lev)
+    for level, cells in read_golden("dependency_levels_3x3.txt"):
+        assert sorted(np.nonzero(lev == int(level))[0].tolist()) == sorted(int(c) for c in cells.split(","))
+    lib.pdg_destroy(ctx)
+
+
+def test_axis_aligned_levels_are_planes_and_match_oracle(lib):
+    vel = [[0.0, 0.0, -2.0], [1.0, 0.0, 0.0], [0.0, 0.5, 0.0], [0.3, -0.2, 0.1]]
+    ctx = lib.pdg_setup_mesh([_desc(dim=3, n=[3, 4, 5], degree=1, v=vel)])
+    m = omesh.Mesh((3, 4, 5), np.zeros(3), np.ones(3), 1)
+    for v in range(4):
+        lev = np.zeros(60, np.int32)
+        lib.pdg_levels(ctx, 0, v, lev)
+        np.testing.assert_array_equal(lev, otr.topological_levels(m, vel[v]))
+    lib.pdg_destroy(ctx)
+
+
+def test_topo_levels_detects_cycles(lib):
+    lev = np.zeros(4, np.int32)
+    src = np.array([0, 1, 3, 2], np.int32)
+    dst = np.array([1, 3, 2, 0], np.int32)
+    assert lib.pdg_topo_levels(4, src, dst, lev) == lib.PDG_ENOTDAG
+    src = np.array([0, 0, 1, 2], np.int32)
+    dst = np.array([1, 2, 3, 3], np.int32)
+    assert lib.pdg_topo_levels(4, src, dst, lev) == lib.PDG_OK
+    np.testing.assert_array_equal(lev, [0, 1, 1, 2])
+    bad = np.array([0, 7], np.int32)
+    assert lib.pdg_topo_levels(4, bad, bad, lev) == lib.PDG_EINVAL
+
+
+def test_layout_sizes(lib):
+    descs = [_desc(), _desc(dim=3, n=[2, 3, 4], degree=3, m=5,
+                            v=[[1, 0, 0], [0, 1, 0], [-1, 0, 0], [0, -1, 0], [0, 0, -1], [0, 0, 1]],
+                            feq="euler", feq_param=[1.4])]
+    prob = lib.Problem(descs)
+    lay = prob.layout
+    f0 = 4 * 1 * 9 * 12
+    f1 = 6 * 5 * 64 * 24
+    assert lay["f_elems"] == f0 + f1 and list(lay["f_off"]) == [0, f0, f0 + f1]
+    assert lay["w_elems"] == 9 * 12 + 5 * 64 * 24
+    fb0 = 3 * (3 + 4 + 3 + 4)                 # per velocity: (d+1) nodes x transverse cells
+    fb1 = 5 * 16 * (12 + 8 + 12 + 8 + 6 + 6)
+    assert lay["fb_elems"] == fb0 + fb1
+    prob.close()
+
+
+@pytest.mark.parametrize("dim,n,degree", [(2, (3, 5), 3), (3, (2, 3, 4), 2), (2, (4, 2), 4)])
+def test_coordinates_match_oracle(lib, dim, n, degree):
+    vel = np.vstack([np.eye(dim), -np.eye(dim)])
+    hi = [1.0, 2.0, 0.5][:dim]
+    prob = lib.Problem([_desc(dim=dim, n=list(n), degree=degree, v=vel, hi=hi, lo=[0.0] * dim)])
+    vol, inflow = prob.node_coords(0)
+    m = omesh.Mesh(n, np.zeros(dim), np.array(hi), degree)
+    want = m.node_coords()                                   # (nc, nd, D)
+    np.testing.assert_allclose(np.transpose(vol, (2, 1, 0)), want, atol=1e-14)
+    off = 0
+    for v in range(vel.shape[0]):
+        ent = otr.inflow_entries(m, vel[v])
+        npts = ent["coords"].shape[0]
+        pts = inflow[off:off + dim * npts].reshape(dim, npts).T
+        a = pts[np.lexsort(np.round(pts, 12).T[::-1])]
+        b = ent["coords"][np.lexsort(np.round(ent["coords"], 12).T[::-1])]
+        np.testing.assert_allclose(a, b, atol=1e-14)
+        off += dim * npts
+    prob.close()
+
+
+@pytest.mark.parametrize("degree", [1, 2, 3, 4])
+@pytest.mark.parametrize("vel", [(1.3, 0.0, 0.0), (0.0, -0.7, 0.0), (0.0, 0.0, 2.0), (-3.0, 0.0, 0.0)])
+def test_host_cell_operator_is_the_oracle_block(lib, degree, vel):
+    """Kronecker(I, line block) in downwind-local order == oracle Gamma_{L<-L}."""
+    hi = [1.0, 1.7, 0.6]
+    prob = lib.Problem([_desc(dim=3, n=[3, 2, 2], degree=degree, v=[list(vel)], hi=hi, lo=[0.0] * 3)])
+    npn = degree + 1
+    gam = np.zeros(npn * npn)
+    kappa = lib.pdg_line_operator(prob.ctx, 0, 0, gam)
+    gam = gam.reshape(npn, npn)
+    m = omesh.Mesh((3, 2, 2), np.zeros(3), np.array(hi), degree)
+    blk = otr.cell_blocks(m, np.array(vel), np.array([5]))
+    ax = int(np.nonzero(vel)[0][0])
+    s = 1 if vel[ax] > 0 else -1
+    idx = m.node_idx
+    want = blk.gll[0]
+    got = np.zeros_like(want)
+    for i in range(m.nd):
+        for j in range(m.nd):
+            if all(idx[i, k] == idx[j, k] for k in range(3) if k != ax):
+                qi = idx[i, ax] if s > 0 else degree - idx[i, ax]
+                qj = idx[j, ax] if s > 0 else degree - idx[j, ax]
+                got[i, j] = gam[qi, qj]
+    np.testing.assert_allclose(got, want, rtol=1e-13, atol=1e-13 * np.abs(want).max())
+    # inflow coupling: -kappa at the inflow node of the face opposite to v
+    fc = [f for f in blk.faces if f["axis"] == ax and f["side"] == -s][0]
+    np.testing.assert_allclose(fc["coef"][0], -kappa, rtol=1e-13)
+    prob.close()
