@@ -187,6 +187,11 @@ pdg_status pdg_step(pdg_ctx *c, void *f, const double *fb, int32_t n_steps, void
  * the most recent sweep (synchronises the stream of that sweep). */
 pdg_status pdg_last_refine_correction(const pdg_ctx *c, double *max_rel_correction);
 
+/* Detail of the most recent HIP failure seen by this thread (the failing
+ * call and the runtime's message); empty if none.  Static thread-local
+ * storage, valid until the next failing call. */
+const char *pdg_error_detail(void);
+
 /* Human-readable name of a status code (static storage). */
 const char *pdg_status_string(pdg_status s);
 

@@ -22,13 +22,14 @@ PDG_LIE, PDG_STRANG, PDG_STRANG_COLLAPSED = 0, 1, 2
 
 EXPORTED = ("pdg_setup_mesh", "pdg_layout", "pdg_node_coords", "pdg_levels", "pdg_topo_levels", "pdg_line_operator",
             "pdg_prepare", "pdg_equilibrium", "pdg_inflow_equilibrium", "pdg_transport_sweep",
-            "pdg_relax", "pdg_step", "pdg_last_refine_correction", "pdg_status_string", "pdg_destroy")
+            "pdg_relax", "pdg_step", "pdg_last_refine_correction", "pdg_status_string", "pdg_error_detail", "pdg_destroy")
 
 
 class PdgError(RuntimeError):
     def __init__(self, status, where):
         self.status = status
-        super().__init__(f"{where}: {pdg_status_string(status)}")
+        detail = pdg_error_detail() if status in (PDG_EDEVICE, PDG_ENOMEM) else ""
+        super().__init__(f"{where}: {pdg_status_string(status)}" + (f" [{detail}]" if detail else ""))
 
 
 class pdg_instance_desc(ctypes.Structure):
@@ -39,6 +40,11 @@ class pdg_instance_desc(ctypes.Structure):
 
 
 def _load():
+    # torch ships its own HIP runtime (soname libamdhip64.so.7).  Importing it
+    # first makes the dynamic linker bind libpdg.so to that same runtime, so
+    # the process holds one HIP/HSA runtime and torch tensors, streams and the
+    # library's launches share one device context.
+    import torch  # noqa: F401
     if not os.path.exists(LIB_PATH):
         raise ImportError(f"{LIB_PATH} is missing: build it with `python paper_1702_00169_amd/build.py` "
                           "(the library has no CPU fallback)")
@@ -59,6 +65,7 @@ def _load():
         "pdg_step": (i32, [p, p, p, i32, p]),
         "pdg_last_refine_correction": (i32, [p, ctypes.POINTER(d)]),
         "pdg_status_string": (ctypes.c_char_p, [i32]),
+        "pdg_error_detail": (ctypes.c_char_p, []),
         "pdg_destroy": (None, [p]),
     }
     for name, (res, args) in sig.items():
@@ -73,6 +80,10 @@ _lib = _load()
 
 def pdg_status_string(status):
     return _lib.pdg_status_string(int(status)).decode()
+
+
+def pdg_error_detail():
+    return _lib.pdg_error_detail().decode()
 
 
 def _check(status, where):

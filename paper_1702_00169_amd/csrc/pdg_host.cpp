@@ -212,11 +212,20 @@ void line_block(int d, double V, double h, std::vector<double> &gam, double &inf
 
 bool is_finite(double x) { return std::isfinite(x); }
 
-pdg_status from_hip(hipError_t e) {
+thread_local char g_detail[512] = "";
+
+pdg_status from_hip_at(hipError_t e, const char *where) {
   if (e == hipSuccess) return PDG_OK;
+  std::snprintf(g_detail, sizeof(g_detail), "%s: %s (%d)", where, hipGetErrorString(e), (int)e);
   if (e == hipErrorOutOfMemory) return PDG_ENOMEM;
   return PDG_EDEVICE;
 }
+#define from_hip(e) from_hip_at((e), __func__)
+#define HIP_TRY(call)                                        \
+  do {                                                       \
+    hipError_t e_ = (call);                                  \
+    if (e_ != hipSuccess) return from_hip_at(e_, #call);     \
+  } while (0)
 
 // ---------------------------------------------------------------------------
 // dependency graph of a velocity on a Cartesian mesh and its Kahn layering
@@ -309,6 +318,8 @@ void choose_tile(int prec, int np, int n, int64_t ntc, int x_kind, int &C, int &
 // C ABI
 // ===========================================================================
 extern "C" {
+
+const char *pdg_error_detail(void) { return g_detail; }
 
 const char *pdg_status_string(pdg_status s) {
   switch (s) {
@@ -754,37 +765,30 @@ pdg_status pdg_prepare(pdg_ctx *c, double dt, double theta, double omega, pdg_sc
 
   // ---- upload + device inversion ----------------------------------------
   hipError_t e;
-  if ((e = c->ops.upload(ops)) != hipSuccess || (e = c->sdesc.upload(sdesc)) != hipSuccess ||
-      (e = c->sitems.upload(items)) != hipSuccess || (e = c->rdesc.upload(rdesc)) != hipSuccess ||
-      (e = c->ritems.upload(ritems)) != hipSuccess || (e = c->idesc.upload(idesc_all)) != hipSuccess) {
-    c->release_device();
-    return from_hip(e);
+#define PREP_TRY(call)                      \
+  if ((e = (call)) != hipSuccess) {         \
+    c->release_device();                    \
+    return from_hip_at(e, #call);           \
   }
+  PREP_TRY(c->ops.upload(ops))
+  PREP_TRY(c->sdesc.upload(sdesc))
+  PREP_TRY(c->sitems.upload(items))
+  PREP_TRY(c->rdesc.upload(rdesc))
+  PREP_TRY(c->ritems.upload(ritems))
+  PREP_TRY(c->idesc.upload(idesc_all))
   std::vector<double> zeros(std::max<size_t>(2, 2 * items.size()), 0.0);
-  if ((e = c->stats.upload(zeros)) != hipSuccess) {
-    c->release_device();
-    return from_hip(e);
-  }
-  if ((e = launch_invert(c->ops.p, (int)ops.size(), st)) != hipSuccess ||
-      (e = hipStreamSynchronize(st)) != hipSuccess) {
-    c->release_device();
-    return from_hip(e);
-  }
+  PREP_TRY(c->stats.upload(zeros))
+  PREP_TRY(launch_invert(c->ops.p, (int)ops.size(), st))
+  PREP_TRY(hipStreamSynchronize(st))
   c->ops_h.resize(ops.size());
-  if ((e = hipMemcpy(c->ops_h.data(), c->ops.p, ops.size() * sizeof(OpEntry), hipMemcpyDeviceToHost)) !=
-      hipSuccess) {
-    c->release_device();
-    return from_hip(e);
-  }
+  PREP_TRY(hipMemcpy(c->ops_h.data(), c->ops.p, ops.size() * sizeof(OpEntry), hipMemcpyDeviceToHost))
   for (const OpEntry &o : c->ops_h)
     if (o.singular) {
       c->release_device();
       return PDG_ESINGULAR;
     }
-  if ((e = hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking)) != hipSuccess) {
-    c->release_device();
-    return from_hip(e);
-  }
+  PREP_TRY(hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking))
+#undef PREP_TRY
   c->groups = groups;
   c->rgroups = rgroups;
   c->igroups = igroups;
@@ -806,7 +810,11 @@ pdg_status do_sweep(pdg_ctx *c, void *f, const double *fb_old, const double *fb_
   for (const Group &g : c->groups) {
     hipError_t e = launch_sweep(c->prec, g.np, g.S, g.C, g.x_kind, c->sitems.p + g.first, (int)g.count,
                                 c->sdesc.p, c->ops.p, dt_idx, f, fb_old, fb_new, c->stats.p + 2 * g.first, st);
-    if (e != hipSuccess) return from_hip(e);
+    if (e != hipSuccess) {
+      char what[96];
+      std::snprintf(what, sizeof(what), "launch_sweep(np=%d,S=%d,C=%d,x=%d)", g.np, g.S, g.C, g.x_kind);
+      return from_hip_at(e, what);
+    }
   }
   c->stats_valid = c->prec == PDG_FP32_REFINE;
   c->last_stream = st;
