@@ -1,0 +1,272 @@
+"""Throughput of the PDG transport sweep + relaxation on one MI355X.
+
+One step = one full implicit transport sweep of every velocity and component
+(theta-scheme, Sec. 4.1-4.2) + one relaxation (eq. collision_cn), i.e. the
+interior step of the collapsed Strang composition (Sec. 5.1).  The timed
+region runs pdg_step(K): T(dt/2) C [T(dt) C]^(K-1) T(dt/2), i.e. K+1 sweep
+launches and K relax launches, counted as K steps.  Inputs are resident in
+HBM before the timed region.
+
+Prints one JSON line (rank 0 of a single process):
+  value      = N_DoF * K / wall time      [DoF-updates/s], N_DoF = nv m Nc (d+1)^D
+  roofline   = the sweep kernel (the dominant launch) against the 8 TB/s HBM
+               peak: algorithmic bytes per launch = read + write of the state,
+               2 s N_DoF (s = 8 B for binary64 and binary32+refine state,
+               4 B for binary32), over its HIP-event launch duration
+  precisions = the same measurement for binary64, binary32 + binary64
+               refinement and plain binary32, each with its error
+  cpu_baseline = the CPU oracle timed on a bounded sample of the workload
+"""
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+import workloads as W  # noqa: E402
+
+METRIC = "DoF-updates/s per transport+relax step, FP32+refine vs FP64 at stated error"
+HBM_PEAK_GBS = 8000.0
+PREC_NAMES = {0: "fp64", 2: "fp32refine", 1: "fp32"}
+DTYPE_NAMES = {0: "f64", 2: "f64", 1: "f32"}
+DEFAULT_WORKLOAD = "adv3d_64"
+
+
+def inst_dict(inst):
+    par = list(inst.feq_param["a"]) if inst.feq_kind == "advection" else [inst.feq_param["gamma"]]
+    return dict(dim=inst.dim, n=list(inst.n), degree=inst.degree, v=np.asarray(inst.vel, float), m=inst.m,
+                lo=list(inst.lo), hi=list(inst.hi), feq=inst.feq_kind, feq_param=par)
+
+
+def initial_state(pdg, prob, insts, torch, dtype):
+    """f = f^eq(w0) and fb = f^eq(w0 at the inflow points), built on the device."""
+    w = np.empty(prob.layout["w_elems"])
+    fbw = np.empty(prob.layout["fb_elems"])
+    for i, inst in enumerate(insts):
+        vol, inflow = prob.node_coords(i)
+        w[prob.layout["w_off"][i]:prob.layout["w_off"][i + 1]] = inst.w0(vol.reshape(inst.dim, -1).T).ravel()
+        off = prob.layout["fb_off"][i]
+        ioff = 0
+        nc = int(np.prod(inst.n))
+        for v in range(inst.vel.shape[0]):
+            ax = int(np.nonzero(inst.vel[v])[0][0])
+            npts = (inst.degree + 1) ** (inst.dim - 1) * (nc // inst.n[ax])
+            pts = inflow[ioff:ioff + inst.dim * npts].reshape(inst.dim, npts).T
+            vals = inst.w0(pts)
+            fbw[off:off + vals.size] = vals.ravel()
+            off += vals.size
+            ioff += inst.dim * npts
+    f = torch.empty(prob.layout["f_elems"], dtype=dtype, device="cuda")
+    fb = torch.empty(prob.layout["fb_elems"], dtype=torch.float64, device="cuda")
+    w_t = torch.from_numpy(w).cuda()
+    prob.equilibrium(w_t, f)
+    del w_t
+    fbw_t = torch.from_numpy(fbw).cuda()
+    prob.inflow_equilibrium(fbw_t, fb)
+    torch.cuda.synchronize()
+    return f, fb
+
+
+def kernel_source_hash():
+    h = hashlib.sha256()
+    for name in ("pdg_kernels.hip", "pdg_internal.h", "pdg_host.cpp"):
+        with open(os.path.join(ROOT, "paper_1702_00169_amd", "csrc", name), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def traffic_for(workload, prec_name):
+    """HBM bytes per sweep launch from committed rocprofv3 PMC runs, if they
+    were taken on the current kernel sources; else None."""
+    path = os.path.join(ROOT, "profiles", "sweep_traffic.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as fh:
+        rec = json.load(fh)
+    key = f"{workload}/{prec_name}"
+    ent = rec.get(key)
+    if not ent or ent.get("source_hash") != kernel_source_hash():
+        return None
+    return ent.get("bytes_per_launch")
+
+
+def measure(pdg, torch, wl, prec, steps, warmup, reps, keep_state=False):
+    insts = wl.instances
+    prob = pdg.Problem([inst_dict(i) for i in insts])
+    prob.prepare(wl.dt, theta=wl.theta, omega=wl.omega, scheme=pdg.PDG_STRANG_COLLAPSED, precision=prec)
+    dtype = torch.float32 if prec == pdg.PDG_FP32 else torch.float64
+    f, fb = initial_state(pdg, prob, insts, torch, dtype)
+    f_init = f.clone() if keep_state else None
+    n_dof = wl.n_dof
+    # warm-up (also records the step graph)
+    if warmup > 0:
+        prob.step(f, fb, warmup)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    prob.step(f, fb, steps)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    refine_corr = prob.last_refine_correction() if prec == pdg.PDG_FP32_REFINE else None
+    # per-launch durations on the stream the kernels run on
+    stream = torch.cuda.current_stream()
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(4)]
+    ev[0].record(stream)
+    for _ in range(reps):
+        prob.transport_sweep(f, fb, fb, wl.dt)
+    ev[1].record(stream)
+    for _ in range(reps):
+        prob.relax(f)
+    ev[2].record(stream)
+    torch.cuda.synchronize()
+    t_sweep = ev[0].elapsed_time(ev[1]) / reps * 1e-3
+    t_relax = ev[1].elapsed_time(ev[2]) / reps * 1e-3
+    state_bytes = 4 if prec == pdg.PDG_FP32 else 8
+    out = dict(
+        value=n_dof * steps / wall, ms_per_step=wall / steps * 1e3, wall_s=wall,
+        sweep_us=t_sweep * 1e6, relax_us=t_relax * 1e6,
+        sweep_gbs=2 * state_bytes * n_dof / t_sweep / 1e9,
+        relax_gbs=2 * state_bytes * n_dof / t_relax / 1e9,
+        bytes_per_sweep=2 * state_bytes * n_dof,
+        refine_correction=refine_corr,
+    )
+    result = None
+    if keep_state:
+        # the state after warmup + steps from the same initial data, for errors
+        g = f_init
+        prob.step(g, fb, warmup)
+        prob.step(g, fb, steps)
+        torch.cuda.synchronize()
+        result = g.double().cpu().numpy()
+        del g
+    del f, fb
+    prob.close()
+    torch.cuda.empty_cache()
+    return out, result
+
+
+def cpu_baseline(wl_name, seed, target_s):
+    """The CPU oracle (as it stands) on a bounded sample of the workload."""
+    import threadpoolctl
+
+    from oracle import step as ost
+    wl_full = W.make(wl_name, seed=seed)
+    inst_full = wl_full.instances[0]
+    # shrink the mesh until one oracle step fits the time budget (~1.1e5 DoF/s)
+    scale = inst_full.n[0]
+    while scale > 4:
+        trial = W.make(wl_name, seed=seed, scale=scale) if wl_name != "batch96" else None
+        if trial is None:
+            break
+        if trial.instances[0].n_dof / 1.1e5 <= target_s:
+            break
+        scale = int(scale * 0.8)
+    wl = W.make(wl_name, seed=seed, scale=scale)
+    inst = wl.instances[0]
+    prob = ost.Problem(inst.n, inst.lo, inst.hi, inst.degree, inst.vel, inst.m, inst.feq_kind, inst.feq_param)
+    x = prob.mesh.node_coords().reshape(-1, inst.dim)
+    f0 = prob.feq(inst.w0(x).reshape(inst.m, prob.mesh.nc, prob.mesh.nd))
+    fb = prob.inflow_from_w(inst.w0)
+    info = threadpoolctl.threadpool_info()
+    threads = max([1] + [int(i.get("num_threads", 1)) for i in info])
+    t0 = time.perf_counter()
+    f = prob.transport(f0, fb, fb, wl.dt, wl.theta)
+    f = prob.collide(f, wl.omega)
+    wall = time.perf_counter() - t0
+    return {"value": inst.n_dof / wall, "unit": "DoF-updates/s", "cores": threads, "kind": "oracle",
+            "sample": f"one interior step (sweep of all {inst.vel.shape[0]} velocities + relax) of {wl_name} "
+                      f"shrunk to {'x'.join(map(str, inst.n))} cells ({inst.n_dof} DoF), {wall:.1f} s, "
+                      f"numpy/scipy float64; host os.cpu_count()={os.cpu_count()}"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--workload", default=DEFAULT_WORKLOAD, choices=W.WORKLOADS)
+    ap.add_argument("--precision", default="fp64", choices=["fp64", "fp32refine", "fp32"])
+    ap.add_argument("--reps", type=int, default=20, help="launches per kernel-timing loop")
+    ap.add_argument("--seed", type=int, default=0)
+    ap.add_argument("--no-compare", action="store_true", help="skip the other precisions")
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--copy-probe-mib", type=int, default=0,
+                    help="also run a plain device copy of this size (counter calibration)")
+    args = ap.parse_args()
+
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU: this build has no multi-GPU path (asked for --gpus {args.gpus}); "
+              "run with --gpus 1", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    import paper_1702_00169_amd as pdg
+    torch.cuda.set_device(0)
+
+    prec_main = {"fp64": pdg.PDG_FP64, "fp32refine": pdg.PDG_FP32_REFINE, "fp32": pdg.PDG_FP32}[args.precision]
+    wl = W.make(args.workload, seed=args.seed)
+    compare = not args.no_compare
+    precs = [prec_main] + ([p for p in (0, 2, 1) if p != prec_main] if compare else [])
+    results, states = {}, {}
+    for p in precs:
+        print(f"[bench] {args.workload} {PREC_NAMES[p]}: {args.warmup} warm-up + {args.steps} timed steps",
+              file=sys.stderr, flush=True)
+        results[p], states[p] = measure(pdg, torch, wl, p, args.steps, args.warmup, args.reps, keep_state=compare)
+        print(f"[bench]   {results[p]['value']:.4e} DoF/s, sweep {results[p]['sweep_us']:.1f} us "
+              f"({results[p]['sweep_gbs']:.0f} GB/s), relax {results[p]['relax_us']:.1f} us", file=sys.stderr,
+              flush=True)
+    if args.copy_probe_mib > 0:
+        x = torch.empty(args.copy_probe_mib * 2 ** 20 // 8, dtype=torch.float64, device="cuda")
+        y = torch.empty_like(x)
+        x.fill_(1.0)
+        for _ in range(3):
+            y.copy_(x)
+        torch.cuda.synchronize()
+        del x, y
+
+    main_res = results[prec_main]
+    prec_report = {}
+    ref = states.get(0)
+    for p in precs:
+        r = dict(results[p])
+        entry = {k: r[k] for k in ("value", "ms_per_step", "sweep_us", "relax_us", "sweep_gbs", "relax_gbs")}
+        entry["refine_correction"] = r["refine_correction"]
+        if ref is not None and p != 0 and states.get(p) is not None:
+            d = states[p] - ref
+            entry["rel_err_vs_fp64_l2"] = float(np.linalg.norm(d) / np.linalg.norm(ref))
+            entry["rel_err_vs_fp64_max"] = float(np.max(np.abs(d)) / np.max(np.abs(ref)))
+        prec_report[PREC_NAMES[p]] = entry
+    if ref is not None:
+        prec_report["fp64"]["rel_err_note"] = ("fp64 matches the CPU oracle to <= 1e-12 in the parity tests; "
+                                               "the other precisions are compared with it after the same steps")
+
+    traffic = traffic_for(args.workload, PREC_NAMES[prec_main])
+    roof = {"bound": "hbm", "achieved": main_res["sweep_gbs"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": main_res["sweep_gbs"] / HBM_PEAK_GBS, "traffic": traffic,
+            "kernel": "sweep_kernel", "algorithmic_bytes_per_launch": main_res["bytes_per_sweep"],
+            "launch_us": main_res["sweep_us"]}
+    inst0 = wl.instances[0]
+    config = {"workload": f"{args.workload}: {wl.description}", "n_dof": wl.n_dof,
+              "instances": len(wl.instances), "cells": list(inst0.n) if len(wl.instances) == 1 else "per instance",
+              "degree": inst0.degree if len(wl.instances) == 1 else "per instance",
+              "nv": int(inst0.vel.shape[0]), "m": inst0.m, "dt": wl.dt, "theta": wl.theta, "omega": wl.omega,
+              "scheme": "collapsed Strang", "precision": PREC_NAMES[prec_main], "seed": args.seed}
+    out = {"metric": METRIC, "value": main_res["value"], "unit": "DoF-updates/s", "n_gpus": 1,
+           "steps": args.steps, "warmup": args.warmup, "ms_per_step": main_res["ms_per_step"],
+           "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": DTYPE_NAMES[prec_main],
+           "data": "synthetic", "config": config, "roofline": roof, "precisions": prec_report}
+    if not args.no_cpu:
+        print("[bench] cpu baseline (oracle)", file=sys.stderr, flush=True)
+        out["cpu_baseline"] = cpu_baseline(args.workload if args.workload != "batch96" else "adv2d_16", args.seed,
+                                           args.cpu_seconds)
+    print(json.dumps(out))
+
+
+if __name__ == "__main__":
+    main()

@@ -42,7 +42,7 @@ struct Instance {
 };
 
 struct Group {
-  int np, S, C, x_kind;
+  int np, lds;           // node count, largest LDS tile of its items
   int64_t first, count;  // range in the item array
 };
 
@@ -279,11 +279,13 @@ int pow2_ceil(int x) {
 }
 
 void choose_tile(int prec, int np, int n, int64_t ntc, int x_kind, int &C, int &S) {
+  const int smax = sweep_smax(np);
   if (const char *env = std::getenv("PDG_TILE")) {
     // "C,S" override for tuning sweeps
     int c2 = 0, s2 = 0;
-    if (std::sscanf(env, "%d,%d", &c2, &s2) == 2 && c2 > 0 && s2 > 0) {
-      if (!x_kind || (kBlock / c2) * s2 >= n) {
+    if (std::sscanf(env, "%d,%d", &c2, &s2) == 2 && c2 > 0 && c2 <= kBlock && kBlock % c2 == 0 && s2 > 0 &&
+        s2 <= smax) {
+      if (!x_kind || ((kBlock / c2) * s2 >= n && sweep_lds_bytes(prec, np, s2, 1) <= 49152)) {
         C = c2;
         S = s2;
         return;
@@ -294,12 +296,12 @@ void choose_tile(int prec, int np, int n, int64_t ntc, int x_kind, int &C, int &
     // one window covers the whole row: (kBlock / C) * S >= n and the LDS tile
     // fits in 48 KiB; prefer the smallest S with at most 32 segments per row
     int best = -1;
-    for (int s = 1; s <= 8; s <<= 1) {
+    for (int s = 1; s <= smax; s <<= 1) {
       if (sweep_lds_bytes(prec, np, s, 1) > 49152 || (int64_t)kBlock * s < n) continue;
       best = s;
       if ((n + s - 1) / s <= 32) break;
     }
-    S = best < 0 ? 8 : best;
+    S = best < 0 ? smax : best;
     int P = std::min(kBlock, pow2_ceil((n + S - 1) / S));
     C = kBlock / P;
     return;
@@ -309,7 +311,7 @@ void choose_tile(int prec, int np, int n, int64_t ntc, int x_kind, int &C, int &
   C = std::max(C, 8);
   int P = kBlock / C;
   S = 1;
-  while (S < 8 && P * S < n) S <<= 1;
+  while (S < smax && P * S < n) S <<= 1;
 }
 
 }  // namespace
@@ -578,7 +580,8 @@ pdg_status pdg_prepare(pdg_ctx *c, double dt, double theta, double omega, pdg_sc
   // ---- operator table: (instance, velocity, dt_sub in {dt, dt/2}) --------
   std::vector<OpEntry> ops;
   std::vector<SweepDesc> sdesc;
-  std::vector<std::vector<SweepItem>> by_group;
+  // (estimated cost, item) per launch group; cost = sequential cells per thread
+  std::vector<std::vector<std::pair<int, SweepItem>>> by_group;
   std::map<std::vector<int>, int> group_of;
   std::vector<Group> groups;
   for (size_t ii = 0; ii < c->inst.size(); ++ii) {
@@ -639,17 +642,21 @@ pdg_status pdg_prepare(pdg_ctx *c, double dt, double theta, double omega, pdg_sc
       int C = 64, S = 1;
       choose_tile(prec, np, sd.n_a, ntc, sd.x_kind, C, S);
       if (sd.x_kind && (int64_t)(kBlock / C) * S < sd.n_a) return PDG_EUNSUPPORTED;
-      std::vector<int> key = {np, S, C, sd.x_kind};
+      std::vector<int> key = {np};
       auto itg = group_of.find(key);
       int gi;
       if (itg == group_of.end()) {
         gi = (int)groups.size();
         group_of[key] = gi;
-        groups.push_back(Group{np, S, C, sd.x_kind, 0, 0});
+        groups.push_back(Group{np, 0, 0, 0});
         by_group.emplace_back();
       } else {
         gi = itg->second;
       }
+      groups[gi].lds = std::max(groups[gi].lds, sweep_lds_bytes(prec, np, S, sd.x_kind));
+      // sequential cells per thread: a proxy of the workgroup's duration
+      const int windows = sd.x_kind ? 1 : (sd.n_a + (kBlock / C) * S - 1) / ((kBlock / C) * S);
+      const int cost = windows * S;
       int64_t tnodes = 1;
       for (int k = 0; k < dim - 1; ++k) tnodes *= np;
       int other[2] = {0, 0}, no = 0;
@@ -676,20 +683,24 @@ pdg_status pdg_prepare(pdg_ctx *c, double dt, double theta, double omega, pdg_sc
             item.desc = desc_index;
             item.tau0 = (int32_t)tau0;
             item.count = (int32_t)std::min<int64_t>(C, ntc - tau0);
-            item.pad = sd.n_a;  // work estimate (cells per chain) for ordering
-            by_group[gi].push_back(item);
+            item.C = (int16_t)C;
+            item.S = (int8_t)S;
+            item.xk = (int8_t)sd.x_kind;
+            by_group[gi].push_back({cost, item});
           }
         }
     }
   }
-  // longest chains first inside each group
+  // longest-running workgroups first inside each launch
   std::vector<SweepItem> items;
   for (size_t g = 0; g < groups.size(); ++g) {
     std::stable_sort(by_group[g].begin(), by_group[g].end(),
-                     [](const SweepItem &a, const SweepItem &b) { return a.pad > b.pad; });
+                     [](const std::pair<int, SweepItem> &a, const std::pair<int, SweepItem> &b) {
+                       return a.first > b.first;
+                     });
     groups[g].first = (int64_t)items.size();
     groups[g].count = (int64_t)by_group[g].size();
-    items.insert(items.end(), by_group[g].begin(), by_group[g].end());
+    for (const auto &ci : by_group[g]) items.push_back(ci.second);
   }
 
   // ---- relax tables --------------------------------------------------------
@@ -808,11 +819,11 @@ namespace {
 pdg_status do_sweep(pdg_ctx *c, void *f, const double *fb_old, const double *fb_new, int dt_idx,
                     hipStream_t st) {
   for (const Group &g : c->groups) {
-    hipError_t e = launch_sweep(c->prec, g.np, g.S, g.C, g.x_kind, c->sitems.p + g.first, (int)g.count,
-                                c->sdesc.p, c->ops.p, dt_idx, f, fb_old, fb_new, c->stats.p + 2 * g.first, st);
+    hipError_t e = launch_sweep(c->prec, g.np, g.lds, c->sitems.p + g.first, (int)g.count, c->sdesc.p, c->ops.p,
+                                dt_idx, f, fb_old, fb_new, c->stats.p + 2 * g.first, st);
     if (e != hipSuccess) {
       char what[96];
-      std::snprintf(what, sizeof(what), "launch_sweep(np=%d,S=%d,C=%d,x=%d)", g.np, g.S, g.C, g.x_kind);
+      std::snprintf(what, sizeof(what), "launch_sweep(np=%d,lds=%d,items=%lld)", g.np, g.lds, (long long)g.count);
       return from_hip_at(e, what);
     }
   }

@@ -34,9 +34,14 @@ struct SweepItem {
   int64_t fb;     // fb offset of chain tau0
   int32_t desc;   // SweepDesc index
   int32_t tau0;
-  int32_t count;
-  int32_t pad;
+  int32_t count;  // chains of this item (<= C)
+  int16_t C;      // chains per workgroup; kBlock / C segments per chain window
+  int8_t S;       // cells per segment (<= sweep_smax(np))
+  int8_t xk;      // 1: LDS-staged path (chains along the contiguous axis)
 };
+
+// Largest segment length compiled for a node count (register budget).
+constexpr int sweep_smax(int np) { return np <= 3 ? 8 : 4; }
 
 // Operator table row: one (instance, velocity, dt_sub).  Downwind-local node
 // order (q = 0 inflow node, q = NP-1 outflow node).  Filled partly on the host
@@ -91,8 +96,9 @@ enum Prec { kF64 = 0, kF32 = 1, kRefine = 2 };
 
 hipError_t launch_invert(OpEntry *ops, int n_ops, hipStream_t st);
 
-// Launch one sweep group: all items share (np, S, C, x_kind).
-hipError_t launch_sweep(int prec, int np, int S, int C, int x_kind, const SweepItem *items, int n_items,
+// Launch one sweep over items that share the node count np (any chain kind,
+// tile shape or instance); lds_bytes = largest LDS tile of the items.
+hipError_t launch_sweep(int prec, int np, int lds_bytes, const SweepItem *items, int n_items,
                         const SweepDesc *descs, const OpEntry *ops, int dt_idx, void *f, const double *fb_old,
                         const double *fb_new, double *stats, hipStream_t st);
 

@@ -155,10 +155,10 @@ struct CellOp<kRefine, NP> {
   }
 };
 
-template <int PREC, int NP, int S, bool XK>
+template <int PREC, int NP, int SMAX>
 __global__ __launch_bounds__(kBlock) void sweep_kernel(const SweepItem *__restrict__ items,
                                                       const SweepDesc *__restrict__ descs,
-                                                      const OpEntry *__restrict__ ops, int dt_idx, int C,
+                                                      const OpEntry *__restrict__ ops, int dt_idx,
                                                       typename Pol<PREC>::St *__restrict__ f,
                                                       const double *__restrict__ fb_old,
                                                       const double *__restrict__ fb_new,
@@ -177,10 +177,12 @@ __global__ __launch_bounds__(kBlock) void sweep_kernel(const SweepItem *__restri
   op.load(ops[d.op + dt_idx]);
   const Rt theta = op.theta;
   const Rt omt = (Rt)1 - theta;
-  const Rt gout = op.g[NP - 1];
 
+  const int C = it.C;       // chains per workgroup (lanes per segment row)
+  const int S = it.S;       // cells per segment, <= SMAX
+  const bool xk = it.xk != 0;
   const int t = threadIdx.x;
-  const int P = kBlock / C;
+  const int P = kBlock / C;  // segments per chain window
   const int c = t % C;
   const int p = t / C;
   const bool active = c < it.count;
@@ -194,8 +196,9 @@ __global__ __launch_bounds__(kBlock) void sweep_kernel(const SweepItem *__restri
   const int tau = it.tau0 + c;
   const int64_t chain = it.base + (int64_t)(tau % d.nx) + (int64_t)(tau / d.nx) * d.hi_stride + d.cell0 + d.plane0;
 
-  if (XK) {
+  if (xk) {
     // cooperative coalesced copy of count rows x n cells x NP planes into LDS
+    // (one window covers a whole row: P * S >= n)
     const int total = it.count * n;
 #pragma unroll
     for (int q = 0; q < NP; ++q) {
@@ -216,15 +219,15 @@ __global__ __launch_bounds__(kBlock) void sweep_kernel(const SweepItem *__restri
   for (int w0 = 0; w0 < n; w0 += window, wpar ^= 1) {
     const int lb = w0 + p * S;
     const int cnt = active ? max(0, min(S, n - lb)) : 0;
-    Rt y[S][NP];
-    Rt fo[S];
+    Rt y[SMAX][NP];
+    Rt fo[SMAX];
 #pragma unroll
-    for (int s = 0; s < S; ++s) {
+    for (int s = 0; s < SMAX; ++s) {
       Rt fv[NP];
       if (s < cnt) {
 #pragma unroll
         for (int q = 0; q < NP; ++q) {
-          if (XK)
+          if (xk)
             fv[q] = (Rt)tile[(q * S + s) * kRow + t];
           else
             fv[q] = (Rt)f[chain + (int64_t)(lb + s) * d.cell_step + q * d.plane_step];
@@ -239,7 +242,7 @@ __global__ __launch_bounds__(kBlock) void sweep_kernel(const SweepItem *__restri
     // affine map of this segment: u_out = alpha u_in + beta
     Rt alpha = 1, beta = 0;
 #pragma unroll
-    for (int s = 0; s < S; ++s) {
+    for (int s = 0; s < SMAX; ++s) {
       if (s < cnt) {
         beta = fma(op.a, beta, theta * y[s][NP - 1] + omt * fo[s]);
         alpha *= op.a;
@@ -255,14 +258,14 @@ __global__ __launch_bounds__(kBlock) void sweep_kernel(const SweepItem *__restri
     // finish the segment with its exact inflow
     Rt uu = uin;
 #pragma unroll
-    for (int s = 0; s < S; ++s) {
+    for (int s = 0; s < SMAX; ++s) {
       if (s < cnt) {
         Rt xo = 0;
 #pragma unroll
         for (int q = 0; q < NP; ++q) {
           const Rt xv = fma(op.g[q], uu, y[s][q]);
           if (q == NP - 1) xo = xv;
-          if (XK)
+          if (xk)
             tile[(q * S + s) * kRow + t] = (St)xv;
           else
             f[chain + (int64_t)(lb + s) * d.cell_step + q * d.plane_step] = (St)xv;
@@ -270,11 +273,10 @@ __global__ __launch_bounds__(kBlock) void sweep_kernel(const SweepItem *__restri
         uu = theta * xo + omt * fo[s];
       }
     }
-    (void)gout;
     u = unext;
   }
 
-  if (XK) {
+  if (xk) {
     __syncthreads();
     const int total = it.count * n;
 #pragma unroll
@@ -515,48 +517,26 @@ __global__ void fill_kernel(double *p, int64_t n, double value) {
 // ---------------------------------------------------------------------------
 // dispatch
 // ---------------------------------------------------------------------------
-template <int PREC, int NP, int S, bool XK>
-hipError_t go_sweep(int C, const SweepItem *items, int n_items, const SweepDesc *descs, const OpEntry *ops,
+template <int PREC, int NP>
+hipError_t go_sweep(int lds, const SweepItem *items, int n_items, const SweepDesc *descs, const OpEntry *ops,
                     int dt_idx, void *f, const double *fb_old, const double *fb_new, double *stats,
                     hipStream_t st) {
   using St = typename Pol<PREC>::St;
-  const size_t lds = XK ? (size_t)NP * S * (kBlock + 1) * sizeof(St) : 0;
-  hipLaunchKernelGGL((sweep_kernel<PREC, NP, S, XK>), dim3(n_items), dim3(kBlock), lds, st, items, descs, ops,
-                     dt_idx, C, static_cast<St *>(f), fb_old, fb_new, stats);
+  constexpr int SMAX = sweep_smax(NP);
+  hipLaunchKernelGGL((sweep_kernel<PREC, NP, SMAX>), dim3(n_items), dim3(kBlock), (size_t)lds, st, items, descs, ops,
+                     dt_idx, static_cast<St *>(f), fb_old, fb_new, stats);
   return hipGetLastError();
 }
 
-template <int PREC, int NP, int S>
-hipError_t go_sweep_x(int x_kind, int C, const SweepItem *items, int n_items, const SweepDesc *descs,
-                      const OpEntry *ops, int dt_idx, void *f, const double *fb_old, const double *fb_new,
-                      double *stats, hipStream_t st) {
-  if (x_kind)
-    return go_sweep<PREC, NP, S, true>(C, items, n_items, descs, ops, dt_idx, f, fb_old, fb_new, stats, st);
-  return go_sweep<PREC, NP, S, false>(C, items, n_items, descs, ops, dt_idx, f, fb_old, fb_new, stats, st);
-}
-
-template <int PREC, int NP>
-hipError_t go_sweep_s(int S, int x_kind, int C, const SweepItem *items, int n_items, const SweepDesc *descs,
-                      const OpEntry *ops, int dt_idx, void *f, const double *fb_old, const double *fb_new,
-                      double *stats, hipStream_t st) {
-  switch (S) {
-    case 1: return go_sweep_x<PREC, NP, 1>(x_kind, C, items, n_items, descs, ops, dt_idx, f, fb_old, fb_new, stats, st);
-    case 2: return go_sweep_x<PREC, NP, 2>(x_kind, C, items, n_items, descs, ops, dt_idx, f, fb_old, fb_new, stats, st);
-    case 4: return go_sweep_x<PREC, NP, 4>(x_kind, C, items, n_items, descs, ops, dt_idx, f, fb_old, fb_new, stats, st);
-    case 8: return go_sweep_x<PREC, NP, 8>(x_kind, C, items, n_items, descs, ops, dt_idx, f, fb_old, fb_new, stats, st);
-    default: return hipErrorInvalidValue;
-  }
-}
-
 template <int PREC>
-hipError_t go_sweep_np(int np, int S, int x_kind, int C, const SweepItem *items, int n_items,
-                       const SweepDesc *descs, const OpEntry *ops, int dt_idx, void *f, const double *fb_old,
-                       const double *fb_new, double *stats, hipStream_t st) {
+hipError_t go_sweep_np(int np, int lds, const SweepItem *items, int n_items, const SweepDesc *descs,
+                       const OpEntry *ops, int dt_idx, void *f, const double *fb_old, const double *fb_new,
+                       double *stats, hipStream_t st) {
   switch (np) {
-    case 2: return go_sweep_s<PREC, 2>(S, x_kind, C, items, n_items, descs, ops, dt_idx, f, fb_old, fb_new, stats, st);
-    case 3: return go_sweep_s<PREC, 3>(S, x_kind, C, items, n_items, descs, ops, dt_idx, f, fb_old, fb_new, stats, st);
-    case 4: return go_sweep_s<PREC, 4>(S, x_kind, C, items, n_items, descs, ops, dt_idx, f, fb_old, fb_new, stats, st);
-    case 5: return go_sweep_s<PREC, 5>(S, x_kind, C, items, n_items, descs, ops, dt_idx, f, fb_old, fb_new, stats, st);
+    case 2: return go_sweep<PREC, 2>(lds, items, n_items, descs, ops, dt_idx, f, fb_old, fb_new, stats, st);
+    case 3: return go_sweep<PREC, 3>(lds, items, n_items, descs, ops, dt_idx, f, fb_old, fb_new, stats, st);
+    case 4: return go_sweep<PREC, 4>(lds, items, n_items, descs, ops, dt_idx, f, fb_old, fb_new, stats, st);
+    case 5: return go_sweep<PREC, 5>(lds, items, n_items, descs, ops, dt_idx, f, fb_old, fb_new, stats, st);
     default: return hipErrorInvalidValue;
   }
 }
@@ -615,15 +595,14 @@ hipError_t launch_invert(OpEntry *ops, int n_ops, hipStream_t st) {
   return hipGetLastError();
 }
 
-hipError_t launch_sweep(int prec, int np, int S, int C, int x_kind, const SweepItem *items, int n_items,
+hipError_t launch_sweep(int prec, int np, int lds_bytes, const SweepItem *items, int n_items,
                         const SweepDesc *descs, const OpEntry *ops, int dt_idx, void *f, const double *fb_old,
                         const double *fb_new, double *stats, hipStream_t st) {
   if (n_items <= 0) return hipSuccess;
-  if (C <= 0 || kBlock % C != 0) return hipErrorInvalidValue;
   switch (prec) {
-    case kF64: return go_sweep_np<kF64>(np, S, x_kind, C, items, n_items, descs, ops, dt_idx, f, fb_old, fb_new, stats, st);
-    case kF32: return go_sweep_np<kF32>(np, S, x_kind, C, items, n_items, descs, ops, dt_idx, f, fb_old, fb_new, stats, st);
-    case kRefine: return go_sweep_np<kRefine>(np, S, x_kind, C, items, n_items, descs, ops, dt_idx, f, fb_old, fb_new, stats, st);
+    case kF64: return go_sweep_np<kF64>(np, lds_bytes, items, n_items, descs, ops, dt_idx, f, fb_old, fb_new, stats, st);
+    case kF32: return go_sweep_np<kF32>(np, lds_bytes, items, n_items, descs, ops, dt_idx, f, fb_old, fb_new, stats, st);
+    case kRefine: return go_sweep_np<kRefine>(np, lds_bytes, items, n_items, descs, ops, dt_idx, f, fb_old, fb_new, stats, st);
     default: return hipErrorInvalidValue;
   }
 }
