@@ -66,11 +66,10 @@ def initial_state(pdg, prob, insts, torch, dtype):
     fb = torch.empty(prob.layout["fb_elems"], dtype=torch.float64, device="cuda")
     w_t = torch.from_numpy(w).cuda()
     prob.equilibrium(w_t, f)
-    del w_t
     fbw_t = torch.from_numpy(fbw).cuda()
     prob.inflow_equilibrium(fbw_t, fb)
     torch.cuda.synchronize()
-    return f, fb
+    return f, fb, w_t
 
 
 def kernel_source_hash():
@@ -96,12 +95,19 @@ def traffic_for(workload, prec_name):
     return ent.get("bytes_per_launch")
 
 
-def measure(pdg, torch, wl, prec, steps, warmup, reps, keep_state=False):
+def measure(pdg, torch, wl, prec, steps, warmup, reps, keep_state=False, autotune=True):
     insts = wl.instances
     prob = pdg.Problem([inst_dict(i) for i in insts])
     prob.prepare(wl.dt, theta=wl.theta, omega=wl.omega, scheme=pdg.PDG_STRANG_COLLAPSED, precision=prec)
     dtype = torch.float32 if prec == pdg.PDG_FP32 else torch.float64
-    f, fb = initial_state(pdg, prob, insts, torch, dtype)
+    f, fb, w_t = initial_state(pdg, prob, insts, torch, dtype)
+    if autotune:
+        # tile search on the state buffer itself, then restore the initial state
+        prob.autotune(f, fb, reps=3)
+        prob.equilibrium(w_t, f)
+        torch.cuda.synchronize()
+    del w_t
+    tiles = prob.tiles()
     f_init = f.clone() if keep_state else None
     n_dof = wl.n_dof
     # warm-up (also records the step graph)
@@ -134,6 +140,7 @@ def measure(pdg, torch, wl, prec, steps, warmup, reps, keep_state=False):
         relax_gbs=2 * state_bytes * n_dof / t_relax / 1e9,
         bytes_per_sweep=2 * state_bytes * n_dof,
         refine_correction=refine_corr,
+        tiles=tiles,
     )
     result = None
     if keep_state:
@@ -155,29 +162,32 @@ def cpu_baseline(wl_name, seed, target_s):
     import threadpoolctl
 
     from oracle import step as ost
-    wl_full = W.make(wl_name, seed=seed)
-    inst_full = wl_full.instances[0]
-    # shrink the mesh until one oracle step fits the time budget (~1.1e5 DoF/s)
-    scale = inst_full.n[0]
-    while scale > 4:
-        trial = W.make(wl_name, seed=seed, scale=scale) if wl_name != "batch96" else None
-        if trial is None:
+    def one_step(scale):
+        wl = W.make(wl_name, seed=seed, scale=scale)
+        inst = wl.instances[0]
+        prob = ost.Problem(inst.n, inst.lo, inst.hi, inst.degree, inst.vel, inst.m, inst.feq_kind, inst.feq_param)
+        x = prob.mesh.node_coords().reshape(-1, inst.dim)
+        f0 = prob.feq(inst.w0(x).reshape(inst.m, prob.mesh.nc, prob.mesh.nd))
+        fb = prob.inflow_from_w(inst.w0)
+        t0 = time.perf_counter()
+        f = prob.transport(f0, fb, fb, wl.dt, wl.theta)
+        prob.collide(f, wl.omega)
+        return inst, time.perf_counter() - t0
+
+    # calibrate the oracle's rate on a small mesh, then size the sample for ~target_s
+    full_n = W.make(wl_name, seed=seed).instances[0].n[0]
+    small = min(full_n, 8)
+    inst_s, t_s = one_step(small)
+    rate = inst_s.n_dof / t_s
+    scale = small
+    while scale < full_n:
+        nxt = min(full_n, scale + max(1, scale // 4))
+        if W.make(wl_name, seed=seed, scale=nxt).instances[0].n_dof / rate > target_s:
             break
-        if trial.instances[0].n_dof / 1.1e5 <= target_s:
-            break
-        scale = int(scale * 0.8)
-    wl = W.make(wl_name, seed=seed, scale=scale)
-    inst = wl.instances[0]
-    prob = ost.Problem(inst.n, inst.lo, inst.hi, inst.degree, inst.vel, inst.m, inst.feq_kind, inst.feq_param)
-    x = prob.mesh.node_coords().reshape(-1, inst.dim)
-    f0 = prob.feq(inst.w0(x).reshape(inst.m, prob.mesh.nc, prob.mesh.nd))
-    fb = prob.inflow_from_w(inst.w0)
+        scale = nxt
+    inst, wall = one_step(scale)
     info = threadpoolctl.threadpool_info()
     threads = max([1] + [int(i.get("num_threads", 1)) for i in info])
-    t0 = time.perf_counter()
-    f = prob.transport(f0, fb, fb, wl.dt, wl.theta)
-    f = prob.collide(f, wl.omega)
-    wall = time.perf_counter() - t0
     return {"value": inst.n_dof / wall, "unit": "DoF-updates/s", "cores": threads, "kind": "oracle",
             "sample": f"one interior step (sweep of all {inst.vel.shape[0]} velocities + relax) of {wl_name} "
                       f"shrunk to {'x'.join(map(str, inst.n))} cells ({inst.n_dof} DoF), {wall:.1f} s, "
@@ -195,6 +205,7 @@ def main():
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--no-compare", action="store_true", help="skip the other precisions")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--no-autotune", action="store_true", help="keep the default tiles")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="also run a plain device copy of this size (counter calibration)")
@@ -217,7 +228,8 @@ def main():
     for p in precs:
         print(f"[bench] {args.workload} {PREC_NAMES[p]}: {args.warmup} warm-up + {args.steps} timed steps",
               file=sys.stderr, flush=True)
-        results[p], states[p] = measure(pdg, torch, wl, p, args.steps, args.warmup, args.reps, keep_state=compare)
+        results[p], states[p] = measure(pdg, torch, wl, p, args.steps, args.warmup, args.reps, keep_state=compare,
+                                        autotune=not args.no_autotune)
         print(f"[bench]   {results[p]['value']:.4e} DoF/s, sweep {results[p]['sweep_us']:.1f} us "
               f"({results[p]['sweep_gbs']:.0f} GB/s), relax {results[p]['relax_us']:.1f} us", file=sys.stderr,
               flush=True)
@@ -237,6 +249,7 @@ def main():
         r = dict(results[p])
         entry = {k: r[k] for k in ("value", "ms_per_step", "sweep_us", "relax_us", "sweep_gbs", "relax_gbs")}
         entry["refine_correction"] = r["refine_correction"]
+        entry["tiles"] = r["tiles"]
         if ref is not None and p != 0 and states.get(p) is not None:
             d = states[p] - ref
             entry["rel_err_vs_fp64_l2"] = float(np.linalg.norm(d) / np.linalg.norm(ref))

@@ -183,6 +183,27 @@ pdg_status pdg_relax(pdg_ctx *c, void *f, double *w_out, void *stream);
  * recorded once as a HIP graph per (f, fb) pair and replayed. */
 pdg_status pdg_step(pdg_ctx *c, void *f, const double *fb, int32_t n_steps, void *stream);
 
+/* Autotuner of the sweep's work decomposition.  Work items are grouped in
+ * launch classes (same node count d+1 and same chain kind: chains along the
+ * contiguous x axis, or along a strided axis).  For every class this times
+ * each candidate tile (x chains: rows per workgroup 1..64; strided chains:
+ * chains per workgroup 8..64 x cells per thread segment 1..8) with `reps`
+ * launches of the class alone on `stream`, keeps the fastest, and uses it
+ * from then on.  f is used as scratch and overwritten; fb is read.  Every tile
+ * solves the same system; only the rounding order of the segment combine
+ * differs.  Drops the cached step graph. */
+pdg_status pdg_autotune(pdg_ctx *c, void *f_scratch, const double *fb, int32_t reps, void *stream);
+
+/* Current tiles: *n_classes receives the number of launch classes; if
+ * `tiles` is not NULL, up to the incoming *n_classes entries of 4 int32 each
+ * are written: (d+1, chain kind (1 = x), C, S).  Host only. */
+pdg_status pdg_get_tiles(const pdg_ctx *c, int32_t *n_classes, int32_t *tiles);
+
+/* Apply tiles (same 4-int format, e.g. a cached autotuner result); classes
+ * are matched by (d+1, chain kind).  PDG_EINVAL for an unknown class or an
+ * invalid tile; nothing is changed then. */
+pdg_status pdg_set_tiles(pdg_ctx *c, int32_t n_classes, const int32_t *tiles);
+
 /* For PDG_FP32_REFINE: max over nodes of |correction| / max |solution| seen by
  * the most recent sweep (synchronises the stream of that sweep). */
 pdg_status pdg_last_refine_correction(const pdg_ctx *c, double *max_rel_correction);

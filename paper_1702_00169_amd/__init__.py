@@ -22,7 +22,7 @@ PDG_LIE, PDG_STRANG, PDG_STRANG_COLLAPSED = 0, 1, 2
 
 EXPORTED = ("pdg_setup_mesh", "pdg_layout", "pdg_node_coords", "pdg_levels", "pdg_topo_levels", "pdg_line_operator",
             "pdg_prepare", "pdg_equilibrium", "pdg_inflow_equilibrium", "pdg_transport_sweep",
-            "pdg_relax", "pdg_step", "pdg_last_refine_correction", "pdg_status_string", "pdg_error_detail", "pdg_destroy")
+            "pdg_relax", "pdg_step", "pdg_autotune", "pdg_get_tiles", "pdg_set_tiles", "pdg_last_refine_correction", "pdg_status_string", "pdg_error_detail", "pdg_destroy")
 
 
 class PdgError(RuntimeError):
@@ -63,6 +63,9 @@ def _load():
         "pdg_transport_sweep": (i32, [p, p, p, p, d, p]),
         "pdg_relax": (i32, [p, p, p, p]),
         "pdg_step": (i32, [p, p, p, i32, p]),
+        "pdg_autotune": (i32, [p, p, p, i32, p]),
+        "pdg_get_tiles": (i32, [p, ctypes.POINTER(i32), p]),
+        "pdg_set_tiles": (i32, [p, i32, p]),
         "pdg_last_refine_correction": (i32, [p, ctypes.POINTER(d)]),
         "pdg_status_string": (ctypes.c_char_p, [i32]),
         "pdg_error_detail": (ctypes.c_char_p, []),
@@ -192,6 +195,27 @@ def pdg_step(ctx, f, fb, n_steps, stream=None):
     _check(_lib.pdg_step(ctx, _ptr(f), _ptr(fb), int(n_steps), _stream(stream)), "pdg_step")
 
 
+def pdg_autotune(ctx, f_scratch, fb, reps=3, stream=None):
+    _check(_lib.pdg_autotune(ctx, _ptr(f_scratch), _ptr(fb), int(reps), _stream(stream)), "pdg_autotune")
+
+
+def pdg_get_tiles(ctx):
+    """List of dicts {np, x_kind, C, S}, one per launch class."""
+    import numpy as np
+    n = ctypes.c_int32(0)
+    _check(_lib.pdg_get_tiles(ctx, ctypes.byref(n), None), "pdg_get_tiles")
+    buf = np.zeros(4 * max(1, n.value), np.int32)
+    _check(_lib.pdg_get_tiles(ctx, ctypes.byref(n), _ptr(buf)), "pdg_get_tiles")
+    return [dict(np=int(buf[4 * i]), x_kind=int(buf[4 * i + 1]), C=int(buf[4 * i + 2]), S=int(buf[4 * i + 3]))
+            for i in range(n.value)]
+
+
+def pdg_set_tiles(ctx, tiles):
+    import numpy as np
+    buf = np.array([[t["np"], t["x_kind"], t["C"], t["S"]] for t in tiles], np.int32).ravel()
+    _check(_lib.pdg_set_tiles(ctx, len(tiles), _ptr(buf)), "pdg_set_tiles")
+
+
 def pdg_last_refine_correction(ctx):
     out = ctypes.c_double()
     _check(_lib.pdg_last_refine_correction(ctx, ctypes.byref(out)), "pdg_last_refine_correction")
@@ -255,6 +279,16 @@ class Problem:
 
     def step(self, f, fb, n_steps, stream=None):
         pdg_step(self.ctx, f, fb, n_steps, stream)
+
+    def autotune(self, f_scratch, fb, reps=3, stream=None):
+        pdg_autotune(self.ctx, f_scratch, fb, reps, stream)
+        return pdg_get_tiles(self.ctx)
+
+    def tiles(self):
+        return pdg_get_tiles(self.ctx)
+
+    def set_tiles(self, tiles):
+        pdg_set_tiles(self.ctx, tiles)
 
     def last_refine_correction(self):
         return pdg_last_refine_correction(self.ctx)

@@ -42,13 +42,37 @@ struct Instance {
 };
 
 struct Group {
-  int np, lds;           // node count, largest LDS tile of its items
+  int np;                // node count of every item in the launch
   int64_t first, count;  // range in the item array
 };
 
 struct RelaxGroup {
   int nv, m;
   int64_t first, count;
+};
+
+// One (instance, velocity) family of chains and its launch class.
+struct Family {
+  int desc;                          // SweepDesc index
+  int cls;                           // launch class index
+  int np, x_kind, n_a, m;
+  int64_t ntc;                       // chains per (component, transverse node)
+  int64_t tnodes;                    // transverse node combinations
+  std::vector<int64_t> plane_off;    // per transverse node: element offset of its plane
+  int64_t f_vel;                     // element offset of (instance, v, k = 0, plane 0)
+  int64_t comp_stride;               // Nd * Nc
+  int64_t fb_vel;                    // fb offset of (instance, v, k = 0)
+};
+
+// Launch class: families sharing the node count (one kernel instantiation)
+// and the chain kind (contiguous or strided axis) share one tile choice.
+struct LaunchClass {
+  int np, x_kind;
+  int64_t chains;  // total chains of the class (all components, transverse nodes)
+  int n_max;
+  int C, S;        // x: C = rows per workgroup; strided: C chains, S = segment cap
+  int group;       // launch group (np)
+  int64_t first, count;  // item range
 };
 
 template <class T>
@@ -87,6 +111,8 @@ struct pdg_ctx {
   DevBuf<SweepDesc> sdesc;
   DevBuf<SweepItem> sitems;
   std::vector<Group> groups;
+  std::vector<Family> fams;
+  std::vector<LaunchClass> classes;
   DevBuf<RelaxDesc> rdesc;
   DevBuf<RelaxItem> ritems;
   std::vector<RelaxGroup> rgroups;
@@ -116,6 +142,8 @@ struct pdg_ctx {
     if (cap_stream) (void)hipStreamDestroy(cap_stream);
     cap_stream = nullptr;
     groups.clear();
+    fams.clear();
+    classes.clear();
     rgroups.clear();
     igroups.clear();
     prepared = false;
@@ -278,40 +306,100 @@ int pow2_ceil(int x) {
   return p;
 }
 
-void choose_tile(int prec, int np, int n, int64_t ntc, int x_kind, int &C, int &S) {
-  const int smax = sweep_smax(np);
-  if (const char *env = std::getenv("PDG_TILE")) {
-    // "C,S" override for tuning sweeps
-    int c2 = 0, s2 = 0;
-    if (std::sscanf(env, "%d,%d", &c2, &s2) == 2 && c2 > 0 && c2 <= kBlock && kBlock % c2 == 0 && s2 > 0 &&
-        s2 <= smax) {
-      if (!x_kind || ((kBlock / c2) * s2 >= n && sweep_lds_bytes(prec, np, s2, 1) <= 49152)) {
-        C = c2;
-        S = s2;
-        return;
+// Default tile of a launch class, from measured behaviour on gfx950: enough
+// workgroups to fill the 256 CUs several times over, as much work per
+// workgroup as that allows.  `PDG_TILE_X` / `PDG_TILE_Y` ("C,S") override it.
+void default_tile(LaunchClass &k) {
+  const int smax = sweep_smax(k.np);
+  if (k.x_kind) {
+    int C = 64;
+    while (C > 1 && ((int64_t)C * k.n_max > 4096 || k.chains / C < 2048)) C >>= 1;
+    while (C > 1 && (int64_t)C * k.n_max >= 65536) C >>= 1;
+    k.C = C;
+    k.S = 1;
+  } else {
+    int C = 64;
+    while (C > 16 && k.chains / C < 4096) C >>= 1;
+    k.C = C;
+    k.S = smax;
+  }
+  const char *env = std::getenv(k.x_kind ? "PDG_TILE_X" : "PDG_TILE_Y");
+  if (!env) env = std::getenv("PDG_TILE");
+  int c2 = 0, s2 = 0;
+  if (env && std::sscanf(env, "%d,%d", &c2, &s2) == 2 && c2 > 0 && c2 <= kBlock && s2 > 0 && s2 <= smax) {
+    if (k.x_kind) {
+      k.C = c2;
+      while (k.C > 1 && (int64_t)k.C * k.n_max >= 65536) k.C >>= 1;
+    } else if (kBlock % c2 == 0) {
+      k.C = c2;
+      k.S = s2;
+    }
+  }
+}
+
+// Segment length of a strided family under its class tile: the smallest
+// power of two covering the chain in one window, capped by the class.
+int family_S(const LaunchClass &k, int n_a) {
+  if (k.x_kind) return 1;
+  const int P = kBlock / k.C;
+  int S = 1;
+  while (S < k.S && P * S < n_a) S <<= 1;
+  return S;
+}
+
+// Work items of every class under the current tiles; longest-running
+// workgroups first inside each launch, classes contiguous.
+void build_items(pdg_ctx *c, std::vector<SweepItem> &items) {
+  items.clear();
+  std::vector<Group> groups;
+  std::map<int, int> group_of;
+  for (LaunchClass &k : c->classes) {
+    if (!group_of.count(k.np)) {
+      group_of[k.np] = (int)groups.size();
+      groups.push_back(Group{k.np, 0, 0});
+    }
+    k.group = group_of[k.np];
+  }
+  for (size_t g = 0; g < groups.size(); ++g) {
+    groups[g].first = (int64_t)items.size();
+    for (LaunchClass &k : c->classes) {
+      if (k.group != (int)g) continue;
+      std::vector<std::pair<int, SweepItem>> list;
+      for (const Family &fm : c->fams) {
+        if (&c->classes[fm.cls] != &k) continue;
+        const int C = k.C;
+        const int S = family_S(k, fm.n_a);
+        const int cost = fm.x_kind ? (int)((C * (int64_t)fm.n_a + kBlock - 1) / kBlock)
+                                   : ((fm.n_a + (kBlock / C) * S - 1) / ((kBlock / C) * S)) * S;
+        for (int kk = 0; kk < fm.m; ++kk)
+          for (int64_t t = 0; t < fm.tnodes; ++t) {
+            const int64_t base = fm.f_vel + kk * fm.comp_stride + fm.plane_off[t];
+            const int64_t fbb = fm.fb_vel + ((int64_t)kk * fm.tnodes + t) * fm.ntc;
+            for (int64_t tau0 = 0; tau0 < fm.ntc; tau0 += C) {
+              SweepItem item;
+              item.base = base;
+              item.fb = fbb + tau0;
+              item.desc = fm.desc;
+              item.tau0 = (int32_t)tau0;
+              item.count = (int32_t)std::min<int64_t>(C, fm.ntc - tau0);
+              item.C = (int16_t)(fm.x_kind ? 0 : C);
+              item.S = (int8_t)S;
+              item.xk = (int8_t)fm.x_kind;
+              list.push_back({cost, item});
+            }
+          }
       }
+      std::stable_sort(list.begin(), list.end(),
+                       [](const std::pair<int, SweepItem> &a, const std::pair<int, SweepItem> &b) {
+                         return a.first > b.first;
+                       });
+      k.first = (int64_t)items.size();
+      k.count = (int64_t)list.size();
+      for (const auto &ci : list) items.push_back(ci.second);
     }
+    groups[g].count = (int64_t)items.size() - groups[g].first;
   }
-  if (x_kind) {
-    // one window covers the whole row: (kBlock / C) * S >= n and the LDS tile
-    // fits in 48 KiB; prefer the smallest S with at most 32 segments per row
-    int best = -1;
-    for (int s = 1; s <= smax; s <<= 1) {
-      if (sweep_lds_bytes(prec, np, s, 1) > 49152 || (int64_t)kBlock * s < n) continue;
-      best = s;
-      if ((n + s - 1) / s <= 32) break;
-    }
-    S = best < 0 ? smax : best;
-    int P = std::min(kBlock, pow2_ceil((n + S - 1) / S));
-    C = kBlock / P;
-    return;
-  }
-  // strided axis: C consecutive chains per lane group, P = kBlock / C segments
-  C = (int)std::min<int64_t>(64, pow2_ceil((int)std::min<int64_t>(ntc, 64)));
-  C = std::max(C, 8);
-  int P = kBlock / C;
-  S = 1;
-  while (S < smax && P * S < n) S <<= 1;
+  c->groups = groups;
 }
 
 }  // namespace
@@ -580,10 +668,8 @@ pdg_status pdg_prepare(pdg_ctx *c, double dt, double theta, double omega, pdg_sc
   // ---- operator table: (instance, velocity, dt_sub in {dt, dt/2}) --------
   std::vector<OpEntry> ops;
   std::vector<SweepDesc> sdesc;
-  // (estimated cost, item) per launch group; cost = sequential cells per thread
-  std::vector<std::vector<std::pair<int, SweepItem>>> by_group;
-  std::map<std::vector<int>, int> group_of;
-  std::vector<Group> groups;
+  std::vector<Family> fams;
+  std::vector<LaunchClass> classes;
   for (size_t ii = 0; ii < c->inst.size(); ++ii) {
     const Instance &in = c->inst[ii];
     const int np = (int)in.np;
@@ -637,71 +723,55 @@ pdg_status pdg_prepare(pdg_ctx *c, double dt, double theta, double omega, pdg_sc
       }
       const int desc_index = (int)sdesc.size();
       sdesc.push_back(sd);
-      // work items: (k, transverse node, block of C chains)
-      const int64_t ntc = nc / in.n[ax];
-      int C = 64, S = 1;
-      choose_tile(prec, np, sd.n_a, ntc, sd.x_kind, C, S);
-      if (sd.x_kind && (int64_t)(kBlock / C) * S < sd.n_a) return PDG_EUNSUPPORTED;
-      std::vector<int> key = {np};
-      auto itg = group_of.find(key);
-      int gi;
-      if (itg == group_of.end()) {
-        gi = (int)groups.size();
-        group_of[key] = gi;
-        groups.push_back(Group{np, 0, 0, 0});
-        by_group.emplace_back();
-      } else {
-        gi = itg->second;
-      }
-      groups[gi].lds = std::max(groups[gi].lds, sweep_lds_bytes(prec, np, S, sd.x_kind));
-      // sequential cells per thread: a proxy of the workgroup's duration
-      const int windows = sd.x_kind ? 1 : (sd.n_a + (kBlock / C) * S - 1) / ((kBlock / C) * S);
-      const int cost = windows * S;
-      int64_t tnodes = 1;
-      for (int k = 0; k < dim - 1; ++k) tnodes *= np;
+      Family fm;
+      fm.desc = desc_index;
+      fm.np = np;
+      fm.x_kind = sd.x_kind;
+      fm.n_a = sd.n_a;
+      fm.m = in.d.m;
+      fm.ntc = nc / in.n[ax];
+      fm.tnodes = 1;
+      for (int k = 0; k < dim - 1; ++k) fm.tnodes *= np;
       int other[2] = {0, 0}, no = 0;
       for (int k = 0; k < dim; ++k)
         if (k != ax) other[no++] = k;
-      for (int k = 0; k < in.d.m; ++k)
-        for (int64_t t = 0; t < tnodes; ++t) {
-          // transverse node t -> plane offset
-          int64_t plane = 0;
-          int64_t rem = t;
-          for (int o = 0; o < no; ++o) {
-            int64_t jo = rem % np;
-            rem /= np;
-            int64_t ps = 1;
-            for (int kk = 0; kk < other[o]; ++kk) ps *= np;
-            plane += jo * ps;
-          }
-          const int64_t base = in.f_off + ((int64_t)(v * in.d.m + k) * in.nd + plane) * nc;
-          const int64_t fbb = in.fb_off + in.fb_vel_off[v] + ((int64_t)k * tnodes + t) * ntc;
-          for (int64_t tau0 = 0; tau0 < ntc; tau0 += C) {
-            SweepItem item;
-            item.base = base;
-            item.fb = fbb + tau0;
-            item.desc = desc_index;
-            item.tau0 = (int32_t)tau0;
-            item.count = (int32_t)std::min<int64_t>(C, ntc - tau0);
-            item.C = (int16_t)C;
-            item.S = (int8_t)S;
-            item.xk = (int8_t)sd.x_kind;
-            by_group[gi].push_back({cost, item});
-          }
+      for (int64_t t = 0; t < fm.tnodes; ++t) {
+        // transverse node t -> plane offset
+        int64_t plane = 0;
+        int64_t rem = t;
+        for (int o = 0; o < no; ++o) {
+          const int64_t jo = rem % np;
+          rem /= np;
+          int64_t ps = 1;
+          for (int kk = 0; kk < other[o]; ++kk) ps *= np;
+          plane += jo * ps;
         }
+        fm.plane_off.push_back(plane * nc);
+      }
+      fm.comp_stride = in.nd * nc;
+      fm.f_vel = in.f_off + (int64_t)v * in.d.m * in.nd * nc;
+      fm.fb_vel = in.fb_off + in.fb_vel_off[v];
+      fm.cls = -1;
+      for (size_t k = 0; k < classes.size(); ++k)
+        if (classes[k].np == np && classes[k].x_kind == sd.x_kind) fm.cls = (int)k;
+      if (fm.cls < 0) {
+        LaunchClass k;
+        std::memset(&k, 0, sizeof(k));
+        k.np = np;
+        k.x_kind = sd.x_kind;
+        fm.cls = (int)classes.size();
+        classes.push_back(k);
+      }
+      classes[fm.cls].chains += (int64_t)fm.m * fm.tnodes * fm.ntc;
+      classes[fm.cls].n_max = std::max(classes[fm.cls].n_max, fm.n_a);
+      fams.push_back(std::move(fm));
     }
   }
-  // longest-running workgroups first inside each launch
+  for (LaunchClass &k : classes) default_tile(k);
+  c->fams = std::move(fams);
+  c->classes = std::move(classes);
   std::vector<SweepItem> items;
-  for (size_t g = 0; g < groups.size(); ++g) {
-    std::stable_sort(by_group[g].begin(), by_group[g].end(),
-                     [](const std::pair<int, SweepItem> &a, const std::pair<int, SweepItem> &b) {
-                       return a.first > b.first;
-                     });
-    groups[g].first = (int64_t)items.size();
-    groups[g].count = (int64_t)by_group[g].size();
-    for (const auto &ci : by_group[g]) items.push_back(ci.second);
-  }
+  build_items(c, items);
 
   // ---- relax tables --------------------------------------------------------
   std::vector<RelaxDesc> rdesc;
@@ -800,7 +870,6 @@ pdg_status pdg_prepare(pdg_ctx *c, double dt, double theta, double omega, pdg_sc
     }
   PREP_TRY(hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking))
 #undef PREP_TRY
-  c->groups = groups;
   c->rgroups = rgroups;
   c->igroups = igroups;
   c->dt = dt;
@@ -819,11 +888,11 @@ namespace {
 pdg_status do_sweep(pdg_ctx *c, void *f, const double *fb_old, const double *fb_new, int dt_idx,
                     hipStream_t st) {
   for (const Group &g : c->groups) {
-    hipError_t e = launch_sweep(c->prec, g.np, g.lds, c->sitems.p + g.first, (int)g.count, c->sdesc.p, c->ops.p,
-                                dt_idx, f, fb_old, fb_new, c->stats.p + 2 * g.first, st);
+    hipError_t e = launch_sweep(c->prec, g.np, c->sitems.p + g.first, (int)g.count, c->sdesc.p, c->ops.p, dt_idx, f,
+                                fb_old, fb_new, c->stats.p + 2 * g.first, st);
     if (e != hipSuccess) {
       char what[96];
-      std::snprintf(what, sizeof(what), "launch_sweep(np=%d,lds=%d,items=%lld)", g.np, g.lds, (long long)g.count);
+      std::snprintf(what, sizeof(what), "launch_sweep(np=%d,items=%lld)", g.np, (long long)g.count);
       return from_hip_at(e, what);
     }
   }
@@ -947,6 +1016,129 @@ pdg_status pdg_step(pdg_ctx *c, void *f, const double *fb, int32_t n_steps, void
     c->last_stream = st;
   }
   return do_sweep(c, f, fb, fb, 1, st);
+}
+
+namespace {
+
+// Re-upload the item array after a tile change; grows the per-workgroup
+// statistics buffer if needed and drops the cached step graph.
+pdg_status upload_items(pdg_ctx *c, const std::vector<SweepItem> &items) {
+  hipError_t e = c->sitems.upload(items);
+  if (e != hipSuccess) return from_hip_at(e, "upload items");
+  if (c->stats.n < 2 * items.size()) {
+    std::vector<double> zeros(2 * items.size(), 0.0);
+    e = c->stats.upload(zeros);
+    if (e != hipSuccess) return from_hip_at(e, "upload stats");
+  }
+  if (c->gexec) (void)hipGraphExecDestroy(c->gexec);
+  c->gexec = nullptr;
+  c->g_f = nullptr;
+  c->g_fb = nullptr;
+  return PDG_OK;
+}
+
+bool tile_valid(const LaunchClass &k, int C, int S) {
+  if (C < 1 || C > kBlock || S < 1 || S > sweep_smax(k.np)) return false;
+  if (k.x_kind) return (int64_t)C * k.n_max < 65536 && S == 1;
+  return kBlock % C == 0;
+}
+
+}  // namespace
+
+pdg_status pdg_autotune(pdg_ctx *c, void *f, const double *fb, int32_t reps, void *stream) {
+  if (!c || !f || (c->fb_elems > 0 && !fb) || reps < 1) return PDG_EINVAL;
+  if (!c->prepared) return PDG_ESTATE;
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  HIP_TRY(hipEventCreate(&e0));
+  HIP_TRY(hipEventCreate(&e1));
+  std::vector<SweepItem> items;
+  pdg_status status = PDG_OK;
+  for (size_t ki = 0; ki < c->classes.size() && status == PDG_OK; ++ki) {
+    LaunchClass &k = c->classes[ki];
+    std::vector<std::pair<int, int>> cands;
+    if (k.x_kind) {
+      for (int C = 1; C <= 64; C <<= 1) cands.push_back({C, 1});
+    } else {
+      for (int C = 8; C <= 64; C <<= 1)
+        for (int S = 1; S <= sweep_smax(k.np); S <<= 1) cands.push_back({C, S});
+    }
+    int bestC = k.C, bestS = k.S;
+    float best = 1e30f;
+    for (const auto &cs : cands) {
+      if (!tile_valid(k, cs.first, cs.second)) continue;
+      k.C = cs.first;
+      k.S = cs.second;
+      build_items(c, items);
+      if ((status = upload_items(c, items)) != PDG_OK) break;
+      const Group &g = c->groups[k.group];
+      hipError_t e = hipSuccess;
+      for (int r = 0; r <= reps && e == hipSuccess; ++r) {
+        if (r == 1) e = hipEventRecord(e0, st);
+        if (e == hipSuccess)
+          e = launch_sweep(c->prec, g.np, c->sitems.p + k.first, (int)k.count, c->sdesc.p, c->ops.p, 0, f, fb, fb,
+                           c->stats.p + 2 * k.first, st);
+      }
+      if (e == hipSuccess) e = hipEventRecord(e1, st);
+      if (e == hipSuccess) e = hipEventSynchronize(e1);
+      float ms = 0.f;
+      if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+      if (e != hipSuccess) {
+        status = from_hip_at(e, "autotune timing");
+        break;
+      }
+      if (ms < best) {
+        best = ms;
+        bestC = cs.first;
+        bestS = cs.second;
+      }
+    }
+    k.C = bestC;
+    k.S = bestS;
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  build_items(c, items);
+  pdg_status s2 = upload_items(c, items);
+  return status != PDG_OK ? status : s2;
+}
+
+pdg_status pdg_get_tiles(const pdg_ctx *c, int32_t *n_classes, int32_t *tiles) {
+  if (!c || !n_classes) return PDG_EINVAL;
+  if (!c->prepared) return PDG_ESTATE;
+  if (tiles) {
+    for (size_t k = 0; k < c->classes.size() && (int32_t)k < *n_classes; ++k) {
+      tiles[4 * k + 0] = c->classes[k].np;
+      tiles[4 * k + 1] = c->classes[k].x_kind;
+      tiles[4 * k + 2] = c->classes[k].C;
+      tiles[4 * k + 3] = c->classes[k].S;
+    }
+  }
+  *n_classes = (int32_t)c->classes.size();
+  return PDG_OK;
+}
+
+pdg_status pdg_set_tiles(pdg_ctx *c, int32_t n_classes, const int32_t *tiles) {
+  if (!c || (n_classes > 0 && !tiles) || n_classes < 0) return PDG_EINVAL;
+  if (!c->prepared) return PDG_ESTATE;
+  for (int32_t i = 0; i < n_classes; ++i) {
+    bool found = false;
+    for (const LaunchClass &k : c->classes)
+      if (k.np == tiles[4 * i] && k.x_kind == tiles[4 * i + 1]) {
+        found = true;
+        if (!tile_valid(k, tiles[4 * i + 2], tiles[4 * i + 3])) return PDG_EINVAL;
+      }
+    if (!found) return PDG_EINVAL;
+  }
+  for (int32_t i = 0; i < n_classes; ++i)
+    for (LaunchClass &k : c->classes)
+      if (k.np == tiles[4 * i] && k.x_kind == tiles[4 * i + 1]) {
+        k.C = tiles[4 * i + 2];
+        k.S = tiles[4 * i + 3];
+      }
+  std::vector<SweepItem> items;
+  build_items(c, items);
+  return upload_items(c, items);
 }
 
 pdg_status pdg_last_refine_correction(const pdg_ctx *c, double *max_rel_correction) {

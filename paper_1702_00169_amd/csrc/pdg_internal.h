@@ -24,7 +24,7 @@ struct SweepDesc {
   int32_t nx;          // transverse decode: tau -> (tau % nx) + (tau / nx) * hi_stride
   int64_t hi_stride;
   int32_t op;          // operator-table row of dt_sub = dt; op + 1 is dt/2
-  int32_t x_kind;      // 1: chains along the contiguous axis (LDS-staged path)
+  int32_t x_kind;      // 1: chains along the contiguous axis
 };
 
 // One workgroup's share of a sweep: `count` consecutive chains (tau0 ..) of
@@ -35,9 +35,9 @@ struct SweepItem {
   int32_t desc;   // SweepDesc index
   int32_t tau0;
   int32_t count;  // chains of this item (<= C)
-  int16_t C;      // chains per workgroup; kBlock / C segments per chain window
-  int8_t S;       // cells per segment (<= sweep_smax(np))
-  int8_t xk;      // 1: LDS-staged path (chains along the contiguous axis)
+  int16_t C;      // strided chains: chains per workgroup (kBlock / C segments per window)
+  int8_t S;       // strided chains: cells per segment (<= sweep_smax(np))
+  int8_t xk;      // 1: chains along the contiguous axis (one cell per thread, wave scan)
 };
 
 // Largest segment length compiled for a node count (register budget).
@@ -97,8 +97,8 @@ enum Prec { kF64 = 0, kF32 = 1, kRefine = 2 };
 hipError_t launch_invert(OpEntry *ops, int n_ops, hipStream_t st);
 
 // Launch one sweep over items that share the node count np (any chain kind,
-// tile shape or instance); lds_bytes = largest LDS tile of the items.
-hipError_t launch_sweep(int prec, int np, int lds_bytes, const SweepItem *items, int n_items,
+// tile shape or instance).
+hipError_t launch_sweep(int prec, int np, const SweepItem *items, int n_items,
                         const SweepDesc *descs, const OpEntry *ops, int dt_idx, void *f, const double *fb_old,
                         const double *fb_new, double *stats, hipStream_t st);
 
@@ -111,6 +111,5 @@ hipError_t launch_inflow_eq(int nv, int m, const InflowDesc *items, int n_items,
 
 hipError_t launch_fill(double *p, int64_t n, double value, hipStream_t st);
 
-int sweep_lds_bytes(int prec, int np, int S, int x_kind);
 
 }  // namespace pdg

@@ -24,14 +24,15 @@
 // inflow.  The result is the block-triangular solve of the paper, with the
 // rounding order of the combine instead of cell after cell.
 //
-// Two staging paths share that arithmetic:
+// Two thread mappings share that arithmetic:
 //  * chains along a strided axis (y, z): a group of C consecutive chains
-//    reads consecutive addresses, so each thread loads its cells directly
-//    from HBM (C lanes per 8-byte row, fully coalesced);
-//  * chains along the contiguous axis x: the workgroup copies its C rows of
-//    all NP node planes into LDS with coalesced loads, threads read their
-//    segments from LDS in a thread-major layout (no bank conflicts on the
-//    read side), and results go back through LDS to coalesced stores.
+//    reads consecutive addresses, so each thread loads its S cells directly
+//    from HBM (C lanes per 8-byte row, fully coalesced) and the segment maps
+//    are combined through LDS;
+//  * chains along the contiguous axis x: one cell per thread with lanes in
+//    downwind order along the rows, so loads and stores are contiguous row
+//    segments; the segment maps (one cell each) are combined by a segmented
+//    Kogge-Stone scan inside each wave and a carry across waves and chunks.
 //
 // Relaxation (eq. collision_cn, Sec. 4.4): one thread per node reads the nv x m
 // values of that node (node-major layout: coalesced across threads), forms
@@ -155,6 +156,114 @@ struct CellOp<kRefine, NP> {
   }
 };
 
+// Chains along the contiguous axis: one cell per thread, lanes in downwind
+// order over the item's rows (rows of one family are contiguous in memory,
+// so every load and store is a coalesced row segment).  The inflow values
+// obey u_{l+1} = a u_l + beta_l with beta_l = theta (M f_l)_out +
+// (1 - theta) f_{l,out}; the chain head absorbs its boundary inflow
+// (beta += a u_b).  A segmented inclusive scan I_l = u_{l+1} runs inside each
+// wave (Kogge-Stone with the powers a^(2^s)), then across the four waves
+// and across 256-cell chunks through a carry.
+template <int PREC, int NP>
+__device__ __forceinline__ void sweep_rows(const SweepItem &it, const SweepDesc &d, const CellOp<PREC, NP> &op,
+                                           typename Pol<PREC>::St *__restrict__ f,
+                                           const double *__restrict__ fb_old, const double *__restrict__ fb_new,
+                                           typename Pol<PREC>::Rt (*wtot)[4], int (*wopen)[4], double &cmax,
+                                           double &ymax) {
+  using St = typename Pol<PREC>::St;
+  using Rt = typename Pol<PREC>::Rt;
+  constexpr int KCH = 4;  // 256-cell chunks whose loads are issued together
+  const Rt theta = op.theta;
+  const Rt omt = (Rt)1 - theta;
+  const Rt a = op.a;
+  Rt apow[7];  // a^(2^s)
+  apow[0] = a;
+#pragma unroll
+  for (int s = 1; s < 7; ++s) apow[s] = apow[s - 1] * apow[s - 1];
+  const int t = threadIdx.x;
+  const int lane = t & 63;
+  const int wv = t >> 6;
+  const int n = d.n_a;
+  const int total = it.count * n;  // < 2^16 (host), so the float quotient below is exact
+  const float inv_n = 1.0f / (float)n;
+  const bool rev = d.cell_step < 0;
+  const int64_t rowbase = it.base + d.plane0 + (int64_t)it.tau0 * d.hi_stride;
+  // a^(lane+1) by binary powering: weight of the wave's carry at this lane
+  Rt alane = 1;
+  {
+    const int e = lane + 1;
+#pragma unroll
+    for (int s = 0; s < 7; ++s)
+      if (e & (1 << s)) alane *= apow[s];
+  }
+  Rt carry = 0;  // I of the last element of the previous chunk
+  int par = 0;
+  for (int c0 = 0; c0 < total; c0 += KCH * kBlock) {
+    // issue the loads of KCH chunks before any of them is used
+    Rt fv[KCH][NP];
+    int pidx[KCH], row[KCH], pos[KCH];
+#pragma unroll
+    for (int k = 0; k < KCH; ++k) {
+      const int e = c0 + k * kBlock + t;
+      const bool valid = e < total;
+      const int pi = rev ? total - 1 - e : e;  // physical flat index (row-major rows x n)
+      const int r = valid ? (int)(((float)pi + 0.5f) * inv_n) : 0;
+      const int x = pi - r * n;
+      pidx[k] = valid ? pi : -1;
+      row[k] = r;
+      pos[k] = rev ? n - 1 - x : x;  // downwind position in the chain
+#pragma unroll
+      for (int q = 0; q < NP; ++q) fv[k][q] = valid ? (Rt)f[rowbase + q * d.plane_step + pi] : (Rt)0;
+    }
+#pragma unroll
+    for (int k = 0; k < KCH; ++k, par ^= 1) {
+      if (c0 + k * kBlock >= total) break;  // uniform across the block
+      const bool valid = pidx[k] >= 0;
+      const int l = pos[k];
+      const int r = row[k];
+      Rt y[NP];
+      op.solve(fv[k], y, cmax, ymax);
+      const Rt fo = fv[k][NP - 1];
+      Rt beta = valid ? theta * y[NP - 1] + omt * fo : (Rt)0;
+      Rt ub = 0;
+      if (valid && l == 0) {
+        ub = theta * (Rt)fb_new[it.fb + r] + omt * (Rt)fb_old[it.fb + r];
+        beta = fma(a, ub, beta);
+      }
+      // segmented scan inside the wave
+      const int kw = l < lane ? l : lane;  // lanes back to the segment start within the wave
+      Rt I = beta;
+#pragma unroll
+      for (int s = 0; s < 6; ++s) {
+        const int dd = 1 << s;
+        const Rt up = __shfl_up(I, dd, 64);
+        if (kw >= dd) I = fma(apow[s], up, I);
+      }
+      if (lane == 63) {
+        wtot[par][wv] = I;
+        wopen[par][wv] = (l > 63) ? 1 : 0;  // segment reaches back before the wave
+      }
+      __syncthreads();
+      // carry into each wave, then into the next chunk
+      Rt cin = carry;
+      Rt cw = carry;
+#pragma unroll
+      for (int w = 0; w < 4; ++w) {
+        if (w == wv) cin = cw;
+        cw = wopen[par][w] ? fma(apow[6], cw, wtot[par][w]) : wtot[par][w];
+      }
+      if (l > lane) I = fma(alane, cin, I);
+      const Rt prev = __shfl_up(I, 1, 64);
+      const Rt u = (l == 0) ? ub : (lane > 0 ? prev : cin);
+      if (valid) {
+#pragma unroll
+        for (int q = 0; q < NP; ++q) f[rowbase + q * d.plane_step + pidx[k]] = (St)fma(op.g[q], u, y[q]);
+      }
+      carry = cw;
+    }
+  }
+}
+
 template <int PREC, int NP, int SMAX>
 __global__ __launch_bounds__(kBlock) void sweep_kernel(const SweepItem *__restrict__ items,
                                                       const SweepDesc *__restrict__ descs,
@@ -167,10 +276,6 @@ __global__ __launch_bounds__(kBlock) void sweep_kernel(const SweepItem *__restri
   using Rt = typename Pol<PREC>::Rt;
   __shared__ Rt xa[2][kBlock];
   __shared__ Rt xb[2][kBlock];
-  extern __shared__ __align__(16) unsigned char lds_raw[];
-  St *tile = reinterpret_cast<St *>(lds_raw);
-  constexpr int kRow = kBlock + 1;  // padded LDS row (elements)
-
   const SweepItem it = items[blockIdx.x];
   const SweepDesc d = descs[it.desc];
   CellOp<PREC, NP> op;
@@ -178,43 +283,27 @@ __global__ __launch_bounds__(kBlock) void sweep_kernel(const SweepItem *__restri
   const Rt theta = op.theta;
   const Rt omt = (Rt)1 - theta;
 
-  const int C = it.C;       // chains per workgroup (lanes per segment row)
-  const int S = it.S;       // cells per segment, <= SMAX
-  const bool xk = it.xk != 0;
   const int t = threadIdx.x;
+  double cmax = 0.0, ymax = 0.0;
+
+  if (it.xk) {
+    __shared__ Rt wtot[2][4];
+    __shared__ int wopen[2][4];
+    sweep_rows<PREC, NP>(it, d, op, f, fb_old, fb_new, wtot, wopen, cmax, ymax);
+  } else {
+  // chains along a strided axis: thread (c, p) owns segment p of chain c
+  const int C = it.C;        // chains per workgroup
+  const int S = it.S;        // cells per segment, <= SMAX
   const int P = kBlock / C;  // segments per chain window
   const int c = t % C;
   const int p = t / C;
   const bool active = c < it.count;
   const int n = d.n_a;
   const int window = P * S;
-  double cmax = 0.0, ymax = 0.0;
-
   Rt u = 0;
   if (active) u = theta * (Rt)fb_new[it.fb + c] + omt * (Rt)fb_old[it.fb + c];
-
   const int tau = it.tau0 + c;
   const int64_t chain = it.base + (int64_t)(tau % d.nx) + (int64_t)(tau / d.nx) * d.hi_stride + d.cell0 + d.plane0;
-
-  if (xk) {
-    // cooperative coalesced copy of count rows x n cells x NP planes into LDS
-    // (one window covers a whole row: P * S >= n)
-    const int total = it.count * n;
-#pragma unroll
-    for (int q = 0; q < NP; ++q) {
-      const St *src = f + it.base + d.plane0 + q * d.plane_step + (int64_t)it.tau0 * d.hi_stride;
-      for (int e = t; e < total; e += kBlock) {
-        const int r = e / n;
-        const int x = e - r * n;
-        const int l = d.cell_step > 0 ? x : n - 1 - x;
-        const int ps = l / S;
-        const int s = l - ps * S;
-        tile[(q * S + s) * kRow + r + C * ps] = src[e];
-      }
-    }
-    __syncthreads();
-  }
-
   int wpar = 0;
   for (int w0 = 0; w0 < n; w0 += window, wpar ^= 1) {
     const int lb = w0 + p * S;
@@ -226,12 +315,7 @@ __global__ __launch_bounds__(kBlock) void sweep_kernel(const SweepItem *__restri
       Rt fv[NP];
       if (s < cnt) {
 #pragma unroll
-        for (int q = 0; q < NP; ++q) {
-          if (xk)
-            fv[q] = (Rt)tile[(q * S + s) * kRow + t];
-          else
-            fv[q] = (Rt)f[chain + (int64_t)(lb + s) * d.cell_step + q * d.plane_step];
-        }
+        for (int q = 0; q < NP; ++q) fv[q] = (Rt)f[chain + (int64_t)(lb + s) * d.cell_step + q * d.plane_step];
       } else {
 #pragma unroll
         for (int q = 0; q < NP; ++q) fv[q] = 0;
@@ -265,10 +349,7 @@ __global__ __launch_bounds__(kBlock) void sweep_kernel(const SweepItem *__restri
         for (int q = 0; q < NP; ++q) {
           const Rt xv = fma(op.g[q], uu, y[s][q]);
           if (q == NP - 1) xo = xv;
-          if (xk)
-            tile[(q * S + s) * kRow + t] = (St)xv;
-          else
-            f[chain + (int64_t)(lb + s) * d.cell_step + q * d.plane_step] = (St)xv;
+          f[chain + (int64_t)(lb + s) * d.cell_step + q * d.plane_step] = (St)xv;
         }
         uu = theta * xo + omt * fo[s];
       }
@@ -276,21 +357,6 @@ __global__ __launch_bounds__(kBlock) void sweep_kernel(const SweepItem *__restri
     u = unext;
   }
 
-  if (xk) {
-    __syncthreads();
-    const int total = it.count * n;
-#pragma unroll
-    for (int q = 0; q < NP; ++q) {
-      St *dst = f + it.base + d.plane0 + q * d.plane_step + (int64_t)it.tau0 * d.hi_stride;
-      for (int e = t; e < total; e += kBlock) {
-        const int r = e / n;
-        const int x = e - r * n;
-        const int l = d.cell_step > 0 ? x : n - 1 - x;
-        const int ps = l / S;
-        const int s = l - ps * S;
-        dst[e] = tile[(q * S + s) * kRow + r + C * ps];
-      }
-    }
   }
 
   if (PREC == kRefine) {
@@ -518,25 +584,25 @@ __global__ void fill_kernel(double *p, int64_t n, double value) {
 // dispatch
 // ---------------------------------------------------------------------------
 template <int PREC, int NP>
-hipError_t go_sweep(int lds, const SweepItem *items, int n_items, const SweepDesc *descs, const OpEntry *ops,
+hipError_t go_sweep(const SweepItem *items, int n_items, const SweepDesc *descs, const OpEntry *ops,
                     int dt_idx, void *f, const double *fb_old, const double *fb_new, double *stats,
                     hipStream_t st) {
   using St = typename Pol<PREC>::St;
   constexpr int SMAX = sweep_smax(NP);
-  hipLaunchKernelGGL((sweep_kernel<PREC, NP, SMAX>), dim3(n_items), dim3(kBlock), (size_t)lds, st, items, descs, ops,
+  hipLaunchKernelGGL((sweep_kernel<PREC, NP, SMAX>), dim3(n_items), dim3(kBlock), 0, st, items, descs, ops,
                      dt_idx, static_cast<St *>(f), fb_old, fb_new, stats);
   return hipGetLastError();
 }
 
 template <int PREC>
-hipError_t go_sweep_np(int np, int lds, const SweepItem *items, int n_items, const SweepDesc *descs,
+hipError_t go_sweep_np(int np, const SweepItem *items, int n_items, const SweepDesc *descs,
                        const OpEntry *ops, int dt_idx, void *f, const double *fb_old, const double *fb_new,
                        double *stats, hipStream_t st) {
   switch (np) {
-    case 2: return go_sweep<PREC, 2>(lds, items, n_items, descs, ops, dt_idx, f, fb_old, fb_new, stats, st);
-    case 3: return go_sweep<PREC, 3>(lds, items, n_items, descs, ops, dt_idx, f, fb_old, fb_new, stats, st);
-    case 4: return go_sweep<PREC, 4>(lds, items, n_items, descs, ops, dt_idx, f, fb_old, fb_new, stats, st);
-    case 5: return go_sweep<PREC, 5>(lds, items, n_items, descs, ops, dt_idx, f, fb_old, fb_new, stats, st);
+    case 2: return go_sweep<PREC, 2>(items, n_items, descs, ops, dt_idx, f, fb_old, fb_new, stats, st);
+    case 3: return go_sweep<PREC, 3>(items, n_items, descs, ops, dt_idx, f, fb_old, fb_new, stats, st);
+    case 4: return go_sweep<PREC, 4>(items, n_items, descs, ops, dt_idx, f, fb_old, fb_new, stats, st);
+    case 5: return go_sweep<PREC, 5>(items, n_items, descs, ops, dt_idx, f, fb_old, fb_new, stats, st);
     default: return hipErrorInvalidValue;
   }
 }
@@ -595,22 +661,16 @@ hipError_t launch_invert(OpEntry *ops, int n_ops, hipStream_t st) {
   return hipGetLastError();
 }
 
-hipError_t launch_sweep(int prec, int np, int lds_bytes, const SweepItem *items, int n_items,
+hipError_t launch_sweep(int prec, int np, const SweepItem *items, int n_items,
                         const SweepDesc *descs, const OpEntry *ops, int dt_idx, void *f, const double *fb_old,
                         const double *fb_new, double *stats, hipStream_t st) {
   if (n_items <= 0) return hipSuccess;
   switch (prec) {
-    case kF64: return go_sweep_np<kF64>(np, lds_bytes, items, n_items, descs, ops, dt_idx, f, fb_old, fb_new, stats, st);
-    case kF32: return go_sweep_np<kF32>(np, lds_bytes, items, n_items, descs, ops, dt_idx, f, fb_old, fb_new, stats, st);
-    case kRefine: return go_sweep_np<kRefine>(np, lds_bytes, items, n_items, descs, ops, dt_idx, f, fb_old, fb_new, stats, st);
+    case kF64: return go_sweep_np<kF64>(np, items, n_items, descs, ops, dt_idx, f, fb_old, fb_new, stats, st);
+    case kF32: return go_sweep_np<kF32>(np, items, n_items, descs, ops, dt_idx, f, fb_old, fb_new, stats, st);
+    case kRefine: return go_sweep_np<kRefine>(np, items, n_items, descs, ops, dt_idx, f, fb_old, fb_new, stats, st);
     default: return hipErrorInvalidValue;
   }
-}
-
-int sweep_lds_bytes(int prec, int np, int S, int x_kind) {
-  if (!x_kind) return 0;
-  const int es = prec == kF32 ? 4 : 8;
-  return np * S * (kBlock + 1) * es;
 }
 
 hipError_t launch_relax(int prec, int nv, int m, const RelaxItem *items, int n_items, const RelaxDesc *descs,

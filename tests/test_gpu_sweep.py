@@ -103,3 +103,23 @@ def test_sweep_tile_shapes_agree(lib, monkeypatch):
         monkeypatch.setenv("PDG_TILE", tile)
         (l2, mx), _ = _run_case(lib, torch, case, 0, 0.5, False, seed=5)
         assert l2 <= 1e-12 and mx <= 1e-11, tile
+
+
+def test_autotuned_tiles_solve_the_same_system(lib):
+    """The autotuner only changes the work decomposition."""
+    torch = pytest.importorskip("torch")
+    case = ("3d_9x7x13_d2", 3, (9, 7, 13), 2, 1.0, 1)
+    inst = _instance(case)
+    prob = lib.Problem([inst_dict(inst)])
+    prob.prepare(0.05)
+    scratch = torch.zeros(prob.layout["f_elems"], dtype=torch.float64, device="cuda")
+    fb = torch.ones(prob.layout["fb_elems"], dtype=torch.float64, device="cuda")
+    tiles = prob.autotune(scratch, fb, reps=1)
+    assert {(t["np"], t["x_kind"]) for t in tiles} == {(3, 0), (3, 1)}
+    prob.set_tiles(tiles)
+    with pytest.raises(lib.PdgError):
+        prob.set_tiles([dict(np=3, x_kind=0, C=7, S=1)])
+    assert prob.tiles() == tiles
+    prob.close()
+    (l2, mx), _ = _run_case(lib, torch, case, 0, 0.5, False, seed=8)
+    assert l2 <= 1e-12 and mx <= 1e-11
