@@ -500,7 +500,9 @@ __device__ inline void equilibrium(const RelaxDesc &d, const double (&w)[M], dou
   }
 }
 
-// mode 0: relax (w from f);  mode 1: f = f^eq(w_in)
+// mode 0: relax (w from f);  mode 1: f = f^eq(w_in).  The flux of one axis
+// at a time is formed and the velocities along that axis are updated at once,
+// so the n_v x m equilibrium values never live in registers together.
 template <int PREC, int NV, int M>
 __global__ __launch_bounds__(kBlock) void relax_kernel(const RelaxItem *__restrict__ items,
                                                       const RelaxDesc *__restrict__ descs,
@@ -512,6 +514,8 @@ __global__ __launch_bounds__(kBlock) void relax_kernel(const RelaxItem *__restri
   const RelaxDesc d = descs[it.desc];
   const int64_t nodes = d.nodes;
   St *fi = f + d.f_base;
+  const double inv_nv = 1.0 / NV;
+  const double h2l = 0.5 / d.lambda;
   for (int64_t node = it.node0 + threadIdx.x; node < it.node0 + it.count; node += kBlock) {
     double w[M];
     double fv[NV][M];
@@ -536,16 +540,28 @@ __global__ __launch_bounds__(kBlock) void relax_kernel(const RelaxItem *__restri
     } else {
 #pragma unroll
       for (int k = 0; k < M; ++k) w[k] = w_in[d.w_base + (int64_t)k * nodes + node];
+#pragma unroll
+      for (int i = 0; i < NV; ++i)
+#pragma unroll
+        for (int k = 0; k < M; ++k) fv[i][k] = 0.0;
     }
-    double fe[NV][M];
-    equilibrium<NV, M>(d, w, fe);
 #pragma unroll
-    for (int i = 0; i < NV; ++i)
+    for (int a = 0; a < 3; ++a) {
+      if (a >= d.dim) break;
+      double q[M];
+      flux_dir<M>(d, w, a, q);
 #pragma unroll
-      for (int k = 0; k < M; ++k) {
-        const double nv = (mode == 0) ? fma(omega, fe[i][k] - fv[i][k], fv[i][k]) : fe[i][k];
-        fi[(int64_t)(i * M + k) * nodes + node] = (St)nv;
+      for (int i = 0; i < NV; ++i) {
+        if (d.axis[i] != a) continue;
+        const double sg = d.sign[i] * h2l;
+#pragma unroll
+        for (int k = 0; k < M; ++k) {
+          const double fe = fma(sg, q[k], w[k] * inv_nv);
+          const double nv = (mode == 0) ? fma(omega, fe - fv[i][k], fv[i][k]) : fe;
+          fi[(int64_t)(i * M + k) * nodes + node] = (St)nv;
+        }
       }
+    }
     if (w_out != nullptr) {
 #pragma unroll
       for (int k = 0; k < M; ++k) w_out[d.w_base + (int64_t)k * nodes + node] = w[k];
