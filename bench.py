@@ -95,13 +95,15 @@ def traffic_for(workload, prec_name):
     return ent.get("bytes_per_launch")
 
 
-def measure(pdg, torch, wl, prec, steps, warmup, reps, keep_state=False, autotune=True):
+def measure(pdg, torch, wl, prec, steps, warmup, reps, keep_state=False, autotune=True, tiles=None):
     insts = wl.instances
     prob = pdg.Problem([inst_dict(i) for i in insts])
     prob.prepare(wl.dt, theta=wl.theta, omega=wl.omega, scheme=pdg.PDG_STRANG_COLLAPSED, precision=prec)
     dtype = torch.float32 if prec == pdg.PDG_FP32 else torch.float64
     f, fb, w_t = initial_state(pdg, prob, insts, torch, dtype)
-    if autotune:
+    if tiles:
+        prob.set_tiles(tiles)
+    elif autotune:
         # tile search on the state buffer itself, then restore the initial state
         prob.autotune(f, fb, reps=3)
         prob.equilibrium(w_t, f)
@@ -206,9 +208,11 @@ def main():
     ap.add_argument("--no-compare", action="store_true", help="skip the other precisions")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-autotune", action="store_true", help="keep the default tiles")
+    ap.add_argument("--tiles", default=None,
+                    help="JSON list of tiles ({np, x_kind, C, S}) to apply instead of autotuning (main precision)")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--copy-probe-mib", type=int, default=0,
-                    help="also run a plain device copy of this size (counter calibration)")
+                    help="size of the plain device copy (bandwidth reference and counter calibration)")
     args = ap.parse_args()
 
     if args.gpus != 1:
@@ -229,18 +233,25 @@ def main():
         print(f"[bench] {args.workload} {PREC_NAMES[p]}: {args.warmup} warm-up + {args.steps} timed steps",
               file=sys.stderr, flush=True)
         results[p], states[p] = measure(pdg, torch, wl, p, args.steps, args.warmup, args.reps, keep_state=compare,
-                                        autotune=not args.no_autotune)
+                                        autotune=not args.no_autotune,
+                                        tiles=json.loads(args.tiles) if args.tiles and p == prec_main else None)
         print(f"[bench]   {results[p]['value']:.4e} DoF/s, sweep {results[p]['sweep_us']:.1f} us "
               f"({results[p]['sweep_gbs']:.0f} GB/s), relax {results[p]['relax_us']:.1f} us", file=sys.stderr,
               flush=True)
-    if args.copy_probe_mib > 0:
-        x = torch.empty(args.copy_probe_mib * 2 ** 20 // 8, dtype=torch.float64, device="cuda")
-        y = torch.empty_like(x)
-        x.fill_(1.0)
-        for _ in range(3):
-            y.copy_(x)
-        torch.cuda.synchronize()
-        del x, y
+    # a plain device copy of the state's size: the practical streaming ceiling
+    copy_mib = args.copy_probe_mib or max(256, min(4096, results[prec_main]["bytes_per_sweep"] // 2 // 2 ** 20))
+    x = torch.empty(copy_mib * 2 ** 20 // 8, dtype=torch.float64, device="cuda")
+    y = torch.empty_like(x)
+    x.fill_(1.0)
+    y.copy_(x)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(5):
+        y.copy_(x)
+    e1.record()
+    torch.cuda.synchronize()
+    copy_gbs = 2 * x.numel() * 8 * 5 / (e0.elapsed_time(e1) * 1e-3) / 1e9
+    del x, y
 
     main_res = results[prec_main]
     prec_report = {}
@@ -263,7 +274,8 @@ def main():
     roof = {"bound": "hbm", "achieved": main_res["sweep_gbs"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": main_res["sweep_gbs"] / HBM_PEAK_GBS, "traffic": traffic,
             "kernel": "sweep_kernel", "algorithmic_bytes_per_launch": main_res["bytes_per_sweep"],
-            "launch_us": main_res["sweep_us"]}
+            "launch_us": main_res["sweep_us"], "device_copy_gbs": copy_gbs,
+            "step_gbs_at_32B_per_dof": main_res["value"] * 4 * (4 if prec_main == pdg.PDG_FP32 else 8) / 1e9}
     inst0 = wl.instances[0]
     config = {"workload": f"{args.workload}: {wl.description}", "n_dof": wl.n_dof,
               "instances": len(wl.instances), "cells": list(inst0.n) if len(wl.instances) == 1 else "per instance",

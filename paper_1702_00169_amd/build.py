@@ -23,14 +23,18 @@ def _hipcc():
     return shutil.which("hipcc") or "/opt/rocm/bin/hipcc"
 
 
-def build(verbose=False, jobs=2):
-    """Compile every source and link the shared library; raises on failure."""
+def build(verbose=False, jobs=2, out=None, defines=()):
+    """Compile every source and link the shared library; raises on failure.
+
+    ``out`` and ``defines`` (e.g. ``["PDG_NONTEMPORAL=1"]``) build a variant
+    library elsewhere for comparisons; the default builds ``_lib/libpdg.so``."""
     os.makedirs(LIBDIR, exist_ok=True)
+    target = out or LIB
     objs = []
     procs = []
     for src in SOURCES:
         obj = os.path.join(LIBDIR, os.path.splitext(src)[0] + ".o")
-        cmd = [_hipcc()] + HIP_FLAGS + ["-c", os.path.join(CSRC, src), "-o", obj]
+        cmd = [_hipcc()] + HIP_FLAGS + ["-D" + d for d in defines] + ["-c", os.path.join(CSRC, src), "-o", obj]
         if src.endswith(".cpp"):
             cmd[1:1] = ["-x", "hip"]
         procs.append((cmd, subprocess.Popen(cmd, stdout=subprocess.PIPE, stderr=subprocess.STDOUT, text=True)))
@@ -45,16 +49,16 @@ def build(verbose=False, jobs=2):
             failed = True
     if failed:
         raise RuntimeError("HIP compilation failed")
-    tmp = LIB + ".tmp"
+    tmp = target + ".tmp"
     cmd = [_hipcc(), "--offload-arch=gfx950", "-shared", "-fPIC", "-o", tmp] + objs
     res = subprocess.run(cmd, stdout=subprocess.PIPE, stderr=subprocess.STDOUT, text=True)
     if res.returncode != 0:
         sys.stderr.write(res.stdout)
         raise RuntimeError("link failed")
-    os.replace(tmp, LIB)
+    os.replace(tmp, target)
     for obj in objs:
         os.remove(obj)
-    return LIB
+    return target
 
 
 if __name__ == "__main__":

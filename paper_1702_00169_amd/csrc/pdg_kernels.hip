@@ -43,8 +43,31 @@
 
 #include "pdg_internal.h"
 
+#ifndef PDG_NONTEMPORAL
+#define PDG_NONTEMPORAL 0
+#endif
+
 namespace pdg {
 namespace {
+
+// State traffic: every value is read once and written once per kernel, so
+// the loads and stores may carry the streaming (non-temporal) hint.
+template <class T>
+__device__ __forceinline__ T ld_state(const T *p) {
+#if PDG_NONTEMPORAL
+  return __builtin_nontemporal_load(p);
+#else
+  return *p;
+#endif
+}
+template <class T>
+__device__ __forceinline__ void st_state(T *p, T v) {
+#if PDG_NONTEMPORAL
+  __builtin_nontemporal_store(v, p);
+#else
+  *p = v;
+#endif
+}
 
 template <int PREC>
 struct Pol;
@@ -213,7 +236,7 @@ __device__ __forceinline__ void sweep_rows(const SweepItem &it, const SweepDesc 
       row[k] = r;
       pos[k] = rev ? n - 1 - x : x;  // downwind position in the chain
 #pragma unroll
-      for (int q = 0; q < NP; ++q) fv[k][q] = valid ? (Rt)f[rowbase + q * d.plane_step + pi] : (Rt)0;
+      for (int q = 0; q < NP; ++q) fv[k][q] = valid ? (Rt)ld_state(f + rowbase + q * d.plane_step + pi) : (Rt)0;
     }
 #pragma unroll
     for (int k = 0; k < KCH; ++k, par ^= 1) {
@@ -257,7 +280,7 @@ __device__ __forceinline__ void sweep_rows(const SweepItem &it, const SweepDesc 
       const Rt u = (l == 0) ? ub : (lane > 0 ? prev : cin);
       if (valid) {
 #pragma unroll
-        for (int q = 0; q < NP; ++q) f[rowbase + q * d.plane_step + pidx[k]] = (St)fma(op.g[q], u, y[q]);
+        for (int q = 0; q < NP; ++q) st_state(f + rowbase + q * d.plane_step + pidx[k], (St)fma(op.g[q], u, y[q]));
       }
       carry = cw;
     }
@@ -315,7 +338,7 @@ __global__ __launch_bounds__(kBlock) void sweep_kernel(const SweepItem *__restri
       Rt fv[NP];
       if (s < cnt) {
 #pragma unroll
-        for (int q = 0; q < NP; ++q) fv[q] = (Rt)f[chain + (int64_t)(lb + s) * d.cell_step + q * d.plane_step];
+        for (int q = 0; q < NP; ++q) fv[q] = (Rt)ld_state(f + chain + (int64_t)(lb + s) * d.cell_step + q * d.plane_step);
       } else {
 #pragma unroll
         for (int q = 0; q < NP; ++q) fv[q] = 0;
@@ -349,7 +372,7 @@ __global__ __launch_bounds__(kBlock) void sweep_kernel(const SweepItem *__restri
         for (int q = 0; q < NP; ++q) {
           const Rt xv = fma(op.g[q], uu, y[s][q]);
           if (q == NP - 1) xo = xv;
-          f[chain + (int64_t)(lb + s) * d.cell_step + q * d.plane_step] = (St)xv;
+          st_state(f + chain + (int64_t)(lb + s) * d.cell_step + q * d.plane_step, (St)xv);
         }
         uu = theta * xo + omt * fo[s];
       }
@@ -523,7 +546,7 @@ __global__ __launch_bounds__(kBlock) void relax_kernel(const RelaxItem *__restri
 #pragma unroll
       for (int i = 0; i < NV; ++i)
 #pragma unroll
-        for (int k = 0; k < M; ++k) fv[i][k] = (double)fi[(int64_t)(i * M + k) * nodes + node];
+        for (int k = 0; k < M; ++k) fv[i][k] = (double)ld_state(fi + (int64_t)(i * M + k) * nodes + node);
 #pragma unroll
       for (int k = 0; k < M; ++k) {
         // Neumaier compensated sum over velocities, fixed order
@@ -558,7 +581,7 @@ __global__ __launch_bounds__(kBlock) void relax_kernel(const RelaxItem *__restri
         for (int k = 0; k < M; ++k) {
           const double fe = fma(sg, q[k], w[k] * inv_nv);
           const double nv = (mode == 0) ? fma(omega, fe - fv[i][k], fv[i][k]) : fe;
-          fi[(int64_t)(i * M + k) * nodes + node] = (St)nv;
+          st_state(fi + (int64_t)(i * M + k) * nodes + node, (St)nv);
         }
       }
     }
