@@ -270,11 +270,12 @@ def main():
         prec_report["fp64"]["rel_err_note"] = ("fp64 matches the CPU oracle to <= 1e-12 in the parity tests; "
                                                "the other precisions are compared with it after the same steps")
 
-    traffic = traffic_for(args.workload, PREC_NAMES[prec_main])
+    traffic = traffic_for(args.workload, PREC_NAMES[prec_main])  # HBM bytes per sweep launch, or None
     roof = {"bound": "hbm", "achieved": main_res["sweep_gbs"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": main_res["sweep_gbs"] / HBM_PEAK_GBS, "traffic": traffic,
             "kernel": "sweep_kernel", "algorithmic_bytes_per_launch": main_res["bytes_per_sweep"],
             "launch_us": main_res["sweep_us"], "device_copy_gbs": copy_gbs,
+            "traffic_over_algorithmic": (traffic / main_res["bytes_per_sweep"]) if traffic else None,
             "step_gbs_at_32B_per_dof": main_res["value"] * 4 * (4 if prec_main == pdg.PDG_FP32 else 8) / 1e9}
     inst0 = wl.instances[0]
     config = {"workload": f"{args.workload}: {wl.description}", "n_dof": wl.n_dof,
