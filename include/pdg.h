@@ -79,9 +79,16 @@ typedef enum {
 } pdg_feq_kind;
 
 typedef enum {
-  PDG_LIE = 0,             /* [T(dt) C]^N */
-  PDG_STRANG = 1,          /* [T(dt/2) C T(dt/2)]^N  (M_2, Sec. 3.2) */
-  PDG_STRANG_COLLAPSED = 2 /* T(dt/2) C [T(dt) C]^(N-1) T(dt/2)  (Sec. 5.1) */
+  PDG_LIE = 0,              /* [T(dt) C(dt)]^N */
+  PDG_STRANG = 1,           /* [T(dt/2) C(dt) T(dt/2)]^N  (M_2, Sec. 3.2) */
+  PDG_STRANG_COLLAPSED = 2, /* T(dt/2) C [T(dt) C]^(N-1) T(dt/2)  (Sec. 5.1) */
+  PDG_KIN = 3,              /* [M_2^kin(dt)]^N, M_2^kin(h) = T(h/4) C(h/2) T(h/2) C(h/2) T(h/4)
+                               (Sec. 3.2: second order also as tau -> 0) */
+  PDG_KIN4 = 4              /* [M_2^kin(g1 dt) M_2^kin(g2 dt) M_2^kin(g1 dt)]^N, triple-jump
+                               coefficients g1 = 1/(2 - 2^(1/3)), g2 = 1 - 2 g1: a fourth-order
+                               palindromic composition (Sec. 3.2 raises the order this way).
+                               The negative middle stage makes it only conditionally stable
+                               on the strongly damped upwind modes: use small dt. */
 } pdg_scheme;
 
 /* One independent kinetic problem.  The equilibrium (Sec. 2: P f^eq = P f and
@@ -142,13 +149,16 @@ pdg_status pdg_topo_levels(int32_t n_nodes, int64_t n_edges, const int32_t *src,
 pdg_status pdg_line_operator(const pdg_ctx *c, int32_t inst, int32_t vel, double *gamma, double *kappa);
 
 /* Prepare the time step (Sec. 3.2): for every instance, velocity and
- * sub-step size dt_sub in {dt, dt/2}, build on the host in binary64 the
+ * transport sub-step dt_sub of the scheme (always dt and dt/2; also dt/4 for
+ * PDG_KIN; g dt/4 and g dt/2 for both triple-jump g for PDG_KIN4), build on
+ * the host in binary64 the
  * one-dimensional cell blocks A = I + theta dt_sub Gamma_{L<-L} and
  * B = I - (1-theta) dt_sub Gamma_{L<-L} of eq. DG_reduit, invert A on the device
  * in binary64 (Gauss-Jordan with partial pivoting, PDG_ESINGULAR on a pivot
  * below 1e-300 times the block norm) and keep binary64 and binary32 copies.
- * omega is the collision factor of eq. collision_cn (2 dt/(2 tau + dt); 2 is
- * tau = 0).  Allocates the context's device tables; synchronises `stream`.
+ * omega is the collision factor of eq. collision_cn over dt (2 dt/(2 tau + dt);
+ * 2 is tau = 0); collisions over other sub-steps h use 2h/(2 tau + h).
+ * Allocates the context's device tables; synchronises `stream`.
  * theta in (0, 1], dt finite and non-zero (negative dt runs time backwards). */
 pdg_status pdg_prepare(pdg_ctx *c, double dt, double theta, double omega, pdg_scheme scheme,
                        pdg_precision prec, void *stream);
@@ -169,7 +179,7 @@ pdg_status pdg_inflow_equilibrium(pdg_ctx *c, const double *w_inflow, double *fb
  *                              + dt (theta b(fb_new) + (1-theta) b(fb_old))
  * cell by cell in downwind order.  fb_old/fb_new: inflow data at the old and
  * new time (the same pointer for time-independent data).  PDG_ESTATE if
- * dt_sub was not prepared. */
+ * dt_sub is not one of the prepared sub-steps (bitwise). */
 pdg_status pdg_transport_sweep(pdg_ctx *c, void *f, const double *fb_old, const double *fb_new,
                                double dt_sub, void *stream);
 
@@ -179,8 +189,9 @@ pdg_status pdg_transport_sweep(pdg_ctx *c, void *f, const double *fb_old, const 
 pdg_status pdg_relax(pdg_ctx *c, void *f, double *w_out, void *stream);
 
 /* n_steps time steps of the prepared scheme with time-independent inflow fb
- * (Sec. 3.2 and Sec. 5.1).  The interior step (relax + full transport) is
- * recorded once as a HIP graph per (f, fb) pair and replayed. */
+ * (Sec. 3.2 and Sec. 5.1).  The repeated part of the scheme (one step; for
+ * the collapsed form relax + full transport) is recorded once as a HIP graph
+ * per (f, fb) pair and replayed. */
 pdg_status pdg_step(pdg_ctx *c, void *f, const double *fb, int32_t n_steps, void *stream);
 
 /* Autotuner of the sweep's work decomposition.  Work items are grouped in

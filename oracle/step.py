@@ -7,13 +7,24 @@ velocity, and an equilibrium model.  The state F has shape (nv, m, nc, nd)
 in the oracle's numbering (cells lexicographic x fastest, nodes tensor with
 the first index fastest).
 
-Compositions (Sec. 3.2 and Sec. 5.1), with T = theta-scheme transport of every
-velocity and C = collision:
-* LIE:               [T(dt) C]^N
-* STRANG:            [T(dt/2) C T(dt/2)]^N     (the three-stage M_2)
+Compositions (Sec. 3.2 and Sec. 5.1), with T(h) = theta-scheme transport of
+every velocity over h and C(h) = collision over h:
+* LIE:               [T(dt) C(dt)]^N
+* STRANG:            [T(dt/2) C(dt) T(dt/2)]^N     (the three-stage M_2)
 * STRANG_COLLAPSED:  T(dt/2) C [T(dt) C]^{N-1} T(dt/2), the collapsed Strang
                      scheme of Sec. 5.1 in which the last half transport of a
                      step and the first of the next are fused.
+* KIN:               [M_2^kin(dt)]^N, M_2^kin(h) = T(h/4) C(h/2) T(h/2) C(h/2) T(h/4)
+                     (Sec. 3.2, second order also for tau -> 0)
+* KIN4:              [M_2^kin(g1 dt) M_2^kin(g2 dt) M_2^kin(g1 dt)]^N with
+                     g1 = 1/(2 - 2^(1/3)), g2 = 1 - 2 g1: a palindromic
+                     composition of M_2^kin.  The paper raises the order by such
+                     compositions but takes its coefficients from another
+                     paper; these are the published triple-jump coefficients
+                     (Creutz-Gocksch, Suzuki, Yoshida), which give fourth order
+                     for a time-symmetric second-order base step.
+The collision over h uses omega(h) = 2h / (2 tau + h) (eq. collision_cn); the
+omega given for dt fixes tau (omega = 2: tau = 0, then omega(h) = 2 for all h).
 The inflow data f^b is time independent (Sec. 2).
 
 Pins: a constant equilibrium state is preserved over several steps (scalar
@@ -27,7 +38,18 @@ from . import mesh as _mesh
 from . import relax as _relax
 from . import transport as _tr
 
-LIE, STRANG, STRANG_COLLAPSED = 0, 1, 2
+LIE, STRANG, STRANG_COLLAPSED, KIN, KIN4 = 0, 1, 2, 3, 4
+
+TRIPLE_JUMP_G1 = 1.0 / (2.0 - 2.0 ** (1.0 / 3.0))
+TRIPLE_JUMP_G2 = 1.0 - 2.0 * TRIPLE_JUMP_G1
+
+
+def omega_for(h, dt, omega):
+    """Collision factor over h given the factor omega over dt (eq. collision_cn)."""
+    if omega == 2.0:
+        return 2.0
+    tau = dt * (2.0 - omega) / (2.0 * omega)
+    return 2.0 * h / (2.0 * tau + h)
 
 
 class Problem:
@@ -108,6 +130,17 @@ def run(prob, f0, fb, dt, theta, omega, scheme, nsteps, method="sweep"):
             f = prob.transport(f, fb, fb, dt / 2, theta, method)
             f = prob.collide(f, omega)
             f = prob.transport(f, fb, fb, dt / 2, theta, method)
+    elif scheme in (KIN, KIN4):
+        subs = [1.0] if scheme == KIN else [TRIPLE_JUMP_G1, TRIPLE_JUMP_G2, TRIPLE_JUMP_G1]
+        for _ in range(nsteps):
+            for g in subs:
+                h = g * dt
+                wh = omega_for(h / 2, dt, omega)
+                f = prob.transport(f, fb, fb, h / 4, theta, method)
+                f = prob.collide(f, wh)
+                f = prob.transport(f, fb, fb, h / 2, theta, method)
+                f = prob.collide(f, wh)
+                f = prob.transport(f, fb, fb, h / 4, theta, method)
     elif scheme == STRANG_COLLAPSED:
         f = prob.transport(f, fb, fb, dt / 2, theta, method)
         f = prob.collide(f, omega)

@@ -298,7 +298,8 @@ def theta_step_sweep(mesh, v, f_old, fb_old, fb_new, dt, theta, levels=None):
             for k, (c, n, e) in enumerate(zip(ent["cell"], ent["node"], ent["face"]))}
     grad = reference_gradients(mesh)
     rfaces = reference_faces(mesh)
-    f_new = np.full_like(f_old, np.nan)
+    f_new = np.zeros_like(f_old)
+    solved = np.zeros(nc, dtype=bool)
     eye = np.eye(nd)
     order = np.argsort(levels, kind="stable")
     bounds = np.searchsorted(levels[order], np.arange(levels.max() + 2))
@@ -318,9 +319,9 @@ def theta_step_sweep(mesh, v, f_old, fb_old, fb_new, dt, theta, levels=None):
                 if inside.any():
                     r = fc["nbr"][inside]
                     ip = fc["partner"][inside, col]
-                    up_new = f_new[:, r, ip]
-                    if np.isnan(up_new).any():
+                    if not solved[r].all():
                         raise RuntimeError("upwind cell not solved before its downwind cell")
+                    up_new = f_new[:, r, ip]
                     rhs[:, inside, i] -= dt * coef[inside] * (theta * up_new + (1.0 - theta) * f_old[:, r, ip])
                 bnd = nz & (fc["nbr"] < 0)
                 if bnd.any():
@@ -328,4 +329,5 @@ def theta_step_sweep(mesh, v, f_old, fb_old, fb_new, dt, theta, levels=None):
                     rhs[:, bnd, i] -= dt * coef[bnd] * (theta * fb_new[:, idx] + (1.0 - theta) * fb_old[:, idx])
         sol = np.linalg.solve(a[None], rhs[..., None])[..., 0]   # (m, N, nd)
         f_new[:, cells, :] = sol
+        solved[cells] = True
     return f_new

@@ -18,7 +18,7 @@ LIB_PATH = os.path.join(_HERE, "_lib", "libpdg.so")
 PDG_OK, PDG_EINVAL, PDG_EUNSUPPORTED, PDG_ENOTDAG, PDG_ESINGULAR, PDG_ENOMEM, PDG_EDEVICE, PDG_ESTATE = range(8)
 PDG_FP64, PDG_FP32, PDG_FP32_REFINE = 0, 1, 2
 PDG_FEQ_ADVECTION, PDG_FEQ_EULER = 0, 1
-PDG_LIE, PDG_STRANG, PDG_STRANG_COLLAPSED = 0, 1, 2
+PDG_LIE, PDG_STRANG, PDG_STRANG_COLLAPSED, PDG_KIN, PDG_KIN4 = 0, 1, 2, 3, 4
 
 EXPORTED = ("pdg_setup_mesh", "pdg_layout", "pdg_node_coords", "pdg_levels", "pdg_topo_levels", "pdg_line_operator",
             "pdg_prepare", "pdg_equilibrium", "pdg_inflow_equilibrium", "pdg_transport_sweep",

@@ -106,6 +106,8 @@ struct pdg_ctx {
   bool prepared = false;
   double dt = 0, theta = 0, omega = 0;
   int scheme = 0, prec = 0;
+  std::vector<double> dts;  // prepared transport sub-steps; index = operator-table offset
+  double tau = 0.0;         // relaxation time implied by (dt, omega)
   std::vector<OpEntry> ops_h;
   DevBuf<OpEntry> ops;
   DevBuf<SweepDesc> sdesc;
@@ -239,6 +241,11 @@ void line_block(int d, double V, double h, std::vector<double> &gam, double &inf
 }
 
 bool is_finite(double x) { return std::isfinite(x); }
+
+// Triple-jump coefficients of a fourth-order palindromic composition of a
+// time-symmetric second-order step: g1 = 1/(2 - 2^(1/3)), g2 = 1 - 2 g1.
+const double kTripleJump1 = 1.0 / (2.0 - std::cbrt(2.0));
+const double kTripleJump2 = 1.0 - 2.0 / (2.0 - std::cbrt(2.0));
 
 thread_local char g_detail[512] = "";
 
@@ -657,7 +664,7 @@ pdg_status pdg_prepare(pdg_ctx *c, double dt, double theta, double omega, pdg_sc
   if (!c) return PDG_EINVAL;
   if (!is_finite(dt) || dt == 0.0 || !is_finite(theta) || !(theta > 0.0) || theta > 1.0 || !is_finite(omega))
     return PDG_EINVAL;
-  if (scheme < PDG_LIE || scheme > PDG_STRANG_COLLAPSED) return PDG_EINVAL;
+  if (scheme < PDG_LIE || scheme > PDG_KIN4) return PDG_EINVAL;
   if (prec < PDG_FP64 || prec > PDG_FP32_REFINE) return PDG_EINVAL;
   for (const Instance &in : c->inst)
     for (int v = 0; v < in.d.nv; ++v)
@@ -665,7 +672,22 @@ pdg_status pdg_prepare(pdg_ctx *c, double dt, double theta, double omega, pdg_sc
   hipStream_t st = static_cast<hipStream_t>(stream);
   c->release_device();
 
-  // ---- operator table: (instance, velocity, dt_sub in {dt, dt/2}) --------
+  // ---- transport sub-steps of the scheme (index 0: dt, 1: dt/2) ---------
+  std::vector<double> dts = {dt, 0.5 * dt};
+  if (scheme == PDG_KIN) dts.push_back(0.25 * dt);
+  if (scheme == PDG_KIN4) {
+    for (double g : {kTripleJump1, kTripleJump2}) {
+      dts.push_back(0.25 * g * dt);
+      dts.push_back(0.5 * g * dt);
+    }
+  }
+  // collision over h: omega(h) = 2h / (2 tau + h), tau from omega over dt
+  const double tau = omega == 2.0 ? 0.0 : dt * (2.0 - omega) / (2.0 * omega);
+  if (!is_finite(tau)) return PDG_EINVAL;
+  for (double h : dts)
+    if (2.0 * tau + 0.5 * h == 0.0 || 2.0 * tau + h == 0.0) return PDG_EINVAL;
+
+  // ---- operator table: (instance, velocity, dt_sub in dts) ---------------
   std::vector<OpEntry> ops;
   std::vector<SweepDesc> sdesc;
   std::vector<Family> fams;
@@ -680,9 +702,8 @@ pdg_status pdg_prepare(pdg_ctx *c, double dt, double theta, double omega, pdg_sc
       std::vector<double> gam;
       double inflow = 0.0;
       line_block(in.d.degree, V, in.h[ax], gam, inflow);
-      const int op_index = (int)ops.size();
-      for (int half = 0; half < 2; ++half) {
-        const double ds = half ? 0.5 * dt : dt;
+      const int op_index = (int)ops.size();  // + index into dts
+      for (double ds : dts) {
         OpEntry e;
         std::memset(&e, 0, sizeof(e));
         e.np = np;
@@ -875,6 +896,8 @@ pdg_status pdg_prepare(pdg_ctx *c, double dt, double theta, double omega, pdg_sc
   c->dt = dt;
   c->theta = theta;
   c->omega = omega;
+  c->dts = dts;
+  c->tau = tau;
   c->scheme = scheme;
   c->prec = prec;
   c->prepared = true;
@@ -901,12 +924,26 @@ pdg_status do_sweep(pdg_ctx *c, void *f, const double *fb_old, const double *fb_
   return PDG_OK;
 }
 
-pdg_status do_relax(pdg_ctx *c, void *f, double *w_out, hipStream_t st) {
+pdg_status do_relax(pdg_ctx *c, void *f, double *w_out, double omega, hipStream_t st) {
   if (c->rgroups.empty()) return PDG_EUNSUPPORTED;
   for (const RelaxGroup &g : c->rgroups) {
     hipError_t e = launch_relax(c->prec, g.nv, g.m, c->ritems.p + g.first, (int)g.count, c->rdesc.p, f, w_out,
-                                nullptr, c->omega, 0, st);
+                                nullptr, omega, 0, st);
     if (e != hipSuccess) return from_hip(e);
+  }
+  return PDG_OK;
+}
+
+struct StepOp {
+  int kind;      // 0: transport sweep, 1: relaxation
+  int dt_idx;    // sweep: index into the prepared sub-steps
+  double omega;  // relaxation factor
+};
+
+pdg_status run_ops(pdg_ctx *c, const std::vector<StepOp> &ops, void *f, const double *fb, hipStream_t st) {
+  for (const StepOp &o : ops) {
+    const pdg_status s = o.kind == 0 ? do_sweep(c, f, fb, fb, o.dt_idx, st) : do_relax(c, f, nullptr, o.omega, st);
+    if (s != PDG_OK) return s;
   }
   return PDG_OK;
 }
@@ -919,20 +956,20 @@ pdg_status pdg_transport_sweep(pdg_ctx *c, void *f, const double *fb_old, const 
                                void *stream) {
   if (!c || !f || (c->fb_elems > 0 && (!fb_old || !fb_new))) return PDG_EINVAL;
   if (!c->prepared) return PDG_ESTATE;
-  int dt_idx;
-  if (dt_sub == c->dt)
-    dt_idx = 0;
-  else if (dt_sub == 0.5 * c->dt)
-    dt_idx = 1;
-  else
-    return PDG_ESTATE;
+  int dt_idx = -1;
+  for (size_t i = 0; i < c->dts.size(); ++i)
+    if (dt_sub == c->dts[i]) {
+      dt_idx = (int)i;
+      break;
+    }
+  if (dt_idx < 0) return PDG_ESTATE;
   return do_sweep(c, f, fb_old, fb_new, dt_idx, static_cast<hipStream_t>(stream));
 }
 
 pdg_status pdg_relax(pdg_ctx *c, void *f, double *w_out, void *stream) {
   if (!c || !f) return PDG_EINVAL;
   if (!c->prepared) return PDG_ESTATE;
-  return do_relax(c, f, w_out, static_cast<hipStream_t>(stream));
+  return do_relax(c, f, w_out, c->omega, static_cast<hipStream_t>(stream));
 }
 
 pdg_status pdg_equilibrium(pdg_ctx *c, const double *w, void *f, void *stream) {
@@ -965,57 +1002,79 @@ pdg_status pdg_step(pdg_ctx *c, void *f, const double *fb, int32_t n_steps, void
   if (c->rgroups.empty()) return PDG_EUNSUPPORTED;
   if (n_steps == 0) return PDG_OK;
   hipStream_t st = static_cast<hipStream_t>(stream);
-  pdg_status s;
-  const bool use_graph = std::getenv("PDG_NO_GRAPH") == nullptr;
-  if (c->scheme == PDG_LIE || c->scheme == PDG_STRANG) {
-    const int idx = c->scheme == PDG_LIE ? 0 : 1;
-    for (int32_t i = 0; i < n_steps; ++i) {
-      if ((s = do_sweep(c, f, fb, fb, idx, st)) != PDG_OK) return s;
-      if ((s = do_relax(c, f, nullptr, st)) != PDG_OK) return s;
-      if (c->scheme == PDG_STRANG && (s = do_sweep(c, f, fb, fb, idx, st)) != PDG_OK) return s;
+  // prologue, interior (repeated), epilogue: sweeps by sub-step index, relaxations by omega
+  std::vector<StepOp> pro, body, epi;
+  int reps = n_steps;
+  const double w = c->omega;
+  auto om = [c](double h) { return c->tau == 0.0 ? 2.0 : 2.0 * h / (2.0 * c->tau + h); };
+  switch (c->scheme) {
+    case PDG_LIE: body = {{0, 0, 0.0}, {1, 0, w}}; break;
+    case PDG_STRANG: body = {{0, 1, 0.0}, {1, 0, w}, {0, 1, 0.0}}; break;
+    case PDG_STRANG_COLLAPSED:
+      // T(dt/2) C [T(dt) C]^(N-1) T(dt/2)
+      pro = {{0, 1, 0.0}, {1, 0, w}};
+      body = {{0, 0, 0.0}, {1, 0, w}};
+      epi = {{0, 1, 0.0}};
+      reps = n_steps - 1;
+      break;
+    case PDG_KIN:
+      // M_2^kin(dt) = T(dt/4) C(dt/2) T(dt/2) C(dt/2) T(dt/4)
+      body = {{0, 2, 0.0}, {1, 0, om(0.5 * c->dt)}, {0, 1, 0.0}, {1, 0, om(0.5 * c->dt)}, {0, 2, 0.0}};
+      break;
+    case PDG_KIN4: {
+      // M_2^kin(g1 dt) M_2^kin(g2 dt) M_2^kin(g1 dt); sub-steps 2..5 = g1/4, g1/2, g2/4, g2/2
+      const double g[3] = {kTripleJump1, kTripleJump2, kTripleJump1};
+      const int q[3] = {2, 4, 2};
+      for (int j = 0; j < 3; ++j) {
+        const double wc = om(0.5 * g[j] * c->dt);
+        body.push_back({0, q[j], 0.0});
+        body.push_back({1, 0, wc});
+        body.push_back({0, q[j] + 1, 0.0});
+        body.push_back({1, 0, wc});
+        body.push_back({0, q[j], 0.0});
+      }
+      break;
     }
-    return PDG_OK;
+    default: return PDG_ESTATE;
   }
-  // collapsed Strang: T(dt/2) C [T(dt) C]^(N-1) T(dt/2)
-  if ((s = do_sweep(c, f, fb, fb, 1, st)) != PDG_OK) return s;
-  if ((s = do_relax(c, f, nullptr, st)) != PDG_OK) return s;
-  if (n_steps > 1) {
+  pdg_status s;
+  if ((s = run_ops(c, pro, f, fb, st)) != PDG_OK) return s;
+  if (reps > 0) {
+    const bool use_graph = std::getenv("PDG_NO_GRAPH") == nullptr;
     if (use_graph && (c->gexec == nullptr || c->g_f != f || c->g_fb != fb)) {
       if (c->gexec) (void)hipGraphExecDestroy(c->gexec);
       c->gexec = nullptr;
       hipGraph_t graph = nullptr;
       hipError_t e = hipStreamBeginCapture(c->cap_stream, hipStreamCaptureModeThreadLocal);
-      if (e != hipSuccess) return from_hip(e);
-      pdg_status s1 = do_sweep(c, f, fb, fb, 0, c->cap_stream);
-      pdg_status s2 = s1 == PDG_OK ? do_relax(c, f, nullptr, c->cap_stream) : s1;
+      if (e != hipSuccess) return from_hip_at(e, "hipStreamBeginCapture");
+      pdg_status s2 = run_ops(c, body, f, fb, c->cap_stream);
       e = hipStreamEndCapture(c->cap_stream, &graph);
       if (s2 != PDG_OK) {
         if (graph) (void)hipGraphDestroy(graph);
         return s2;
       }
-      if (e != hipSuccess) return from_hip(e);
+      if (e != hipSuccess) return from_hip_at(e, "hipStreamEndCapture");
       e = hipGraphInstantiate(&c->gexec, graph, nullptr, nullptr, 0);
       (void)hipGraphDestroy(graph);
       if (e != hipSuccess) {
         c->gexec = nullptr;
-        return from_hip(e);
+        return from_hip_at(e, "hipGraphInstantiate");
       }
       c->g_f = f;
       c->g_fb = fb;
     }
-    for (int32_t i = 1; i < n_steps; ++i) {
+    for (int32_t i = 0; i < reps; ++i) {
       if (use_graph) {
         hipError_t e = hipGraphLaunch(c->gexec, st);
-        if (e != hipSuccess) return from_hip(e);
-      } else {
-        if ((s = do_sweep(c, f, fb, fb, 0, st)) != PDG_OK) return s;
-        if ((s = do_relax(c, f, nullptr, st)) != PDG_OK) return s;
+        if (e != hipSuccess) return from_hip_at(e, "hipGraphLaunch");
+      } else if ((s = run_ops(c, body, f, fb, st)) != PDG_OK) {
+        return s;
       }
     }
     c->stats_valid = c->prec == PDG_FP32_REFINE;
     c->last_stream = st;
   }
-  return do_sweep(c, f, fb, fb, 1, st);
+  return run_ops(c, epi, f, fb, st);
 }
 
 namespace {

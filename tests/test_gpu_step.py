@@ -54,7 +54,7 @@ def _run(lib, torch, wl, prec, scheme, steps):
     return res, corr
 
 
-@pytest.mark.parametrize("scheme", [0, 1, 2], ids=["lie", "strang", "collapsed"])
+@pytest.mark.parametrize("scheme", [0, 1, 2, 3, 4], ids=["lie", "strang", "collapsed", "kin", "kin4"])
 @pytest.mark.parametrize("prec", [0, 2, 1], ids=["fp64", "fp32refine", "fp32"])
 def test_step_adv2d_16(lib, scheme, prec):
     torch = pytest.importorskip("torch")
@@ -64,6 +64,24 @@ def test_step_adv2d_16(lib, scheme, prec):
     print(f"  rel L2 {err[0]:.3e} max {err[1]:.3e} refine correction {corr}")
     bar = {0: 1e-12, 2: 1e-10, 1: 1e-5}[prec]
     assert err[0] <= bar and err[1] <= 10 * bar
+
+
+@pytest.mark.parametrize("scheme", [3, 4], ids=["kin", "kin4"])
+@pytest.mark.parametrize("name", ["adv2d_16", "euler2d_256"])
+@pytest.mark.parametrize("omega", [2.0, 1.6])
+def test_step_kin_compositions(lib, scheme, name, omega):
+    """M_2^kin and its triple-jump composition (Sec. 3.2), tau = 0 and tau > 0."""
+    torch = pytest.importorskip("torch")
+    print(f"step {name} scheme={scheme} omega={omega}", flush=True)
+    wl = _small(name)
+    wl.omega = omega
+    if scheme == 4 and name == "euler2d_256":
+        # the negative middle stage is only conditionally stable on the
+        # damped upwind modes; at dt = h / lambda the Euler state blows up
+        wl.dt = wl.dt / 8
+    (err,), _ = _run(lib, torch, wl, 0, scheme, 3)
+    print(f"  rel L2 {err[0]:.3e} max {err[1]:.3e}")
+    assert err[0] <= 1e-12 and err[1] <= 1e-11
 
 
 @pytest.mark.parametrize("name", ["adv3d_64", "euler2d_256", "euler3d_128"])

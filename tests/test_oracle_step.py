@@ -62,3 +62,65 @@ def test_collapsed_strang_is_second_order_in_time():
     errs = [np.linalg.norm(w_at(n) - ref) for n in (4, 8, 16)]
     rates = [np.log2(errs[i] / errs[i + 1]) for i in range(2)]
     assert all(1.7 < r < 2.4 for r in rates), (errs, rates)
+
+
+def _order_rates(scheme, omega, nsteps_list, ref_steps, t_end=0.2, degree=3, cells=6):
+    inst = W.Instance(2, (cells, cells), degree, 1.0, 1, "advection", {"a": [0.5, 0.25]},
+                      W.gaussian_bump(1.0, (0.4, 0.45), 20.0))
+    prob = _problem(inst)
+    f0, fb = _initial(prob, inst.w0)
+
+    def f_at(n):
+        dt = t_end / n
+        # omega is given for dt; keep tau fixed across the refinements
+        return ost.run(prob, f0, fb, dt, 0.5, ost.omega_for(dt, TAU_DT, omega), scheme, n)
+
+    ref = f_at(ref_steps)
+    errs = [np.linalg.norm(f_at(n) - ref) for n in nsteps_list]
+    return errs, [np.log2(errs[i] / errs[i + 1]) for i in range(len(errs) - 1)]
+
+
+TAU_DT = 0.05   # omega below is the collision factor over this step: tau = 0.05 (2 - w)/(2 w)
+
+
+def test_omega_for_matches_crank_nicolson_collision():
+    # eq. collision_cn: omega(h) = 2h/(2 tau + h); tau from omega over dt
+    tau = 0.013
+    dt = 0.05
+    omega = 2 * dt / (2 * tau + dt)
+    for h in (dt, dt / 2, -dt / 3, 0.37 * dt):
+        assert abs(ost.omega_for(h, dt, omega) - 2 * h / (2 * tau + h)) < 1e-14
+    assert ost.omega_for(0.123, dt, 2.0) == 2.0
+
+
+@pytest.mark.slow
+def test_kin_composition_is_second_order_with_relaxation_time():
+    errs, rates = _order_rates(ost.KIN, 1.6, [4, 8, 16], 64)
+    assert all(1.7 < r < 2.5 for r in rates), (errs, rates)
+
+
+@pytest.mark.slow
+def test_kin_composition_is_second_order_at_tau_zero():
+    errs, rates = _order_rates(ost.KIN, 2.0, [4, 8, 16], 64)
+    assert all(1.7 < r < 2.5 for r in rates), (errs, rates)
+
+
+@pytest.mark.slow
+def test_triple_jump_of_kin_is_fourth_order():
+    # the negative middle stage makes the composition only conditionally
+    # stable on the strongly damped upwind modes: test in its asymptotic range
+    errs, rates = _order_rates(ost.KIN4, 1.6, [16, 32], 128, t_end=0.1, degree=1, cells=4)
+    assert all(3.5 < r < 5.0 for r in rates), (errs, rates)
+
+
+def test_kin_step_is_time_symmetric_with_relaxation_time():
+    # M_2^kin is a palindrome of time-symmetric stages when tau > 0
+    inst = W.make("adv2d_16", scale=4).instances[0]
+    prob = _problem(inst)
+    f0, fb = _initial(prob, inst.w0)
+    f0 = f0 * (1 + 0.1 * np.random.default_rng(1).standard_normal(f0.shape))
+    dt, tau = 0.03, 0.02
+    omega = 2 * dt / (2 * tau + dt)
+    g = ost.run(prob, f0, fb, dt, 0.5, omega, ost.KIN, 1)
+    back = ost.run(prob, g, fb, -dt, 0.5, 2 * (-dt) / (2 * tau - dt), ost.KIN, 1)
+    assert np.max(np.abs(back - f0)) < 1e-12 * np.max(np.abs(f0))
