@@ -55,13 +55,18 @@ def initial_state(pdg, prob, insts, torch, dtype):
         ioff = 0
         nc = int(np.prod(inst.n))
         for v in range(inst.vel.shape[0]):
-            ax = int(np.nonzero(inst.vel[v])[0][0])
-            npts = (inst.degree + 1) ** (inst.dim - 1) * (nc // inst.n[ax])
-            pts = inflow[ioff:ioff + inst.dim * npts].reshape(inst.dim, npts).T
-            vals = inst.w0(pts)
-            fbw[off:off + vals.size] = vals.ravel()
-            off += vals.size
-            ioff += inst.dim * npts
+            blocks = []
+            for ax in range(inst.dim):
+                if inst.vel[v][ax] == 0:
+                    continue
+                npts = (inst.degree + 1) ** (inst.dim - 1) * (nc // inst.n[ax])
+                pts = inflow[ioff:ioff + inst.dim * npts].reshape(inst.dim, npts).T
+                blocks.append(inst.w0(pts))
+                ioff += inst.dim * npts
+            if blocks:
+                vals = np.concatenate(blocks, axis=1)   # fb block [k][face][t][tau]
+                fbw[off:off + vals.size] = vals.ravel()
+                off += vals.size
     f = torch.empty(prob.layout["f_elems"], dtype=dtype, device="cuda")
     fb = torch.empty(prob.layout["fb_elems"], dtype=torch.float64, device="cuda")
     w_t = torch.from_numpy(w).cuda()

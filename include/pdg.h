@@ -14,11 +14,15 @@
  * triangular in a topological order of the upwind dependency graph (Sec. 4.1),
  * so each implicit step is solved by a downwind sweep.
  *
- * Supported here: D in {2, 3}, degree d in 1..4, velocity sets made of
- * axis-aligned non-zero velocities (+-lambda e_k).  For such velocities the
- * cell block I + theta dt Gamma_{L<-L} factorises as a Kronecker product of a
- * (d+1) x (d+1) one-dimensional block with the identity, and the dependency
- * graph splits into independent lines of cells along the velocity axis.
+ * Supported here: D in {2, 3}, degree d in 1..4, any constant velocities.
+ * - axis-aligned velocities (+-lambda e_k): the cell block I + theta dt
+ *   Gamma_{L<-L} factorises as a Kronecker product of a (d+1) x (d+1)
+ *   one-dimensional block with the identity, and the dependency graph splits
+ *   into independent lines of cells along the velocity axis;
+ * - velocities with two or three non-zero components (e.g. the diagonal
+ *   velocities of D2Q9 / D3Q27): dense cell blocks, swept as a tiled
+ *   wavefront; (d+1)^D <= 27 (2D: d <= 4, 3D: d <= 2);
+ * - the zero velocity: transport is the identity.
  *
  * Conventions used by every entry point:
  *  - Status codes are returned synchronously; the library never aborts and no
@@ -148,6 +152,16 @@ pdg_status pdg_topo_levels(int32_t n_nodes, int64_t n_edges, const int32_t *src,
  * Host only; gamma holds (d+1)^2 values. */
 pdg_status pdg_line_operator(const pdg_ctx *c, int32_t inst, int32_t vel, double *gamma, double *kappa);
 
+/* Host introspection of the full cell block of any velocity: gamma receives
+ * Gamma_{L<-L} of eq. DG_reduit ((d+1)^D x (d+1)^D, row-major) in
+ * downwind-local tensor order (node q = q_0 + (d+1) q_1 + (d+1)^2 q_2 with
+ * q_a = j_a if v_a >= 0 else d - j_a, so q_a = 0 lies on the inflow face of
+ * each non-zero component); kappa[a] (3 values) is the inflow coupling
+ * magnitude of axis a (Gamma_{L<-R} = -kappa[a] at the inflow face nodes; 0 if
+ * v_a = 0).  On uniform Cartesian cells the block is the Kronecker sum of the
+ * one-dimensional blocks of the non-zero components.  Host only. */
+pdg_status pdg_cell_operator(const pdg_ctx *c, int32_t inst, int32_t vel, double *gamma, double *kappa);
+
 /* Prepare the time step (Sec. 3.2): for every instance, velocity and
  * transport sub-step dt_sub of the scheme (always dt and dt/2; also dt/4 for
  * PDG_KIN; g dt/4 and g dt/2 for both triple-jump g for PDG_KIN4), build on
@@ -223,6 +237,11 @@ pdg_status pdg_last_refine_correction(const pdg_ctx *c, double *max_rel_correcti
  * call and the runtime's message); empty if none.  Static thread-local
  * storage, valid until the next failing call. */
 const char *pdg_error_detail(void);
+
+/* Wait for the work enqueued by the most recent sweep and report device-side
+ * failures: PDG_EDEVICE if a kernel failed or a dense-path tile wait timed
+ * out (the result is then invalid), else PDG_OK.  Synchronises. */
+pdg_status pdg_sync_status(pdg_ctx *c);
 
 /* Human-readable name of a status code (static storage). */
 const char *pdg_status_string(pdg_status s);

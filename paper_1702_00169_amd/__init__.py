@@ -20,9 +20,9 @@ PDG_FP64, PDG_FP32, PDG_FP32_REFINE = 0, 1, 2
 PDG_FEQ_ADVECTION, PDG_FEQ_EULER = 0, 1
 PDG_LIE, PDG_STRANG, PDG_STRANG_COLLAPSED, PDG_KIN, PDG_KIN4 = 0, 1, 2, 3, 4
 
-EXPORTED = ("pdg_setup_mesh", "pdg_layout", "pdg_node_coords", "pdg_levels", "pdg_topo_levels", "pdg_line_operator",
+EXPORTED = ("pdg_setup_mesh", "pdg_layout", "pdg_node_coords", "pdg_levels", "pdg_topo_levels", "pdg_line_operator", "pdg_cell_operator",
             "pdg_prepare", "pdg_equilibrium", "pdg_inflow_equilibrium", "pdg_transport_sweep",
-            "pdg_relax", "pdg_step", "pdg_autotune", "pdg_get_tiles", "pdg_set_tiles", "pdg_last_refine_correction", "pdg_status_string", "pdg_error_detail", "pdg_destroy")
+            "pdg_relax", "pdg_step", "pdg_autotune", "pdg_get_tiles", "pdg_set_tiles", "pdg_last_refine_correction", "pdg_sync_status", "pdg_status_string", "pdg_error_detail", "pdg_destroy")
 
 
 class PdgError(RuntimeError):
@@ -57,6 +57,7 @@ def _load():
         "pdg_levels": (i32, [p, i32, i32, p]),
         "pdg_topo_levels": (i32, [i32, i64, p, p, p]),
         "pdg_line_operator": (i32, [p, i32, i32, p, ctypes.POINTER(d)]),
+        "pdg_cell_operator": (i32, [p, i32, i32, p, p]),
         "pdg_prepare": (i32, [p, d, d, d, i32, i32, p]),
         "pdg_equilibrium": (i32, [p, p, p, p]),
         "pdg_inflow_equilibrium": (i32, [p, p, p, p]),
@@ -67,6 +68,7 @@ def _load():
         "pdg_get_tiles": (i32, [p, ctypes.POINTER(i32), p]),
         "pdg_set_tiles": (i32, [p, i32, p]),
         "pdg_last_refine_correction": (i32, [p, ctypes.POINTER(d)]),
+        "pdg_sync_status": (i32, [p]),
         "pdg_status_string": (ctypes.c_char_p, [i32]),
         "pdg_error_detail": (ctypes.c_char_p, []),
         "pdg_destroy": (None, [p]),
@@ -169,6 +171,10 @@ def pdg_line_operator(ctx, inst, vel, gamma):
     return kappa.value
 
 
+def pdg_cell_operator(ctx, inst, vel, gamma, kappa):
+    _check(_lib.pdg_cell_operator(ctx, int(inst), int(vel), _ptr(gamma), _ptr(kappa)), "pdg_cell_operator")
+
+
 def pdg_prepare(ctx, dt, theta, omega, scheme, precision, stream=None):
     _check(_lib.pdg_prepare(ctx, float(dt), float(theta), float(omega), int(scheme), int(precision),
                             _stream(stream)), "pdg_prepare")
@@ -220,6 +226,10 @@ def pdg_last_refine_correction(ctx):
     out = ctypes.c_double()
     _check(_lib.pdg_last_refine_correction(ctx, ctypes.byref(out)), "pdg_last_refine_correction")
     return out.value
+
+
+def pdg_sync_status(ctx):
+    _check(_lib.pdg_sync_status(ctx), "pdg_sync_status")
 
 
 def pdg_destroy(ctx):
@@ -289,6 +299,9 @@ class Problem:
 
     def set_tiles(self, tiles):
         pdg_set_tiles(self.ctx, tiles)
+
+    def sync_status(self):
+        pdg_sync_status(self.ctx)
 
     def last_refine_correction(self):
         return pdg_last_refine_correction(self.ctx)

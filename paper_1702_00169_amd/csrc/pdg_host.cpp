@@ -13,6 +13,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <array>
 #include <cmath>
 #include <cstdio>
 #include <cstdlib>
@@ -37,6 +38,8 @@ struct Instance {
   std::vector<int64_t> fb_vel_off;  // per velocity, offset within the instance's fb block
   std::vector<int> axis;            // per velocity: axis of the velocity, -1 if not axis-aligned
   std::vector<int> sign;
+  std::vector<int> ndep;            // per velocity: number of non-zero components
+  std::vector<std::array<int, 3>> sgn;  // per velocity and axis: sign of the component (0 if zero)
   double h[3];
   int64_t n[3];
 };
@@ -49,6 +52,13 @@ struct Group {
 struct RelaxGroup {
   int nv, m;
   int64_t first, count;
+};
+
+// Dense launch group: tiles of one (d+1, D) kernel instantiation.
+struct DenseGroup {
+  int np, dim;
+  int64_t first, count;  // tile range (tiles and claim order)
+  int64_t sync_off;      // counter at sync_off, flags at sync_off + 1 ..
 };
 
 // One (instance, velocity) family of chains and its launch class.
@@ -115,6 +125,16 @@ struct pdg_ctx {
   std::vector<Group> groups;
   std::vector<Family> fams;
   std::vector<LaunchClass> classes;
+  // dense path (velocities with two or three non-zero components)
+  std::vector<DenseGroup> dgroups;
+  DevBuf<DenseDesc> ddesc;
+  DevBuf<DenseFam> dfams;
+  DevBuf<DenseTile> dtiles;
+  DevBuf<int32_t> dorder;
+  DevBuf<double> dtable;
+  DevBuf<double> dtraces;
+  DevBuf<int32_t> dsync;     // per group: counter + one flag per tile
+  DevBuf<int32_t> derr;      // wait-timeout flag
   DevBuf<RelaxDesc> rdesc;
   DevBuf<RelaxItem> ritems;
   std::vector<RelaxGroup> rgroups;
@@ -140,6 +160,15 @@ struct pdg_ctx {
     rdesc.release();
     ritems.release();
     idesc.release();
+    ddesc.release();
+    dfams.release();
+    dtiles.release();
+    dorder.release();
+    dtable.release();
+    dtraces.release();
+    dsync.release();
+    derr.release();
+    dgroups.clear();
     stats.release();
     if (cap_stream) (void)hipStreamDestroy(cap_stream);
     cap_stream = nullptr;
@@ -238,6 +267,34 @@ void line_block(int d, double V, double h, std::vector<double> &gam, double &inf
     for (int j = 0; j < np; ++j) gam[i * np + j] = -(s * dm[j * np + i] * w[j]) / w[i];
   gam[(np - 1) * np + (np - 1)] += s / w[np - 1];
   inflow_coef = s / w[0];  // magnitude of -(Gamma_{L<-R}) at node 0
+}
+
+// Cell block Gamma_{L<-L} of eq. DG_reduit for any constant velocity on a
+// uniform Cartesian cell, in downwind-local tensor order (node index
+// q = q_0 + NP q_1 + NP^2 q_2 with q_a = j_a if v_a >= 0 else NP-1-j_a, so
+// q_a = 0 lies on the inflow face of every axis with v_a != 0).  On these
+// cells the block is the Kronecker sum of the one-dimensional blocks of the
+// non-zero components; kappa[a] is the inflow coupling magnitude of axis a
+// (Gamma_{L<-R} = -kappa[a] at the inflow face nodes), 0 for v_a = 0.
+void dense_block(int dim, int d, const double *v, const double *h, std::vector<double> &gam, double kappa[3]) {
+  const int np = d + 1;
+  int nd = 1;
+  for (int k = 0; k < dim; ++k) nd *= np;
+  gam.assign((size_t)nd * nd, 0.0);
+  for (int a = 0; a < 3; ++a) kappa[a] = 0.0;
+  int stride[3] = {1, np, np * np};
+  for (int a = 0; a < dim; ++a) {
+    if (v[a] == 0.0) continue;
+    std::vector<double> g1;
+    line_block(d, std::fabs(v[a]), h[a], g1, kappa[a]);
+    for (int q = 0; q < nd; ++q) {
+      const int qa = (q / stride[a]) % np;
+      for (int qa2 = 0; qa2 < np; ++qa2) {
+        const int q2 = q + (qa2 - qa) * stride[a];
+        gam[(size_t)q * nd + q2] += g1[qa * np + qa2];
+      }
+    }
+  }
 }
 
 bool is_finite(double x) { return std::isfinite(x); }
@@ -512,27 +569,31 @@ pdg_status pdg_setup_mesh(const pdg_instance_desc *descs, int32_t n_inst, pdg_ct
     }
     in.axis.assign(d.nv, -1);
     in.sign.assign(d.nv, 0);
+    in.ndep.assign(d.nv, 0);
+    in.sgn.assign(d.nv, {0, 0, 0});
     in.fb_vel_off.assign(d.nv + 1, 0);
     int64_t fbo = 0;
+    int64_t tnodes = 1;
+    for (int k = 0; k < d.dim - 1; ++k) tnodes *= in.np;
     for (int v = 0; v < d.nv; ++v) {
       int nz = 0, ax = -1;
-      for (int k = 0; k < d.dim; ++k)
-        if (in.v[(size_t)v * d.dim + k] != 0.0) {
+      for (int k = 0; k < d.dim; ++k) {
+        const double comp = in.v[(size_t)v * d.dim + k];
+        if (comp != 0.0) {
           nz++;
           ax = k;
+          in.sgn[v][k] = comp > 0 ? 1 : -1;
         }
+      }
+      in.ndep[v] = nz;
       if (nz == 1) {
         in.axis[v] = ax;
-        in.sign[v] = in.v[(size_t)v * d.dim + ax] > 0 ? 1 : -1;
+        in.sign[v] = in.sgn[v][ax];
       }
+      // inflow data: one face block per non-zero component, [k][axis][t][tau]
       in.fb_vel_off[v] = fbo;
-      if (nz == 1) {
-        int64_t tnodes = 1;
-        for (int k = 0; k < d.dim - 1; ++k) tnodes *= in.np;
-        fbo += (int64_t)d.m * tnodes * (in.nc / in.n[ax]);
-      } else {
-        fbo += 0;  // non-axis-aligned velocities: transport not supported here
-      }
+      for (int k = 0; k < d.dim; ++k)
+        if (in.sgn[v][k] != 0) fbo += (int64_t)d.m * tnodes * (in.nc / in.n[k]);
       // the upwind dependency graph must be acyclic (Sec. 4.1)
       std::vector<int32_t> lev;
       pdg_status s = mesh_levels(in, v, lev);
@@ -607,9 +668,9 @@ pdg_status pdg_node_coords(const pdg_ctx *c, int32_t inst, double *vol_xyz, doub
   }
   if (inflow_xyz) {
     int64_t off = 0;
-    for (int v = 0; v < in.d.nv; ++v) {
-      const int ax = in.axis[v];
-      if (ax < 0) continue;
+    for (int v = 0; v < in.d.nv; ++v)
+    for (int ax = 0; ax < dim; ++ax) {
+      if (in.sgn[v][ax] == 0) continue;
       int other[2], no = 0;
       for (int k = 0; k < dim; ++k)
         if (k != ax) other[no++] = k;
@@ -621,7 +682,7 @@ pdg_status pdg_node_coords(const pdg_ctx *c, int32_t inst, double *vol_xyz, doub
           for (int64_t tau = 0; tau < ntc; ++tau) {
             double val;
             if (k == ax) {
-              val = in.sign[v] > 0 ? in.d.lo[k] : in.d.hi[k];
+              val = in.sgn[v][ax] > 0 ? in.d.lo[k] : in.d.hi[k];
             } else {
               const int slot = (k == other[0]) ? 0 : 1;
               const int node = slot == 0 ? (int)(t % np) : (int)(t / np);
@@ -659,6 +720,16 @@ pdg_status pdg_line_operator(const pdg_ctx *c, int32_t inst, int32_t vel, double
   return PDG_OK;
 }
 
+pdg_status pdg_cell_operator(const pdg_ctx *c, int32_t inst, int32_t vel, double *gamma, double *kappa) {
+  if (!c || !gamma || !kappa || inst < 0 || inst >= (int32_t)c->inst.size()) return PDG_EINVAL;
+  const Instance &in = c->inst[inst];
+  if (vel < 0 || vel >= in.d.nv) return PDG_EINVAL;
+  std::vector<double> gam;
+  dense_block(in.d.dim, in.d.degree, &in.v[(size_t)vel * in.d.dim], in.h, gam, kappa);
+  std::memcpy(gamma, gam.data(), gam.size() * sizeof(double));
+  return PDG_OK;
+}
+
 pdg_status pdg_prepare(pdg_ctx *c, double dt, double theta, double omega, pdg_scheme scheme, pdg_precision prec,
                        void *stream) {
   if (!c) return PDG_EINVAL;
@@ -668,7 +739,7 @@ pdg_status pdg_prepare(pdg_ctx *c, double dt, double theta, double omega, pdg_sc
   if (prec < PDG_FP64 || prec > PDG_FP32_REFINE) return PDG_EINVAL;
   for (const Instance &in : c->inst)
     for (int v = 0; v < in.d.nv; ++v)
-      if (in.axis[v] < 0) return PDG_EUNSUPPORTED;
+      if (in.ndep[v] >= 2 && in.nd > kDenseMaxN) return PDG_EUNSUPPORTED;
   hipStream_t st = static_cast<hipStream_t>(stream);
   c->release_device();
 
@@ -697,6 +768,7 @@ pdg_status pdg_prepare(pdg_ctx *c, double dt, double theta, double omega, pdg_sc
     const int np = (int)in.np;
     const int dim = in.d.dim;
     for (int v = 0; v < in.d.nv; ++v) {
+      if (in.ndep[v] != 1) continue;  // zero velocity: identity; two or more components: dense path
       const int ax = in.axis[v];
       const double V = std::fabs(in.v[(size_t)v * dim + ax]);
       std::vector<double> gam;
@@ -794,6 +866,185 @@ pdg_status pdg_prepare(pdg_ctx *c, double dt, double theta, double omega, pdg_sc
   std::vector<SweepItem> items;
   build_items(c, items);
 
+  // ---- dense path tables -----------------------------------------------------
+  std::vector<DenseDesc> ddesc;
+  std::vector<DenseFam> dfam;
+  std::vector<DenseTile> dtile;
+  std::vector<double> dtable;
+  std::vector<int64_t> drow_off;
+  std::vector<int32_t> drow_desc;
+  std::vector<double> drow_c0;
+  std::vector<std::pair<int, int>> dshape;  // (np, dim) per family
+  int64_t trace_total = 0;
+  for (size_t ii = 0; ii < c->inst.size(); ++ii) {
+    const Instance &in = c->inst[ii];
+    const int np = (int)in.np, dim = in.d.dim;
+    const int N = (int)in.nd;
+    int F = 1;
+    for (int k = 0; k < dim - 1; ++k) F *= np;
+    for (int v = 0; v < in.d.nv; ++v) {
+      if (in.ndep[v] < 2) continue;
+      DenseDesc dd;
+      std::memset(&dd, 0, sizeof(dd));
+      dd.nc = in.nc;
+      dd.theta = theta;
+      dd.trans_axis = -1;
+      int64_t fboff = 0, tnodes = F;
+      for (int a = 0; a < 3; ++a) {
+        dd.n[a] = (int32_t)in.n[a];
+        dd.sgn[a] = a < dim ? in.sgn[v][a] : 0;
+        dd.T[a] = dd.sgn[a] == 0 ? 1 : (in.ndep[v] == 2 ? 8 : 4);
+        if (a < dim && dd.sgn[a] == 0) dd.trans_axis = a;
+        if (dd.sgn[a] != 0) {
+          dd.fb_axis_off[a] = fboff;
+          dd.fb_ntc[a] = in.nc / in.n[a];
+          fboff += tnodes * dd.fb_ntc[a];
+        }
+      }
+      const int64_t per_comp = fboff;
+      // node planes in downwind-local order
+      for (int q = 0; q < N; ++q) {
+        int64_t j = 0, st2 = 1;
+        int rem = q;
+        for (int a = 0; a < dim; ++a) {
+          const int qa = rem % np;
+          rem /= np;
+          const int ja = dd.sgn[a] < 0 ? np - 1 - qa : qa;
+          j += ja * st2;
+          st2 *= np;
+        }
+        dd.plane_off[q] = j * in.nc;
+      }
+      for (int a = 0; a < dim; ++a)
+        for (int t = 0; t < F; ++t) {
+          int q = 0, stride = 1, rem = t, tphys = 0, ps = 1;
+          for (int b = 0; b < dim; ++b) {
+            int qb;
+            if (b == a) {
+              qb = 0;
+            } else {
+              qb = rem % np;
+              rem /= np;
+              const int jb = dd.sgn[b] < 0 ? np - 1 - qb : qb;
+              tphys += jb * ps;
+              ps *= np;
+            }
+            q += qb * stride;
+            stride *= np;
+          }
+          dd.face_q[a][t] = q;
+          dd.fb_t[a][t] = tphys;
+        }
+      // operator rows: one per transport sub-step
+      std::vector<double> gam;
+      double kappa[3];
+      dense_block(dim, in.d.degree, &in.v[(size_t)v * dim], in.h, gam, kappa);
+      const int64_t stride_row = 4LL * N * N + 3LL * N * F;
+      dd.op_off = (int64_t)dtable.size();
+      dd.op_stride = stride_row;
+      const int desc_index = (int)ddesc.size();
+      for (double ds : dts) {
+        const int64_t off = (int64_t)dtable.size();
+        dtable.resize(dtable.size() + stride_row, 0.0);
+        for (int i = 0; i < N; ++i)
+          for (int j = 0; j < N; ++j) {
+            const double id = i == j ? 1.0 : 0.0;
+            dtable[off + (int64_t)N * N + 3LL * N * F + i * N + j] = id + theta * ds * gam[(size_t)i * N + j];
+            dtable[off + 2LL * N * N + 3LL * N * F + i * N + j] = id - (1.0 - theta) * ds * gam[(size_t)i * N + j];
+          }
+        drow_off.push_back(off);
+        drow_desc.push_back(desc_index);
+        for (int a = 0; a < 3; ++a) drow_c0.push_back(ds * kappa[a]);
+      }
+      ddesc.push_back(dd);
+      // families (component x transverse slice) and their tiles
+      const int nslice = dd.trans_axis >= 0 ? (int)in.n[dd.trans_axis] : 1;
+      int ntile[3];
+      for (int a = 0; a < 3; ++a) ntile[a] = dd.sgn[a] == 0 ? 1 : (int)((in.n[a] + dd.T[a] - 1) / dd.T[a]);
+      int slot = 0;  // doubles per axis slot: largest tile face x F
+      for (int a = 0; a < dim; ++a) {
+        if (dd.sgn[a] == 0) continue;
+        int cells = 1;
+        for (int b = 0; b < dim; ++b)
+          if (b != a && dd.sgn[b] != 0) cells *= dd.T[b];
+        slot = std::max(slot, cells * F);
+      }
+      for (int k = 0; k < in.d.m; ++k)
+        for (int sl = 0; sl < nslice; ++sl) {
+          DenseFam fmd;
+          fmd.f_base = in.f_off + (int64_t)(v * in.d.m + k) * in.nd * in.nc;
+          fmd.fb_base = in.fb_off + in.fb_vel_off[v] + (int64_t)k * per_comp;
+          fmd.desc = desc_index;
+          fmd.slice = sl;
+          const int fam_index = (int)dfam.size();
+          dfam.push_back(fmd);
+          dshape.push_back({np, dim});
+          const int64_t tile0 = (int64_t)dtile.size();
+          for (int t2 = 0; t2 < ntile[2]; ++t2)
+            for (int t1 = 0; t1 < ntile[1]; ++t1)
+              for (int t0 = 0; t0 < ntile[0]; ++t0) {
+                DenseTile tl;
+                std::memset(&tl, 0, sizeof(tl));
+                tl.fam = fam_index;
+                tl.tc[0] = t0;
+                tl.tc[1] = t1;
+                tl.tc[2] = t2;
+                tl.slot = slot;
+                tl.trace_off = trace_total;
+                trace_total += 3LL * slot;
+                const int tcs[3] = {t0, t1, t2};
+                const int tstr[3] = {1, ntile[0], ntile[0] * ntile[1]};
+                const int64_t me = tile0 + t0 + (int64_t)ntile[0] * (t1 + (int64_t)ntile[1] * t2);
+                for (int a = 0; a < 3; ++a) {
+                  tl.up[a] = (dd.sgn[a] != 0 && tcs[a] > 0) ? (int32_t)(me - tstr[a]) : -1;
+                  tl.down[a] = (dd.sgn[a] != 0 && tcs[a] + 1 < ntile[a]) ? (int32_t)(me + tstr[a]) : -1;
+                }
+                dtile.push_back(tl);
+              }
+        }
+    }
+  }
+  // launch groups by (d+1, D); claim order: tiles by diagonal, so every tile's
+  // upwind tiles are claimed before it
+  std::vector<DenseTile> dtile_sorted;
+  std::vector<int32_t> dorder;
+  std::vector<DenseGroup> dgroups;
+  int64_t sync_total = 0;
+  {
+    std::map<std::pair<int, int>, std::vector<int64_t>> by_shape;
+    for (size_t i = 0; i < dtile.size(); ++i) by_shape[dshape[dtile[i].fam]].push_back((int64_t)i);
+    std::vector<int64_t> new_index(dtile.size(), -1);
+    for (auto &kv : by_shape) {
+      DenseGroup g;
+      g.np = kv.first.first;
+      g.dim = kv.first.second;
+      g.first = (int64_t)dtile_sorted.size();
+      g.count = (int64_t)kv.second.size();
+      g.sync_off = sync_total;
+      sync_total += 1 + g.count;
+      for (int64_t i : kv.second) {
+        new_index[i] = (int64_t)dtile_sorted.size() - g.first;  // index within the group
+        dtile_sorted.push_back(dtile[i]);
+      }
+      dgroups.push_back(g);
+    }
+    // remap neighbour indices to group-local indices, build claim orders
+    for (DenseGroup &g : dgroups) {
+      std::vector<std::pair<int, int32_t>> diag;
+      for (int64_t i = 0; i < g.count; ++i) {
+        DenseTile &tl = dtile_sorted[g.first + i];
+        for (int a = 0; a < 3; ++a) {
+          if (tl.up[a] >= 0) tl.up[a] = (int32_t)new_index[tl.up[a]];
+          if (tl.down[a] >= 0) tl.down[a] = (int32_t)new_index[tl.down[a]];
+        }
+        diag.push_back({tl.tc[0] + tl.tc[1] + tl.tc[2], (int32_t)i});
+      }
+      std::stable_sort(diag.begin(), diag.end(),
+                       [](const std::pair<int, int32_t> &x, const std::pair<int, int32_t> &y) { return x.first < y.first; });
+      for (const auto &di : diag) dorder.push_back(di.second);
+    }
+  }
+
   // ---- relax tables --------------------------------------------------------
   std::vector<RelaxDesc> rdesc;
   std::map<std::pair<int, int>, std::vector<RelaxItem>> ritems_by;
@@ -813,9 +1064,11 @@ pdg_status pdg_prepare(pdg_ctx *c, double dt, double theta, double omega, pdg_sc
     rd.dim = in.d.dim;
     rd.feq = in.d.feq;
     // the equilibrium needs the full {+-lambda e_k} set
-    double lam = std::fabs(in.v[(size_t)0 * in.d.dim + in.axis[0]]);
-    int seen[3][2] = {{0, 0}, {0, 0}, {0, 0}};
     bool ok = in.d.nv == 2 * in.d.dim;
+    for (int v = 0; v < in.d.nv; ++v)
+      if (in.axis[v] < 0) ok = false;
+    const double lam = ok ? std::fabs(in.v[(size_t)0 * in.d.dim + in.axis[0]]) : 0.0;
+    int seen[3][2] = {{0, 0}, {0, 0}, {0, 0}};
     for (int v = 0; v < in.d.nv && ok; ++v) {
       const double sp = std::fabs(in.v[(size_t)v * in.d.dim + in.axis[v]]);
       if (sp != lam) ok = false;
@@ -889,6 +1142,65 @@ pdg_status pdg_prepare(pdg_ctx *c, double dt, double theta, double omega, pdg_sc
       c->release_device();
       return PDG_ESINGULAR;
     }
+  // dense path: tables, tiles, and the device inversion of the dense blocks
+  PREP_TRY(c->ddesc.upload(ddesc))
+  PREP_TRY(c->dfams.upload(dfam))
+  PREP_TRY(c->dtiles.upload(dtile_sorted))
+  PREP_TRY(c->dorder.upload(dorder))
+  PREP_TRY(c->dtable.upload(dtable))
+  PREP_TRY(c->dtraces.upload(std::vector<double>((size_t)trace_total, 0.0)))
+  PREP_TRY(c->dsync.upload(std::vector<int32_t>((size_t)sync_total, 0)))
+  PREP_TRY(c->derr.upload(std::vector<int32_t>(1, 0)))
+  if (!drow_off.empty()) {
+    std::map<std::pair<int, int>, std::vector<size_t>> rows_by_shape;
+    for (size_t r = 0; r < drow_off.size(); ++r) {
+      const DenseDesc &dd = ddesc[drow_desc[r]];
+      int np2 = 0, dim2 = 0;
+      // recover (d+1, D) from the descriptor's instance
+      for (size_t f2 = 0; f2 < dfam.size(); ++f2)
+        if (dfam[f2].desc == drow_desc[r]) {
+          np2 = dshape[f2].first;
+          dim2 = dshape[f2].second;
+          break;
+        }
+      (void)dd;
+      rows_by_shape[{np2, dim2}].push_back(r);
+    }
+    for (auto &kv : rows_by_shape) {
+      const int np2 = kv.first.first, dim2 = kv.first.second;
+      const int n2 = dim2 == 2 ? np2 * np2 : np2 * np2 * np2;
+      const int F2 = dim2 == 2 ? np2 : np2 * np2;
+      std::vector<int64_t> ro;
+      std::vector<int32_t> rd;
+      std::vector<double> rc;
+      for (size_t r : kv.second) {
+        ro.push_back(drow_off[r]);
+        rd.push_back(drow_desc[r]);
+        for (int a = 0; a < 3; ++a) rc.push_back(drow_c0[3 * r + a]);
+      }
+      DevBuf<int64_t> d_ro;
+      DevBuf<int32_t> d_rd, d_fl;
+      DevBuf<double> d_rc;
+      PREP_TRY(d_ro.upload(ro))
+      PREP_TRY(d_rd.upload(rd))
+      PREP_TRY(d_rc.upload(rc))
+      PREP_TRY(d_fl.upload(std::vector<int32_t>(ro.size(), 0)))
+      PREP_TRY(launch_dense_invert(c->dtable.p, d_ro.p, c->ddesc.p, d_rd.p, d_rc.p, d_fl.p, (int)ro.size(), n2, F2, st))
+      PREP_TRY(hipStreamSynchronize(st))
+      std::vector<int32_t> fl(ro.size());
+      PREP_TRY(hipMemcpy(fl.data(), d_fl.p, fl.size() * sizeof(int32_t), hipMemcpyDeviceToHost))
+      d_ro.release();
+      d_rd.release();
+      d_rc.release();
+      d_fl.release();
+      for (int32_t x : fl)
+        if (x) {
+          c->release_device();
+          return PDG_ESINGULAR;
+        }
+    }
+  }
+  c->dgroups = dgroups;
   PREP_TRY(hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking))
 #undef PREP_TRY
   c->rgroups = rgroups;
@@ -918,6 +1230,14 @@ pdg_status do_sweep(pdg_ctx *c, void *f, const double *fb_old, const double *fb_
       std::snprintf(what, sizeof(what), "launch_sweep(np=%d,items=%lld)", g.np, (long long)g.count);
       return from_hip_at(e, what);
     }
+  }
+  for (const DenseGroup &g : c->dgroups) {
+    hipError_t e = launch_fill_int(c->dsync.p + g.sync_off, 1 + g.count, 0, st);
+    if (e == hipSuccess)
+      e = launch_dense_sweep(c->prec, g.np, g.dim, c->dtiles.p + g.first, c->dorder.p + g.first, (int)g.count,
+                             c->dfams.p, c->ddesc.p, c->dtable.p, dt_idx, f, fb_old, fb_new, c->dtraces.p,
+                             c->dsync.p + g.sync_off, c->dsync.p + g.sync_off + 1, c->derr.p, st);
+    if (e != hipSuccess) return from_hip_at(e, "launch_dense_sweep");
   }
   c->stats_valid = c->prec == PDG_FP32_REFINE;
   c->last_stream = st;
@@ -1214,6 +1534,22 @@ pdg_status pdg_last_refine_correction(const pdg_ctx *c, double *max_rel_correcti
     ym = std::max(ym, h[i + 1]);
   }
   *max_rel_correction = ym > 0 ? cm / ym : 0.0;
+  return PDG_OK;
+}
+
+pdg_status pdg_sync_status(pdg_ctx *c) {
+  if (!c) return PDG_EINVAL;
+  if (!c->prepared) return PDG_ESTATE;
+  HIP_TRY(hipStreamSynchronize(c->last_stream));
+  HIP_TRY(hipGetLastError());
+  int32_t err = 0;
+  HIP_TRY(hipMemcpy(&err, c->derr.p, sizeof(err), hipMemcpyDeviceToHost));
+  if (err) {
+    const int32_t zero = 0;
+    HIP_TRY(hipMemcpy(c->derr.p, &zero, sizeof(zero), hipMemcpyHostToDevice));
+    std::snprintf(g_detail, sizeof(g_detail), "dense sweep: a wait for an upwind tile timed out");
+    return PDG_EDEVICE;
+  }
   return PDG_OK;
 }
 

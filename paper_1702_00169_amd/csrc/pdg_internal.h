@@ -91,6 +91,52 @@ struct InflowDesc {
   int32_t vel;
 };
 
+// ---- velocities with two or three non-zero components ---------------------
+// The cell block is dense and the dependency graph is a k-dimensional
+// wavefront over the axes with non-zero components.  Cells are grouped in
+// tiles (8 x 8 for k = 2, 4 x 4 x 4 for k = 3); a tile waits for its upwind
+// tiles and sweeps its own diagonals.
+constexpr int kDenseMaxN = 27;      // (d+1)^D cell nodes handled by the dense path
+constexpr int kDenseMaxF = 9;       // (d+1)^(D-1) face nodes
+constexpr int kDenseThreads = 64;   // one thread per cell of a tile
+
+// One (instance, velocity) of the dense path.
+struct DenseDesc {
+  int64_t nc;                        // cells
+  int64_t plane_off[kDenseMaxN];     // element offset of downwind-local node q's plane
+  int64_t fb_axis_off[3];            // offset of axis a's face block inside a (v, k) fb block
+  int64_t fb_ntc[3];                 // cells on the inflow face of axis a (Nc / n_a)
+  int64_t op_off;                    // dense operator table offset of dt index 0 (doubles)
+  int64_t op_stride;                 // doubles per dt index
+  int32_t n[3];                      // cells per axis
+  int32_t sgn[3];                    // sign of the velocity component per axis (0: zero)
+  int32_t T[3];                      // tile extent per axis (1 on zero components)
+  int32_t face_q[3][kDenseMaxF];     // local node of inflow-face node t of axis a (q_a = 0)
+  int32_t out_q[3][kDenseMaxF];      // local node of outflow-face node t of axis a (q_a = NP-1)
+  int32_t fb_t[3][kDenseMaxF];       // physical face-node index (fb layout) of face node t
+  int32_t trans_axis;                // zero-component axis whose cells are independent, or -1
+  double theta;
+};
+
+// One (instance, velocity, component, transverse slice) sweep.
+struct DenseFam {
+  int64_t f_base;   // element offset of (instance, v, k, plane 0, cell 0)
+  int64_t fb_base;  // fb offset of (instance, v, k)
+  int32_t desc;
+  int32_t slice;    // cell index along trans_axis (0 if none)
+};
+
+// One tile of a dense sweep.
+struct DenseTile {
+  int64_t trace_off;  // offset of this tile's inflow-trace slots (one per axis)
+  int32_t fam;
+  int32_t tc[3];      // tile coordinates (downwind order), 0 on zero components
+  int32_t up[3];      // upwind tile per axis, -1 on the domain boundary or zero component
+  int32_t down[3];    // downwind tile per axis, -1 if none
+  int32_t slot;       // doubles per axis slot of trace_off
+  int32_t pad;
+};
+
 // ---- kernel launchers (pdg_kernels.hip) ----------------------------------
 enum Prec { kF64 = 0, kF32 = 1, kRefine = 2 };
 
@@ -110,6 +156,22 @@ hipError_t launch_inflow_eq(int nv, int m, const InflowDesc *items, int n_items,
                             const double *w_inflow, double *fb, hipStream_t st);
 
 hipError_t launch_fill(double *p, int64_t n, double value, hipStream_t st);
+hipError_t launch_fill_int(int32_t *p, int64_t n, int32_t value, hipStream_t st);
+
+// Dense cell blocks: per operator row, A and B (n x n) and the inflow
+// coefficients c0[3] are set; computes Ainv, M = Ainv B and the face columns
+// G_a = c0_a Ainv[:, face_q[a][t]].  Row layout (doubles): M, G[3] (n x F each),
+// A, B, Ainv; flags[row] = 1 if A is singular.
+hipError_t launch_dense_invert(double *table, const int64_t *row_off, const DenseDesc *descs,
+                               const int32_t *row_desc, const double *c0, int32_t *flags, int n_rows, int n,
+                               int F, hipStream_t st);
+
+// Dense sweep of n_tiles tiles (claim order `order`); counter and flags must be
+// zero on entry; err_flag is set if a wait times out.
+hipError_t launch_dense_sweep(int prec, int np, int dim, const DenseTile *tiles, const int32_t *order,
+                              int n_tiles, const DenseFam *fams, const DenseDesc *descs, const double *table,
+                              int dt_idx, void *f, const double *fb_old, const double *fb_new, double *traces,
+                              int32_t *counter, int32_t *flags, int32_t *err_flag, hipStream_t st);
 
 
 }  // namespace pdg

@@ -41,6 +41,8 @@
 #include <float.h>
 #include <math.h>
 
+#include <algorithm>
+
 #include "pdg_internal.h"
 
 #ifndef PDG_NONTEMPORAL
@@ -620,6 +622,326 @@ __global__ void fill_kernel(double *p, int64_t n, double value) {
 }
 
 // ---------------------------------------------------------------------------
+// dense path: velocities with two or three non-zero components
+// ---------------------------------------------------------------------------
+// Operator row layout (doubles): M (N x N) | G_0 G_1 G_2 (N x F each) | A | B | Ainv
+struct DenseRowLayout {
+  int64_t n, f;
+  __host__ __device__ int64_t g(int a) const { return n * n + a * n * f; }
+  __host__ __device__ int64_t a_off() const { return n * n + 3 * n * f; }
+  __host__ __device__ int64_t b_off() const { return 2 * n * n + 3 * n * f; }
+  __host__ __device__ int64_t ai_off() const { return 3 * n * n + 3 * n * f; }
+};
+
+__global__ __launch_bounds__(kDenseThreads) void dense_invert_kernel(double *table, const int64_t *row_off,
+                                                                    const DenseDesc *descs,
+                                                                    const int32_t *row_desc, const double *c0,
+                                                                    int32_t *flags, int n, int F) {
+  __shared__ double a[kDenseMaxN][kDenseMaxN + 1];
+  __shared__ double inv[kDenseMaxN][kDenseMaxN + 1];
+  __shared__ double fct[kDenseMaxN];
+  __shared__ double norm;
+  __shared__ int piv, sing;
+  const int r = blockIdx.x;
+  const int t = threadIdx.x;
+  double *row = table + row_off[r];
+  const DenseRowLayout L{n, F};
+  for (int e = t; e < n * n; e += kDenseThreads) {
+    const int i = e / n, j = e - (e / n) * n;
+    a[i][j] = row[L.a_off() + e];
+    inv[i][j] = (i == j) ? 1.0 : 0.0;
+  }
+  __syncthreads();
+  if (t == 0) {
+    double m = 0.0;
+    for (int i = 0; i < n; ++i)
+      for (int j = 0; j < n; ++j) m = fmax(m, fabs(a[i][j]));
+    norm = m;
+    sing = 0;
+  }
+  __syncthreads();
+  for (int col = 0; col < n; ++col) {
+    if (t == 0) {
+      int pv = col;
+      for (int i = col + 1; i < n; ++i)
+        if (fabs(a[i][col]) > fabs(a[pv][col])) pv = i;
+      piv = pv;
+      if (!(fabs(a[pv][col]) > 1e-300 * norm)) sing = 1;
+    }
+    __syncthreads();
+    if (sing) break;
+    if (piv != col) {
+      for (int j = t; j < n; j += kDenseThreads) {
+        double tmp = a[col][j];
+        a[col][j] = a[piv][j];
+        a[piv][j] = tmp;
+        tmp = inv[col][j];
+        inv[col][j] = inv[piv][j];
+        inv[piv][j] = tmp;
+      }
+    }
+    __syncthreads();
+    const double rp = 1.0 / a[col][col];
+    __syncthreads();
+    for (int j = t; j < n; j += kDenseThreads) {
+      a[col][j] *= rp;
+      inv[col][j] *= rp;
+    }
+    __syncthreads();
+    for (int i = t; i < n; i += kDenseThreads) fct[i] = (i == col) ? 0.0 : a[i][col];
+    __syncthreads();
+    for (int e = t; e < n * n; e += kDenseThreads) {
+      const int i = e / n, j = e - (e / n) * n;
+      if (i == col) continue;
+      a[i][j] = fma(-fct[i], a[col][j], a[i][j]);
+      inv[i][j] = fma(-fct[i], inv[col][j], inv[i][j]);
+    }
+    __syncthreads();
+  }
+  if (t == 0) flags[r] = sing;
+  if (sing) return;
+  const DenseDesc &d = descs[row_desc[r]];
+  for (int e = t; e < n * n; e += kDenseThreads) {
+    const int i = e / n, j = e - (e / n) * n;
+    double acc = 0.0;
+    for (int k = 0; k < n; ++k) acc = fma(inv[i][k], row[L.b_off() + (int64_t)k * n + j], acc);
+    row[e] = acc;                       // M = Ainv B
+    row[L.ai_off() + e] = inv[i][j];    // Ainv
+  }
+  for (int e = t; e < 3 * n * F; e += kDenseThreads) {
+    const int ax = e / (n * F);
+    const int rem = e - ax * n * F;
+    const int i = rem / F, tt = rem - (rem / F) * F;
+    const double c = c0[3 * r + ax];
+    row[L.g(ax) + (int64_t)i * F + tt] = (c == 0.0) ? 0.0 : c * inv[i][d.face_q[ax][tt]];
+  }
+}
+
+// downwind-local node index of face node t on the face q_a = qa of axis a
+template <int NP, int DIM>
+__device__ constexpr int face_node(int a, int t, int qa) {
+  int q = 0, stride = 1, rem = t;
+  for (int b = 0; b < DIM; ++b) {
+    int qb;
+    if (b == a) {
+      qb = qa;
+    } else {
+      qb = rem % NP;
+      rem /= NP;
+    }
+    q += qb * stride;
+    stride *= NP;
+  }
+  return q;
+}
+
+template <int PREC, int NP, int DIM>
+__global__ __launch_bounds__(kDenseThreads) void dense_sweep_kernel(
+    const DenseTile *__restrict__ tiles, const int32_t *__restrict__ order, const DenseFam *__restrict__ fams,
+    const DenseDesc *__restrict__ descs, const double *__restrict__ table, int dt_idx,
+    typename Pol<PREC>::St *__restrict__ f, const double *__restrict__ fb_old, const double *__restrict__ fb_new,
+    double *traces, int32_t *counter, int32_t *flags, int32_t *err_flag) {
+  using St = typename Pol<PREC>::St;
+  using Rt = typename Pol<PREC>::Rt;
+  constexpr int N = DIM == 2 ? NP * NP : NP * NP * NP;
+  constexpr int F = DIM == 2 ? NP : NP * NP;
+  __shared__ int s_tile;
+  __shared__ Rt otr[3][kDenseThreads][F];  // outflow traces per axis of every cell of the tile
+  const int t = threadIdx.x;
+  if (t == 0) s_tile = order[atomicAdd(counter, 1)];
+  __syncthreads();
+  const int tile = s_tile;
+  const DenseTile tl = tiles[tile];
+  const DenseFam fm = fams[tl.fam];
+  const DenseDesc &d = descs[fm.desc];
+  // wait for the upwind tiles (bounded: a timeout is reported, never a hang)
+  if (t == 0) {
+    for (int a = 0; a < DIM; ++a) {
+      if (tl.up[a] < 0) continue;
+      // upwind tiles were claimed earlier and never wait on this one, so the
+      // wait ends; the wall-clock bound (about a second at the 100 MHz
+      // constant clock) turns a logic error into a reported failure
+      int ok = 0;
+      const uint64_t t_start = wall_clock64();
+      while (true) {
+        if (__hip_atomic_load(flags + tl.up[a], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) != 0) {
+          ok = 1;
+          break;
+        }
+        if (wall_clock64() - t_start > 100000000ull) break;
+        __builtin_amdgcn_s_sleep(2);
+      }
+      if (!ok) atomicOr(err_flag, 1);
+    }
+  }
+  __syncthreads();
+  __threadfence();
+
+  // this thread's cell: local coordinates over the non-zero components
+  int cl[3] = {0, 0, 0}, tstride[3] = {0, 0, 0};
+  int rem = t, st_acc = 1;
+  bool active = true;
+#pragma unroll
+  for (int a = 0; a < DIM; ++a) {
+    if (d.sgn[a] == 0) continue;
+    cl[a] = rem % d.T[a];
+    rem /= d.T[a];
+    tstride[a] = st_acc;
+    st_acc *= d.T[a];
+  }
+  if (rem != 0) active = false;
+  int x[3] = {0, 0, 0};
+#pragma unroll
+  for (int a = 0; a < DIM; ++a) {
+    if (d.sgn[a] == 0) {
+      x[a] = (a == d.trans_axis) ? fm.slice : 0;
+    } else {
+      const int p = tl.tc[a] * d.T[a] + cl[a];
+      if (p >= d.n[a]) active = false;
+      x[a] = d.sgn[a] > 0 ? p : d.n[a] - 1 - p;
+    }
+  }
+  const int64_t cell = x[0] + (int64_t)d.n[0] * (x[1] + (int64_t)d.n[1] * x[2]);
+  const double *row = table + d.op_off + (int64_t)dt_idx * d.op_stride;
+  const DenseRowLayout L{N, F};
+
+  // load the cell and apply the local block
+  Rt fv[N], y[N];
+#pragma unroll
+  for (int q = 0; q < N; ++q) fv[q] = active ? (Rt)ld_state(f + fm.f_base + d.plane_off[q] + cell) : (Rt)0;
+  if (PREC == kRefine) {
+    double r[N];
+    float r32[N], y1[N];
+#pragma unroll
+    for (int i = 0; i < N; ++i) {
+      double acc = 0.0;
+#pragma unroll
+      for (int j = 0; j < N; ++j) acc = fma(row[L.b_off() + i * N + j], (double)fv[j], acc);
+      r[i] = acc;
+      r32[i] = (float)acc;
+    }
+#pragma unroll
+    for (int i = 0; i < N; ++i) {
+      float acc = 0.f;
+#pragma unroll
+      for (int j = 0; j < N; ++j) acc = fmaf((float)row[L.ai_off() + i * N + j], r32[j], acc);
+      y1[i] = acc;
+    }
+#pragma unroll
+    for (int i = 0; i < N; ++i) {
+      double acc = r[i];
+#pragma unroll
+      for (int j = 0; j < N; ++j) acc = fma(-row[L.a_off() + i * N + j], (double)y1[j], acc);
+      r32[i] = (float)acc;
+    }
+#pragma unroll
+    for (int i = 0; i < N; ++i) {
+      float acc = 0.f;
+#pragma unroll
+      for (int j = 0; j < N; ++j) acc = fmaf((float)row[L.ai_off() + i * N + j], r32[j], acc);
+      y[i] = (Rt)((double)y1[i] + (double)acc);
+    }
+  } else {
+#pragma unroll
+    for (int i = 0; i < N; ++i) {
+      Rt acc = 0;
+#pragma unroll
+      for (int j = 0; j < N; ++j) acc = fma((Rt)row[i * N + j], fv[j], acc);
+      y[i] = acc;
+    }
+  }
+  const Rt th = (Rt)d.theta;
+  const Rt omt = (Rt)1 - th;
+
+  int diag = 0, ndiag = 1;
+#pragma unroll
+  for (int a = 0; a < DIM; ++a)
+    if (d.sgn[a] != 0) {
+      diag += cl[a];
+      ndiag += d.T[a] - 1;
+    }
+  for (int s = 0; s < ndiag; ++s) {
+    if (active && diag == s) {
+#pragma unroll
+      for (int a = 0; a < DIM; ++a) {
+        if (d.sgn[a] == 0) continue;
+        // face cell index of this cell on faces normal to a (tile-local)
+        int fc = 0, fs = 1;
+#pragma unroll
+        for (int b = 0; b < DIM; ++b)
+          if (b != a && d.sgn[b] != 0) {
+            fc += cl[b] * fs;
+            fs *= d.T[b];
+          }
+        Rt u[F];
+        if (cl[a] > 0) {
+#pragma unroll
+          for (int tt = 0; tt < F; ++tt) u[tt] = otr[a][t - tstride[a]][tt];
+        } else if (tl.up[a] >= 0) {
+#pragma unroll
+          for (int tt = 0; tt < F; ++tt) u[tt] = (Rt)traces[tl.trace_off + (int64_t)a * tl.slot + fc * F + tt];
+        } else {
+          // domain inflow face: transverse cell index over the other axes
+          int64_t tau = 0, ts = 1;
+#pragma unroll
+          for (int b = 0; b < DIM; ++b)
+            if (b != a) {
+              tau += x[b] * ts;
+              ts *= d.n[b];
+            }
+          const int64_t base = fm.fb_base + d.fb_axis_off[a] + tau;
+#pragma unroll
+          for (int tt = 0; tt < F; ++tt) {
+            const int64_t k = base + (int64_t)d.fb_t[a][tt] * d.fb_ntc[a];
+            u[tt] = th * (Rt)fb_new[k] + omt * (Rt)fb_old[k];
+          }
+        }
+#pragma unroll
+        for (int i = 0; i < N; ++i) {
+          Rt acc = y[i];
+#pragma unroll
+          for (int tt = 0; tt < F; ++tt) acc = fma((Rt)row[L.g(a) + i * F + tt], u[tt], acc);
+          y[i] = acc;
+        }
+      }
+#pragma unroll
+      for (int q = 0; q < N; ++q) st_state(f + fm.f_base + d.plane_off[q] + cell, (St)y[q]);
+      // outflow traces: theta x + (1 - theta) f^n on each downwind face
+#pragma unroll
+      for (int b = 0; b < DIM; ++b) {
+        if (d.sgn[b] == 0) continue;
+        int fc = 0, fs = 1;
+#pragma unroll
+        for (int a2 = 0; a2 < DIM; ++a2)
+          if (a2 != b && d.sgn[a2] != 0) {
+            fc += cl[a2] * fs;
+            fs *= d.T[a2];
+          }
+        const bool to_next = cl[b] == d.T[b] - 1 && tl.down[b] >= 0;
+        const DenseTile *dn = to_next ? tiles + tl.down[b] : nullptr;
+#pragma unroll
+        for (int tt = 0; tt < F; ++tt) {
+          const int q = face_node<NP, DIM>(b, tt, NP - 1);
+          const Rt o = th * y[q] + omt * fv[q];
+          otr[b][t][tt] = o;
+          if (to_next) traces[dn->trace_off + (int64_t)b * dn->slot + fc * F + tt] = (double)o;
+        }
+      }
+    }
+    __syncthreads();
+  }
+  // publish: traces written above are made visible before the flag
+  __threadfence();
+  __syncthreads();
+  if (t == 0) __hip_atomic_store(flags + tile, 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+__global__ void fill_int_kernel(int32_t *p, int64_t n, int32_t value) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    p[i] = value;
+}
+
+// ---------------------------------------------------------------------------
 // dispatch
 // ---------------------------------------------------------------------------
 template <int PREC, int NP>
@@ -736,6 +1058,66 @@ hipError_t launch_inflow_eq(int nv, int m, const InflowDesc *items, int n_items,
   switch (nv) {
     case 4: return go_inflow_m<4>(m, items, n_items, descs, w_inflow, fb, st);
     case 6: return go_inflow_m<6>(m, items, n_items, descs, w_inflow, fb, st);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+hipError_t launch_fill_int(int32_t *p, int64_t n, int32_t value, hipStream_t st) {
+  if (n <= 0) return hipSuccess;
+  const int grid = (int)std::min<int64_t>(1024, (n + 255) / 256);
+  hipLaunchKernelGGL(fill_int_kernel, dim3(grid), dim3(256), 0, st, p, n, value);
+  return hipGetLastError();
+}
+
+hipError_t launch_dense_invert(double *table, const int64_t *row_off, const DenseDesc *descs,
+                               const int32_t *row_desc, const double *c0, int32_t *flags, int n_rows, int n,
+                               int F, hipStream_t st) {
+  if (n_rows <= 0) return hipSuccess;
+  if (n > kDenseMaxN || F > kDenseMaxF) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(dense_invert_kernel, dim3(n_rows), dim3(kDenseThreads), 0, st, table, row_off, descs, row_desc,
+                     c0, flags, n, F);
+  return hipGetLastError();
+}
+
+template <int PREC, int NP, int DIM>
+hipError_t go_dense(const DenseTile *tiles, const int32_t *order, int n_tiles, const DenseFam *fams,
+                    const DenseDesc *descs, const double *table, int dt_idx, void *f, const double *fb_old,
+                    const double *fb_new, double *traces, int32_t *counter, int32_t *flags, int32_t *err,
+                    hipStream_t st) {
+  using St = typename Pol<PREC>::St;
+  hipLaunchKernelGGL((dense_sweep_kernel<PREC, NP, DIM>), dim3(n_tiles), dim3(kDenseThreads), 0, st, tiles, order,
+                     fams, descs, table, dt_idx, static_cast<St *>(f), fb_old, fb_new, traces, counter, flags, err);
+  return hipGetLastError();
+}
+
+template <int PREC>
+hipError_t go_dense_shape(int np, int dim, const DenseTile *tiles, const int32_t *order, int n_tiles,
+                          const DenseFam *fams, const DenseDesc *descs, const double *table, int dt_idx, void *f,
+                          const double *fb_old, const double *fb_new, double *traces, int32_t *counter,
+                          int32_t *flags, int32_t *err, hipStream_t st) {
+#define PDG_DENSE_CASE(NPV, DIMV)                                                                             \
+  if (np == NPV && dim == DIMV)                                                                               \
+    return go_dense<PREC, NPV, DIMV>(tiles, order, n_tiles, fams, descs, table, dt_idx, f, fb_old, fb_new,   \
+                                     traces, counter, flags, err, st);
+  PDG_DENSE_CASE(2, 2)
+  PDG_DENSE_CASE(3, 2)
+  PDG_DENSE_CASE(4, 2)
+  PDG_DENSE_CASE(5, 2)
+  PDG_DENSE_CASE(2, 3)
+  PDG_DENSE_CASE(3, 3)
+#undef PDG_DENSE_CASE
+  return hipErrorInvalidValue;
+}
+
+hipError_t launch_dense_sweep(int prec, int np, int dim, const DenseTile *tiles, const int32_t *order,
+                              int n_tiles, const DenseFam *fams, const DenseDesc *descs, const double *table,
+                              int dt_idx, void *f, const double *fb_old, const double *fb_new, double *traces,
+                              int32_t *counter, int32_t *flags, int32_t *err_flag, hipStream_t st) {
+  if (n_tiles <= 0) return hipSuccess;
+  switch (prec) {
+    case kF64: return go_dense_shape<kF64>(np, dim, tiles, order, n_tiles, fams, descs, table, dt_idx, f, fb_old, fb_new, traces, counter, flags, err_flag, st);
+    case kF32: return go_dense_shape<kF32>(np, dim, tiles, order, n_tiles, fams, descs, table, dt_idx, f, fb_old, fb_new, traces, counter, flags, err_flag, st);
+    case kRefine: return go_dense_shape<kRefine>(np, dim, tiles, order, n_tiles, fams, descs, table, dt_idx, f, fb_old, fb_new, traces, counter, flags, err_flag, st);
     default: return hipErrorInvalidValue;
   }
 }

@@ -30,37 +30,41 @@ def sizes(inst):
     return nc, nd
 
 
-def inflow_blocks(inst):
-    """[(v, axis, tnodes, ntc)] in fb order."""
-    out = []
+def inflow_faces(inst, v):
+    """[(axis, tnodes, ntc)] of the inflow face blocks of velocity v (one per
+    non-zero component, increasing axis)."""
     nc, _ = sizes(inst)
-    for v in range(inst.vel.shape[0]):
-        ax = int(np.nonzero(inst.vel[v])[0][0])
-        out.append((v, ax, (inst.degree + 1) ** (inst.dim - 1), nc // inst.n[ax]))
-    return out
+    tn = (inst.degree + 1) ** (inst.dim - 1)
+    return [(a, tn, nc // inst.n[a]) for a in range(inst.dim) if inst.vel[v][a] != 0]
 
 
 def gpu_inflow_points(prob, i, inst):
-    """List per velocity of (npts, D) inflow coordinates in fb order."""
+    """Per velocity, the list of (npts, D) coordinate arrays of its face blocks."""
     _, inflow = prob.node_coords(i)
-    pts = []
+    out = []
     off = 0
-    for v, ax, tn, ntc in inflow_blocks(inst):
-        blk = inflow[off:off + inst.dim * tn * ntc].reshape(inst.dim, tn * ntc)
-        pts.append(blk.T.copy())
-        off += inst.dim * tn * ntc
-    return pts
+    for v in range(inst.vel.shape[0]):
+        faces = []
+        for a, tn, ntc in inflow_faces(inst, v):
+            blk = inflow[off:off + inst.dim * tn * ntc].reshape(inst.dim, tn * ntc)
+            faces.append(blk.T.copy())
+            off += inst.dim * tn * ntc
+        out.append(faces)
+    return out
 
 
 def gpu_fb_from_function(prob, insts, fn_of_inst_v):
-    """fb (numpy, fb layout) with value fn(i, v, pts) -> (m, npts)."""
+    """fb (numpy, fb layout [v][k][face][t][tau]) with value fn(i, v, pts) -> (m, npts)."""
     fb = np.zeros(prob.layout["fb_elems"])
     for i, inst in enumerate(insts):
         off = prob.layout["fb_off"][i]
-        for (v, ax, tn, ntc), pts in zip(inflow_blocks(inst), gpu_inflow_points(prob, i, inst)):
-            vals = fn_of_inst_v(i, v, pts)
-            fb[off:off + vals.size] = vals.ravel()
-            off += vals.size
+        for v, faces in enumerate(gpu_inflow_points(prob, i, inst)):
+            if not faces:
+                continue
+            vals = [fn_of_inst_v(i, v, pts) for pts in faces]   # each (m, npts_face)
+            blk = np.concatenate(vals, axis=1)                  # (m, sum npts)
+            fb[off:off + blk.size] = blk.ravel()
+            off += blk.size
     return fb
 
 

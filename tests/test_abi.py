@@ -186,3 +186,89 @@ def test_host_cell_operator_is_the_oracle_block(lib, degree, vel):
     fc = [f for f in blk.faces if f["axis"] == ax and f["side"] == -s][0]
     np.testing.assert_allclose(fc["coef"][0], -kappa, rtol=1e-13)
     prob.close()
+
+
+D2Q9 = [[0, 0], [1, 0], [0, 1], [-1, 0], [0, -1], [1, 1], [-1, 1], [-1, -1], [1, -1]]
+
+
+@pytest.mark.parametrize("dim,degree,vel", [
+    (2, 2, (1.0, 1.0)), (2, 3, (-0.7, 0.4)), (2, 1, (0.3, -1.1)), (2, 4, (-1.0, -1.0)), (2, 2, (0.0, 0.0)),
+    (3, 2, (1.0, -1.0, 0.5)), (3, 1, (0.0, 0.8, -0.3)), (3, 2, (0.0, 0.0, -1.0)),
+])
+def test_host_dense_cell_operator_is_the_oracle_block(lib, dim, degree, vel):
+    """Gamma_{L<-L} of any velocity, downwind-local order, == oracle block."""
+    hi = [1.0, 1.7, 0.6][:dim]
+    n = [3, 2, 2][:dim]
+    prob = lib.Problem([_desc(dim=dim, n=n, degree=degree, v=[list(vel)], hi=hi, lo=[0.0] * dim)])
+    npn = degree + 1
+    nd = npn ** dim
+    gam = np.zeros(nd * nd)
+    kap = np.zeros(3)
+    lib.pdg_cell_operator(prob.ctx, 0, 0, gam, kap)
+    gam = gam.reshape(nd, nd)
+    m = omesh.Mesh(tuple(n), np.zeros(dim), np.array(hi), degree)
+    blk = otr.cell_blocks(m, np.array(vel), np.array([1]))
+    idx = m.node_idx
+    # oracle node i (physical tensor index) -> downwind-local index q
+    q = np.zeros(nd, dtype=np.int64)
+    for i in range(nd):
+        for a in range(dim):
+            qa = idx[i, a] if vel[a] >= 0 else degree - idx[i, a]
+            q[i] += qa * npn ** a
+    np.testing.assert_allclose(gam[np.ix_(q, q)], blk.gll[0], rtol=1e-13,
+                               atol=1e-13 * max(1.0, np.abs(blk.gll[0]).max()))
+    for fc in blk.faces:
+        a = fc["axis"]
+        if vel[a] == 0 or fc["side"] != (-1 if vel[a] > 0 else 1):
+            continue
+        np.testing.assert_allclose(fc["coef"][0], -kap[a], rtol=1e-13)
+    for a in range(dim):
+        if vel[a] == 0:
+            assert kap[a] == 0.0
+    prob.close()
+
+
+def test_d2q9_setup_layout_and_levels(lib):
+    prob = lib.Problem([_desc(n=[5, 4], degree=2, v=D2Q9)])
+    lay = prob.layout
+    # fb: one face block per non-zero component: axis-aligned 3*n_other, diagonal both faces
+    per = [0, 3 * 4, 3 * 5, 3 * 4, 3 * 5] + [3 * 4 + 3 * 5] * 4
+    assert lay["fb_elems"] == sum(per)
+    m = omesh.Mesh((5, 4), np.zeros(2), np.ones(2), 2)
+    for v in range(9):
+        lev = np.zeros(20, np.int32)
+        lib.pdg_levels(prob.ctx, 0, v, lev)
+        np.testing.assert_array_equal(lev, otr.topological_levels(m, D2Q9[v]))
+    # inflow coordinates, velocity by velocity, == oracle inflow entries
+    _, inflow = prob.node_coords(0)
+    off = 0
+    for v in range(9):
+        ent = otr.inflow_entries(m, np.array(D2Q9[v], float))
+        npts = ent["coords"].shape[0]
+        if npts == 0:
+            assert vel_is_zero(D2Q9[v])
+            continue
+        pts = np.concatenate([b.T for b in _split_faces(inflow[off:off + 2 * npts], D2Q9[v], (5, 4), 3)])
+        a = pts[np.lexsort(np.round(pts, 12).T[::-1])]
+        b = ent["coords"][np.lexsort(np.round(ent["coords"], 12).T[::-1])]
+        np.testing.assert_allclose(a, b, atol=1e-14)
+        off += 2 * npts
+    prob.close()
+
+
+def vel_is_zero(v):
+    return all(c == 0 for c in v)
+
+
+def _split_faces(flat, vel, n, npn):
+    """Split one velocity's inflow coordinate block into its face blocks (D, t*tau)."""
+    dim = len(n)
+    out = []
+    off = 0
+    for a in range(dim):
+        if vel[a] == 0:
+            continue
+        npts = npn ** (dim - 1) * int(np.prod(n)) // n[a]
+        out.append(flat[off:off + dim * npts].reshape(dim, npts))
+        off += dim * npts
+    return out

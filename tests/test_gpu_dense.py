@@ -1,0 +1,107 @@
+"""GPU parity of the transport sweep for velocities with two or three
+non-zero components (dense cell blocks, tiled wavefront) and for the zero
+velocity, on the paper's D2Q9 and D3Q27 velocity sets (Sec. 4.5, figure of
+the D2Q9 / D3Q27 grids), against the oracle's level sweep."""
+import itertools
+
+import numpy as np
+import pytest
+
+import workloads as W
+from helpers import (gpu_fb_from_function, gpu_to_oracle, inst_dict, oracle_fb_from_function, oracle_problem,
+                     oracle_to_gpu, rel_errors, sizes)
+from oracle import transport as otr
+
+pytestmark = pytest.mark.gpu
+
+D2Q9 = np.array([[0, 0], [1, 0], [0, 1], [-1, 0], [0, -1], [1, 1], [-1, 1], [-1, -1], [1, -1]], float)
+D3Q27 = np.array(list(itertools.product([0, 1, -1], repeat=3)), float)
+
+CASES = [
+    # name, dim, n, degree, velocities, m
+    ("d2q9_16x16_d2", 2, (16, 16), 2, D2Q9, 1),
+    ("d2q9_37x23_d3_m2", 2, (37, 23), 3, D2Q9 * 0.7, 2),
+    ("d2q9_9x30_d1", 2, (9, 30), 1, D2Q9, 1),
+    ("d2q9_5x6_d4", 2, (5, 6), 4, D2Q9 * 1.3, 1),
+    ("d3q27_9x7x5_d1", 3, (9, 7, 5), 1, D3Q27, 1),
+    ("d3q27_6x5x7_d2_m2", 3, (6, 5, 7), 2, D3Q27 * 0.8, 2),
+    ("d3q27_12x9x10_d2", 3, (12, 9, 10), 2, D3Q27, 1),
+]
+BARS = {0: 1e-12, 2: 1e-10, 1: 2e-5}
+
+
+@pytest.fixture(scope="module")
+def lib():
+    import paper_1702_00169_amd as P
+    return P
+
+
+def _instance(case):
+    name, dim, n, degree, vel, m = case
+    inst = W.Instance(dim, n, degree, 1.0, m, "advection", {"a": [0.1] * dim}, W.uniform_state([1.0] * m))
+    inst.vel = np.asarray(vel, float)
+    inst.hi = np.array([1.0, 1.7, 0.6][:dim])
+    return inst
+
+
+def _run(lib, torch, case, prec, theta=0.5, half=False, seed=0):
+    inst = _instance(case)
+    print(f"dense case={case[0]} prec={prec} theta={theta} half={half}", flush=True)
+    prob = lib.Problem([inst_dict(inst)])
+    nc, nd = sizes(inst)
+    h = np.min((inst.hi - inst.lo) / np.array(inst.n))
+    dt = 0.77 * h / np.max(np.abs(inst.vel))
+    prob.prepare(dt, theta=theta, omega=2.0, precision=prec)
+    nv, m = inst.vel.shape[0], inst.m
+    f_or = W.random_state(seed, (nv, m, nc, nd))
+    if prec == 1:
+        f_or = f_or.astype(np.float32).astype(np.float64)
+    fo = W.smooth_field(seed + 1, inst.dim, m)
+    fn = W.smooth_field(seed + 2, inst.dim, m)
+    fbo = torch.tensor(gpu_fb_from_function(prob, [inst], lambda i, v, p: fo(p)), device="cuda")
+    fbn = torch.tensor(gpu_fb_from_function(prob, [inst], lambda i, v, p: fn(p)), device="cuda")
+    f = torch.tensor(oracle_to_gpu(f_or), dtype=torch.float32 if prec == 1 else torch.float64, device="cuda")
+    dsub = 0.5 * dt if half else dt
+    prob.transport_sweep(f, fbo, fbn, dsub)
+    prob.sync_status()
+    got = gpu_to_oracle(f.double().cpu().numpy(), inst)
+    oprob = oracle_problem(inst)
+    ofo = oracle_fb_from_function(oprob, 0, lambda i, v, p: fo(p))
+    ofn = oracle_fb_from_function(oprob, 0, lambda i, v, p: fn(p))
+    want = np.empty_like(f_or)
+    for v in range(nv):
+        want[v] = otr.theta_step_sweep(oprob.mesh, inst.vel[v], f_or[v], ofo[v], ofn[v], dsub, theta,
+                                       levels=oprob.levels(v))
+    per_v = [rel_errors(got[v], want[v])[0] for v in range(nv)]
+    prob.close()
+    return rel_errors(got, want), per_v
+
+
+@pytest.mark.parametrize("case", CASES, ids=[c[0] for c in CASES])
+@pytest.mark.parametrize("prec", [0, 2, 1], ids=["fp64", "fp32refine", "fp32"])
+def test_dense_sweep_matches_oracle(lib, case, prec):
+    torch = pytest.importorskip("torch")
+    (l2, mx), per_v = _run(lib, torch, case, prec)
+    print(f"  rel L2 {l2:.3e} max {mx:.3e}; worst velocity {max(per_v):.3e}")
+    assert l2 <= BARS[prec] and mx <= 10 * BARS[prec] and max(per_v) <= 10 * BARS[prec]
+
+
+@pytest.mark.parametrize("theta,half", [(1.0, False), (0.5, True), (0.6, False)])
+def test_dense_sweep_theta_and_half_step(lib, theta, half):
+    torch = pytest.importorskip("torch")
+    (l2, mx), _ = _run(lib, torch, CASES[1], 0, theta, half, seed=4)
+    assert l2 <= 1e-12 and mx <= 1e-11
+
+
+def test_zero_velocity_is_identity(lib):
+    torch = pytest.importorskip("torch")
+    inst = _instance(("z", 2, (7, 5), 2, np.zeros((1, 2)), 1))
+    prob = lib.Problem([inst_dict(inst)])
+    prob.prepare(0.1)
+    f = torch.rand(prob.layout["f_elems"], dtype=torch.float64, device="cuda")
+    g = f.clone()
+    fb = torch.zeros(max(1, prob.layout["fb_elems"]), dtype=torch.float64, device="cuda")
+    prob.transport_sweep(f, fb, fb, 0.1)
+    prob.sync_status()
+    assert torch.equal(f, g)
+    prob.close()
