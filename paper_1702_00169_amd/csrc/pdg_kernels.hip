@@ -740,7 +740,7 @@ __global__ __launch_bounds__(kDenseThreads) void dense_sweep_kernel(
     const DenseTile *__restrict__ tiles, const int32_t *__restrict__ order, const DenseFam *__restrict__ fams,
     const DenseDesc *__restrict__ descs, const double *__restrict__ table, int dt_idx,
     typename Pol<PREC>::St *__restrict__ f, const double *__restrict__ fb_old, const double *__restrict__ fb_new,
-    double *traces, int32_t *counter, int32_t *flags, int32_t *err_flag) {
+    double *traces, int32_t *counter, int32_t *flags, int32_t *err_flag, int n_tiles) {
   using St = typename Pol<PREC>::St;
   using Rt = typename Pol<PREC>::Rt;
   constexpr int N = DIM == 2 ? NP * NP : NP * NP * NP;
@@ -748,19 +748,27 @@ __global__ __launch_bounds__(kDenseThreads) void dense_sweep_kernel(
   __shared__ int s_tile;
   __shared__ Rt otr[3][kDenseThreads][F];  // outflow traces per axis of every cell of the tile
   const int t = threadIdx.x;
-  if (t == 0) s_tile = order[atomicAdd(counter, 1)];
+  // persistent loop: claim tiles in dependency order until none is left
+  for (;;) {
+  if (t == 0) {
+    const int i = atomicAdd(counter, 1);
+    s_tile = i < n_tiles ? order[i] : -1;
+  }
   __syncthreads();
   const int tile = s_tile;
+  if (tile < 0) break;
   const DenseTile tl = tiles[tile];
   const DenseFam fm = fams[tl.fam];
   const DenseDesc &d = descs[fm.desc];
-  // wait for the upwind tiles (bounded: a timeout is reported, never a hang)
+  // wait for the upwind tiles.  The flag is polled with agent-scope acquire
+  // loads: each XCD has its own L2, and only the acquire (which invalidates
+  // the local caches) is guaranteed to see another XCD's release.  Upwind
+  // tiles were claimed earlier and never wait on this one, so the wait ends;
+  // the wall-clock bound (0.2 s at the 100 MHz constant clock) turns a logic
+  // error into a reported failure instead of a hang.
   if (t == 0) {
     for (int a = 0; a < DIM; ++a) {
       if (tl.up[a] < 0) continue;
-      // upwind tiles were claimed earlier and never wait on this one, so the
-      // wait ends; the wall-clock bound (about a second at the 100 MHz
-      // constant clock) turns a logic error into a reported failure
       int ok = 0;
       const uint64_t t_start = wall_clock64();
       while (true) {
@@ -768,14 +776,13 @@ __global__ __launch_bounds__(kDenseThreads) void dense_sweep_kernel(
           ok = 1;
           break;
         }
-        if (wall_clock64() - t_start > 100000000ull) break;
-        __builtin_amdgcn_s_sleep(2);
+        if (wall_clock64() - t_start > 20000000ull) break;
+        __builtin_amdgcn_s_sleep(8);
       }
       if (!ok) atomicOr(err_flag, 1);
     }
   }
   __syncthreads();
-  __threadfence();
 
   // this thread's cell: local coordinates over the non-zero components
   int cl[3] = {0, 0, 0}, tstride[3] = {0, 0, 0};
@@ -930,10 +937,14 @@ __global__ __launch_bounds__(kDenseThreads) void dense_sweep_kernel(
     }
     __syncthreads();
   }
-  // publish: traces written above are made visible before the flag
-  __threadfence();
+  // publish: the barrier orders every wave's trace stores before thread 0's
+  // agent-scope release, which makes them visible before the flag
   __syncthreads();
-  if (t == 0) __hip_atomic_store(flags + tile, 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+  if (t == 0) {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+    __hip_atomic_store(flags + tile, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  }
+  }  // claim loop
 }
 
 __global__ void fill_int_kernel(int32_t *p, int64_t n, int32_t value) {
@@ -1085,8 +1096,12 @@ hipError_t go_dense(const DenseTile *tiles, const int32_t *order, int n_tiles, c
                     const double *fb_new, double *traces, int32_t *counter, int32_t *flags, int32_t *err,
                     hipStream_t st) {
   using St = typename Pol<PREC>::St;
-  hipLaunchKernelGGL((dense_sweep_kernel<PREC, NP, DIM>), dim3(n_tiles), dim3(kDenseThreads), 0, st, tiles, order,
-                     fams, descs, table, dt_idx, static_cast<St *>(f), fb_old, fb_new, traces, counter, flags, err);
+  // persistent grid: enough workgroups to cover the wavefront, each claims
+  // tiles until the counter passes n_tiles
+  const int grid = std::min(n_tiles, 2048);
+  hipLaunchKernelGGL((dense_sweep_kernel<PREC, NP, DIM>), dim3(grid), dim3(kDenseThreads), 0, st, tiles, order,
+                     fams, descs, table, dt_idx, static_cast<St *>(f), fb_old, fb_new, traces, counter, flags, err,
+                     n_tiles);
   return hipGetLastError();
 }
 
