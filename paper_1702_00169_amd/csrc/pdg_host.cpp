@@ -58,7 +58,7 @@ struct RelaxGroup {
 struct DenseGroup {
   int np, dim;
   int64_t first, count;  // tile range (tiles and claim order)
-  int64_t sync_off;      // counter at sync_off, flags at sync_off + 1 ..
+  int64_t sync_off;      // index of the group's tile-claim counter
 };
 
 // One (instance, velocity) family of chains and its launch class.
@@ -132,9 +132,9 @@ struct pdg_ctx {
   DevBuf<DenseTile> dtiles;
   DevBuf<int32_t> dorder;
   DevBuf<double> dtable;
-  DevBuf<double> dtraces;
-  DevBuf<int32_t> dsync;     // per group: counter + one flag per tile
-  DevBuf<int32_t> derr;      // wait-timeout flag
+  DevBuf<uint64_t> dtraces;  // inflow-trace slots of the dense tiles (binary64 bits)
+  DevBuf<int32_t> dsync;     // per group: tile-claim counter
+  DevBuf<int32_t> derr;      // 1: a trace wait timed out, 2: claim counter overrun
   DevBuf<RelaxDesc> rdesc;
   DevBuf<RelaxItem> ritems;
   std::vector<RelaxGroup> rgroups;
@@ -1021,7 +1021,7 @@ pdg_status pdg_prepare(pdg_ctx *c, double dt, double theta, double omega, pdg_sc
       g.first = (int64_t)dtile_sorted.size();
       g.count = (int64_t)kv.second.size();
       g.sync_off = sync_total;
-      sync_total += 1 + g.count;
+      sync_total += 1;
       for (int64_t i : kv.second) {
         new_index[i] = (int64_t)dtile_sorted.size() - g.first;  // index within the group
         dtile_sorted.push_back(dtile[i]);
@@ -1148,7 +1148,7 @@ pdg_status pdg_prepare(pdg_ctx *c, double dt, double theta, double omega, pdg_sc
   PREP_TRY(c->dtiles.upload(dtile_sorted))
   PREP_TRY(c->dorder.upload(dorder))
   PREP_TRY(c->dtable.upload(dtable))
-  PREP_TRY(c->dtraces.upload(std::vector<double>((size_t)trace_total, 0.0)))
+  PREP_TRY(c->dtraces.upload(std::vector<uint64_t>((size_t)trace_total, kDenseTraceEmpty)))
   PREP_TRY(c->dsync.upload(std::vector<int32_t>((size_t)sync_total, 0)))
   PREP_TRY(c->derr.upload(std::vector<int32_t>(1, 0)))
   if (!drow_off.empty()) {
@@ -1231,12 +1231,17 @@ pdg_status do_sweep(pdg_ctx *c, void *f, const double *fb_old, const double *fb_
       return from_hip_at(e, what);
     }
   }
+  if (!c->dgroups.empty()) {
+    // every trace slot empty, every claim counter at zero (fill kernels, so
+    // that the sequence can be captured into a graph)
+    hipError_t e = launch_fill_u64(c->dtraces.p, c->dtraces.n, kDenseTraceEmpty, st);
+    if (e == hipSuccess) e = launch_fill_int(c->dsync.p, (int64_t)c->dgroups.size(), 0, st);
+    if (e != hipSuccess) return from_hip_at(e, "dense sweep reset");
+  }
   for (const DenseGroup &g : c->dgroups) {
-    hipError_t e = launch_fill_int(c->dsync.p + g.sync_off, 1 + g.count, 0, st);
-    if (e == hipSuccess)
-      e = launch_dense_sweep(c->prec, g.np, g.dim, c->dtiles.p + g.first, c->dorder.p + g.first, (int)g.count,
-                             c->dfams.p, c->ddesc.p, c->dtable.p, dt_idx, f, fb_old, fb_new, c->dtraces.p,
-                             c->dsync.p + g.sync_off, c->dsync.p + g.sync_off + 1, c->derr.p, st);
+    hipError_t e = launch_dense_sweep(c->prec, g.np, g.dim, c->dtiles.p + g.first, c->dorder.p + g.first,
+                                      (int)g.count, c->dfams.p, c->ddesc.p, c->dtable.p, dt_idx, f, fb_old, fb_new,
+                                      c->dtraces.p, c->dsync.p + g.sync_off, c->derr.p, st);
     if (e != hipSuccess) return from_hip_at(e, "launch_dense_sweep");
   }
   c->stats_valid = c->prec == PDG_FP32_REFINE;
@@ -1547,7 +1552,9 @@ pdg_status pdg_sync_status(pdg_ctx *c) {
   if (err) {
     const int32_t zero = 0;
     HIP_TRY(hipMemcpy(c->derr.p, &zero, sizeof(zero), hipMemcpyHostToDevice));
-    std::snprintf(g_detail, sizeof(g_detail), "dense sweep: a wait for an upwind tile timed out");
+    std::snprintf(g_detail, sizeof(g_detail), "%s",
+                  (err & 2) ? "dense sweep: tile-claim counter overrun"
+                            : "dense sweep: a wait for an upwind trace timed out");
     return PDG_EDEVICE;
   }
   return PDG_OK;

@@ -98,7 +98,10 @@ struct InflowDesc {
 // tiles and sweeps its own diagonals.
 constexpr int kDenseMaxN = 27;      // (d+1)^D cell nodes handled by the dense path
 constexpr int kDenseMaxF = 9;       // (d+1)^(D-1) face nodes
-constexpr int kDenseThreads = 64;   // one thread per cell of a tile
+constexpr int kDenseThreads = 64;   // one thread per cell of a tile; one wave per tile
+// content of an inflow-trace slot that has not been written yet in this sweep
+// (a signalling NaN: arithmetic only ever produces quiet NaNs)
+constexpr uint64_t kDenseTraceEmpty = 0x7ff4c0ffee5a1e57ull;
 
 // One (instance, velocity) of the dense path.
 struct DenseDesc {
@@ -157,6 +160,7 @@ hipError_t launch_inflow_eq(int nv, int m, const InflowDesc *items, int n_items,
 
 hipError_t launch_fill(double *p, int64_t n, double value, hipStream_t st);
 hipError_t launch_fill_int(int32_t *p, int64_t n, int32_t value, hipStream_t st);
+hipError_t launch_fill_u64(uint64_t *p, int64_t n, uint64_t value, hipStream_t st);
 
 // Dense cell blocks: per operator row, A and B (n x n) and the inflow
 // coefficients c0[3] are set; computes Ainv, M = Ainv B and the face columns
@@ -170,8 +174,8 @@ hipError_t launch_dense_invert(double *table, const int64_t *row_off, const Dens
 // zero on entry; err_flag is set if a wait times out.
 hipError_t launch_dense_sweep(int prec, int np, int dim, const DenseTile *tiles, const int32_t *order,
                               int n_tiles, const DenseFam *fams, const DenseDesc *descs, const double *table,
-                              int dt_idx, void *f, const double *fb_old, const double *fb_new, double *traces,
-                              int32_t *counter, int32_t *flags, int32_t *err_flag, hipStream_t st);
+                              int dt_idx, void *f, const double *fb_old, const double *fb_new, uint64_t *traces,
+                              int32_t *counter, int32_t *err_flag, hipStream_t st);
 
 
 }  // namespace pdg

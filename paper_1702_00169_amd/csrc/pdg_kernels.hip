@@ -722,7 +722,7 @@ template <int NP, int DIM>
 __device__ constexpr int face_node(int a, int t, int qa) {
   int q = 0, stride = 1, rem = t;
   for (int b = 0; b < DIM; ++b) {
-    int qb;
+    int qb = 0;
     if (b == a) {
       qb = qa;
     } else {
@@ -735,54 +735,78 @@ __device__ constexpr int face_node(int a, int t, int qa) {
   return q;
 }
 
+// Cross-tile hand-off.  A tile's inflow traces are written by its upwind
+// tiles, which may run on another XCD (each XCD has its own L2).  Every trace
+// value is written once per sweep, into a slot that was filled with a
+// signalling-NaN sentinel before the launch; arithmetic never produces a
+// signalling NaN, so a slot that no longer holds the sentinel holds its final
+// value.  Both sides use device-scope atomic read-modify-writes, which are
+// performed at the device's point of coherence, so no cache-wide write-back or
+// invalidation is needed and each cell waits only for its own upwind cell.
+// Current content of a trace slot, read with a compare-and-swap that writes
+// the sentinel back only where it already is (an idempotent or-with-zero
+// would be turned into a plain load by the compiler).
+__device__ inline uint64_t dense_peek_trace(uint64_t *p) {
+  uint64_t cur = kDenseTraceEmpty;
+  __hip_atomic_compare_exchange_strong(p, &cur, kDenseTraceEmpty, __ATOMIC_RELAXED, __ATOMIC_RELAXED,
+                                       __HIP_MEMORY_SCOPE_AGENT);
+  return cur;
+}
+
+__device__ inline double dense_take_trace(uint64_t *p, int32_t *err_flag) {
+  uint64_t b = dense_peek_trace(p);
+  if (b != kDenseTraceEmpty) return __longlong_as_double((long long)b);
+  // The producer was claimed earlier and is resident, so the wait ends; the
+  // wall-clock bound (1 s at the 100 MHz constant clock) and the shared error
+  // flag turn a logic error into one reported failure instead of a hang.
+  const uint64_t t_start = wall_clock64();
+  for (;;) {
+    __builtin_amdgcn_s_sleep(1);
+    b = dense_peek_trace(p);
+    if (b != kDenseTraceEmpty) return __longlong_as_double((long long)b);
+    if (wall_clock64() - t_start > 100000000ull ||
+        __hip_atomic_load(err_flag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0) {
+      __hip_atomic_fetch_or(err_flag, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      return 0.0;
+    }
+  }
+}
+
+__device__ inline void dense_put_trace(uint64_t *p, double v) {
+  __hip_atomic_exchange(p, (uint64_t)__double_as_longlong(v), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// One wave per tile.  The tile index is claimed by lane 0 from a counter that
+// hands out tiles in dependency order (upwind tiles first) and broadcast with
+// readfirstlane, so it is wave-uniform: descriptors and operator rows are read
+// through scalar loads and all control flow that depends on the tile is
+// uniform.  Inside the tile the cells are solved diagonal by diagonal; the
+// inflow traces of a cell come from the previous diagonal through LDS, from an
+// upwind tile through the trace slots, or from the domain inflow data.
 template <int PREC, int NP, int DIM>
 __global__ __launch_bounds__(kDenseThreads) void dense_sweep_kernel(
     const DenseTile *__restrict__ tiles, const int32_t *__restrict__ order, const DenseFam *__restrict__ fams,
     const DenseDesc *__restrict__ descs, const double *__restrict__ table, int dt_idx,
     typename Pol<PREC>::St *__restrict__ f, const double *__restrict__ fb_old, const double *__restrict__ fb_new,
-    double *traces, int32_t *counter, int32_t *flags, int32_t *err_flag, int n_tiles) {
+    uint64_t *traces, int32_t *counter, int32_t *err_flag, int n_tiles) {
+  static_assert(kDenseThreads == 64, "one workgroup is one wave");
   using St = typename Pol<PREC>::St;
   using Rt = typename Pol<PREC>::Rt;
   constexpr int N = DIM == 2 ? NP * NP : NP * NP * NP;
   constexpr int F = DIM == 2 ? NP : NP * NP;
-  __shared__ int s_tile;
   __shared__ Rt otr[3][kDenseThreads][F];  // outflow traces per axis of every cell of the tile
   const int t = threadIdx.x;
-  // persistent loop: claim tiles in dependency order until none is left
-  for (;;) {
-  if (t == 0) {
-    const int i = atomicAdd(counter, 1);
-    s_tile = i < n_tiles ? order[i] : -1;
+  int claim = 0;
+  if (t == 0) claim = atomicAdd(counter, 1);
+  claim = __builtin_amdgcn_readfirstlane(claim);
+  if (claim >= n_tiles) {  // the counter was not reset: report, do nothing
+    if (t == 0) __hip_atomic_fetch_or(err_flag, 2, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    return;
   }
-  __syncthreads();
-  const int tile = s_tile;
-  if (tile < 0) break;
+  const int tile = order[claim];
   const DenseTile tl = tiles[tile];
   const DenseFam fm = fams[tl.fam];
   const DenseDesc &d = descs[fm.desc];
-  // wait for the upwind tiles.  The flag is polled with agent-scope acquire
-  // loads: each XCD has its own L2, and only the acquire (which invalidates
-  // the local caches) is guaranteed to see another XCD's release.  Upwind
-  // tiles were claimed earlier and never wait on this one, so the wait ends;
-  // the wall-clock bound (0.2 s at the 100 MHz constant clock) turns a logic
-  // error into a reported failure instead of a hang.
-  if (t == 0) {
-    for (int a = 0; a < DIM; ++a) {
-      if (tl.up[a] < 0) continue;
-      int ok = 0;
-      const uint64_t t_start = wall_clock64();
-      while (true) {
-        if (__hip_atomic_load(flags + tl.up[a], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) != 0) {
-          ok = 1;
-          break;
-        }
-        if (wall_clock64() - t_start > 20000000ull) break;
-        __builtin_amdgcn_s_sleep(8);
-      }
-      if (!ok) atomicOr(err_flag, 1);
-    }
-  }
-  __syncthreads();
 
   // this thread's cell: local coordinates over the non-zero components
   int cl[3] = {0, 0, 0}, tstride[3] = {0, 0, 0};
@@ -885,8 +909,9 @@ __global__ __launch_bounds__(kDenseThreads) void dense_sweep_kernel(
 #pragma unroll
           for (int tt = 0; tt < F; ++tt) u[tt] = otr[a][t - tstride[a]][tt];
         } else if (tl.up[a] >= 0) {
+          uint64_t *src = traces + tl.trace_off + (int64_t)a * tl.slot + fc * F;
 #pragma unroll
-          for (int tt = 0; tt < F; ++tt) u[tt] = (Rt)traces[tl.trace_off + (int64_t)a * tl.slot + fc * F + tt];
+          for (int tt = 0; tt < F; ++tt) u[tt] = (Rt)dense_take_trace(src + tt, err_flag);
         } else {
           // domain inflow face: transverse cell index over the other axes
           int64_t tau = 0, ts = 1;
@@ -925,29 +950,30 @@ __global__ __launch_bounds__(kDenseThreads) void dense_sweep_kernel(
             fs *= d.T[a2];
           }
         const bool to_next = cl[b] == d.T[b] - 1 && tl.down[b] >= 0;
-        const DenseTile *dn = to_next ? tiles + tl.down[b] : nullptr;
+        uint64_t *dst = nullptr;
+        if (to_next) {
+          const DenseTile &dn = tiles[tl.down[b]];
+          dst = traces + dn.trace_off + (int64_t)b * dn.slot + fc * F;
+        }
 #pragma unroll
         for (int tt = 0; tt < F; ++tt) {
           const int q = face_node<NP, DIM>(b, tt, NP - 1);
           const Rt o = th * y[q] + omt * fv[q];
           otr[b][t][tt] = o;
-          if (to_next) traces[dn->trace_off + (int64_t)b * dn->slot + fc * F + tt] = (double)o;
+          if (to_next) dense_put_trace(dst + tt, (double)o);
         }
       }
     }
     __syncthreads();
   }
-  // publish: the barrier orders every wave's trace stores before thread 0's
-  // agent-scope release, which makes them visible before the flag
-  __syncthreads();
-  if (t == 0) {
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
-    __hip_atomic_store(flags + tile, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-  }
-  }  // claim loop
 }
 
 __global__ void fill_int_kernel(int32_t *p, int64_t n, int32_t value) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    p[i] = value;
+}
+
+__global__ void fill_u64_kernel(uint64_t *p, int64_t n, uint64_t value) {
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
     p[i] = value;
 }
@@ -1080,6 +1106,13 @@ hipError_t launch_fill_int(int32_t *p, int64_t n, int32_t value, hipStream_t st)
   return hipGetLastError();
 }
 
+hipError_t launch_fill_u64(uint64_t *p, int64_t n, uint64_t value, hipStream_t st) {
+  if (n <= 0) return hipSuccess;
+  const int grid = (int)std::min<int64_t>(1024, (n + 255) / 256);
+  hipLaunchKernelGGL(fill_u64_kernel, dim3(grid), dim3(256), 0, st, p, n, value);
+  return hipGetLastError();
+}
+
 hipError_t launch_dense_invert(double *table, const int64_t *row_off, const DenseDesc *descs,
                                const int32_t *row_desc, const double *c0, int32_t *flags, int n_rows, int n,
                                int F, hipStream_t st) {
@@ -1093,27 +1126,23 @@ hipError_t launch_dense_invert(double *table, const int64_t *row_off, const Dens
 template <int PREC, int NP, int DIM>
 hipError_t go_dense(const DenseTile *tiles, const int32_t *order, int n_tiles, const DenseFam *fams,
                     const DenseDesc *descs, const double *table, int dt_idx, void *f, const double *fb_old,
-                    const double *fb_new, double *traces, int32_t *counter, int32_t *flags, int32_t *err,
-                    hipStream_t st) {
+                    const double *fb_new, uint64_t *traces, int32_t *counter, int32_t *err, hipStream_t st) {
   using St = typename Pol<PREC>::St;
-  // persistent grid: enough workgroups to cover the wavefront, each claims
-  // tiles until the counter passes n_tiles
-  const int grid = std::min(n_tiles, 2048);
-  hipLaunchKernelGGL((dense_sweep_kernel<PREC, NP, DIM>), dim3(grid), dim3(kDenseThreads), 0, st, tiles, order,
-                     fams, descs, table, dt_idx, static_cast<St *>(f), fb_old, fb_new, traces, counter, flags, err,
-                     n_tiles);
+  // one wave per tile; the counter hands the tiles out in dependency order
+  hipLaunchKernelGGL((dense_sweep_kernel<PREC, NP, DIM>), dim3(n_tiles), dim3(kDenseThreads), 0, st, tiles, order,
+                     fams, descs, table, dt_idx, static_cast<St *>(f), fb_old, fb_new, traces, counter, err, n_tiles);
   return hipGetLastError();
 }
 
 template <int PREC>
 hipError_t go_dense_shape(int np, int dim, const DenseTile *tiles, const int32_t *order, int n_tiles,
                           const DenseFam *fams, const DenseDesc *descs, const double *table, int dt_idx, void *f,
-                          const double *fb_old, const double *fb_new, double *traces, int32_t *counter,
-                          int32_t *flags, int32_t *err, hipStream_t st) {
+                          const double *fb_old, const double *fb_new, uint64_t *traces, int32_t *counter,
+                          int32_t *err, hipStream_t st) {
 #define PDG_DENSE_CASE(NPV, DIMV)                                                                             \
   if (np == NPV && dim == DIMV)                                                                               \
     return go_dense<PREC, NPV, DIMV>(tiles, order, n_tiles, fams, descs, table, dt_idx, f, fb_old, fb_new,   \
-                                     traces, counter, flags, err, st);
+                                     traces, counter, err, st);
   PDG_DENSE_CASE(2, 2)
   PDG_DENSE_CASE(3, 2)
   PDG_DENSE_CASE(4, 2)
@@ -1126,13 +1155,13 @@ hipError_t go_dense_shape(int np, int dim, const DenseTile *tiles, const int32_t
 
 hipError_t launch_dense_sweep(int prec, int np, int dim, const DenseTile *tiles, const int32_t *order,
                               int n_tiles, const DenseFam *fams, const DenseDesc *descs, const double *table,
-                              int dt_idx, void *f, const double *fb_old, const double *fb_new, double *traces,
-                              int32_t *counter, int32_t *flags, int32_t *err_flag, hipStream_t st) {
+                              int dt_idx, void *f, const double *fb_old, const double *fb_new, uint64_t *traces,
+                              int32_t *counter, int32_t *err_flag, hipStream_t st) {
   if (n_tiles <= 0) return hipSuccess;
   switch (prec) {
-    case kF64: return go_dense_shape<kF64>(np, dim, tiles, order, n_tiles, fams, descs, table, dt_idx, f, fb_old, fb_new, traces, counter, flags, err_flag, st);
-    case kF32: return go_dense_shape<kF32>(np, dim, tiles, order, n_tiles, fams, descs, table, dt_idx, f, fb_old, fb_new, traces, counter, flags, err_flag, st);
-    case kRefine: return go_dense_shape<kRefine>(np, dim, tiles, order, n_tiles, fams, descs, table, dt_idx, f, fb_old, fb_new, traces, counter, flags, err_flag, st);
+    case kF64: return go_dense_shape<kF64>(np, dim, tiles, order, n_tiles, fams, descs, table, dt_idx, f, fb_old, fb_new, traces, counter, err_flag, st);
+    case kF32: return go_dense_shape<kF32>(np, dim, tiles, order, n_tiles, fams, descs, table, dt_idx, f, fb_old, fb_new, traces, counter, err_flag, st);
+    case kRefine: return go_dense_shape<kRefine>(np, dim, tiles, order, n_tiles, fams, descs, table, dt_idx, f, fb_old, fb_new, traces, counter, err_flag, st);
     default: return hipErrorInvalidValue;
   }
 }
