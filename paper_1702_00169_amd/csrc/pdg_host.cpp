@@ -59,6 +59,7 @@ struct DenseGroup {
   int np, dim;
   int64_t first, count;  // tile range (tiles and claim order)
   int64_t sync_off;      // index of the group's tile-claim counter
+  std::vector<int64_t> level;  // claim-order offsets where each tile diagonal starts (+ count)
 };
 
 // One (instance, velocity) family of chains and its launch class.
@@ -134,6 +135,7 @@ struct pdg_ctx {
   DevBuf<double> dtable;
   DevBuf<uint64_t> dtraces;  // inflow-trace slots of the dense tiles (binary64 bits)
   DevBuf<int32_t> dsync;     // per group: tile-claim counter
+  bool dense_level = true;    // dense tiles: one launch per tile diagonal (else one claimed launch)
   DevBuf<int32_t> derr;      // 1: a trace wait timed out, 2: claim counter overrun
   DevBuf<RelaxDesc> rdesc;
   DevBuf<RelaxItem> ritems;
@@ -1041,7 +1043,11 @@ pdg_status pdg_prepare(pdg_ctx *c, double dt, double theta, double omega, pdg_sc
       }
       std::stable_sort(diag.begin(), diag.end(),
                        [](const std::pair<int, int32_t> &x, const std::pair<int, int32_t> &y) { return x.first < y.first; });
-      for (const auto &di : diag) dorder.push_back(di.second);
+      for (size_t k = 0; k < diag.size(); ++k) {
+        if (k == 0 || diag[k].first != diag[k - 1].first) g.level.push_back((int64_t)k);
+        dorder.push_back(diag[k].second);
+      }
+      g.level.push_back(g.count);
     }
   }
 
@@ -1212,6 +1218,11 @@ pdg_status pdg_prepare(pdg_ctx *c, double dt, double theta, double omega, pdg_sc
   c->tau = tau;
   c->scheme = scheme;
   c->prec = prec;
+  // dense-path schedule: per-diagonal launches unless PDG_DENSE_SCHEDULE=claim
+  {
+    const char *ds = std::getenv("PDG_DENSE_SCHEDULE");
+    c->dense_level = !(ds && std::strcmp(ds, "claim") == 0);
+  }
   c->prepared = true;
   return PDG_OK;
 }
@@ -1231,7 +1242,7 @@ pdg_status do_sweep(pdg_ctx *c, void *f, const double *fb_old, const double *fb_
       return from_hip_at(e, what);
     }
   }
-  if (!c->dgroups.empty()) {
+  if (!c->dgroups.empty() && !c->dense_level) {
     // every trace slot empty, every claim counter at zero (fill kernels, so
     // that the sequence can be captured into a graph)
     hipError_t e = launch_fill_u64(c->dtraces.p, c->dtraces.n, kDenseTraceEmpty, st);
@@ -1239,7 +1250,18 @@ pdg_status do_sweep(pdg_ctx *c, void *f, const double *fb_old, const double *fb_
     if (e != hipSuccess) return from_hip_at(e, "dense sweep reset");
   }
   for (const DenseGroup &g : c->dgroups) {
-    hipError_t e = launch_dense_sweep(c->prec, g.np, g.dim, c->dtiles.p + g.first, c->dorder.p + g.first,
+    if (c->dense_level) {
+      // one launch per tile diagonal: no tile ever waits
+      for (size_t k = 0; k + 1 < g.level.size(); ++k) {
+        hipError_t e = launch_dense_sweep(c->prec, true, g.np, g.dim, c->dtiles.p + g.first,
+                                          c->dorder.p + g.first + g.level[k], (int)(g.level[k + 1] - g.level[k]),
+                                          c->dfams.p, c->ddesc.p, c->dtable.p, dt_idx, f, fb_old, fb_new,
+                                          c->dtraces.p, c->dsync.p + g.sync_off, c->derr.p, st);
+        if (e != hipSuccess) return from_hip_at(e, "launch_dense_sweep(level)");
+      }
+      continue;
+    }
+    hipError_t e = launch_dense_sweep(c->prec, false, g.np, g.dim, c->dtiles.p + g.first, c->dorder.p + g.first,
                                       (int)g.count, c->dfams.p, c->ddesc.p, c->dtable.p, dt_idx, f, fb_old, fb_new,
                                       c->dtraces.p, c->dsync.p + g.sync_off, c->derr.p, st);
     if (e != hipSuccess) return from_hip_at(e, "launch_dense_sweep");

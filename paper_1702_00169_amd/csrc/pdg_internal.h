@@ -172,7 +172,7 @@ hipError_t launch_dense_invert(double *table, const int64_t *row_off, const Dens
 
 // Dense sweep of n_tiles tiles (claim order `order`); counter and flags must be
 // zero on entry; err_flag is set if a wait times out.
-hipError_t launch_dense_sweep(int prec, int np, int dim, const DenseTile *tiles, const int32_t *order,
+hipError_t launch_dense_sweep(int prec, bool level, int np, int dim, const DenseTile *tiles, const int32_t *order,
                               int n_tiles, const DenseFam *fams, const DenseDesc *descs, const double *table,
                               int dt_idx, void *f, const double *fb_old, const double *fb_new, uint64_t *traces,
                               int32_t *counter, int32_t *err_flag, hipStream_t st);

@@ -753,21 +753,51 @@ __device__ inline uint64_t dense_peek_trace(uint64_t *p) {
   return cur;
 }
 
-__device__ inline double dense_take_trace(uint64_t *p, int32_t *err_flag) {
-  uint64_t b = dense_peek_trace(p);
-  if (b != kDenseTraceEmpty) return __longlong_as_double((long long)b);
-  // The producer was claimed earlier and is resident, so the wait ends; the
-  // wall-clock bound (1 s at the 100 MHz constant clock) and the shared error
-  // flag turn a logic error into one reported failure instead of a hang.
+// The inflow traces a cell needs from upwind tiles (up to one face per axis).
+// Every slot is requested at once, so a ready face costs one round trip; the
+// slots still empty are polled again after a short sleep.  The producer was
+// claimed earlier and is resident, so the wait ends; the wall-clock bound
+// (1 s at the 100 MHz constant clock) and the shared error flag turn a logic
+// error into one reported failure instead of a hang.
+template <int DIM, int F>
+__device__ inline void dense_take_faces(uint64_t *const (&src)[DIM], uint64_t (&b)[DIM][F], int32_t *err_flag) {
+  bool ready = true;
+#pragma unroll
+  for (int a = 0; a < DIM; ++a)
+    if (src[a])
+#pragma unroll
+      for (int tt = 0; tt < F; ++tt) b[a][tt] = dense_peek_trace(src[a] + tt);
+#pragma unroll
+  for (int a = 0; a < DIM; ++a)
+    if (src[a])
+#pragma unroll
+      for (int tt = 0; tt < F; ++tt) ready = ready && b[a][tt] != kDenseTraceEmpty;
+  if (ready) return;
   const uint64_t t_start = wall_clock64();
   for (;;) {
-    __builtin_amdgcn_s_sleep(1);
-    b = dense_peek_trace(p);
-    if (b != kDenseTraceEmpty) return __longlong_as_double((long long)b);
+    __builtin_amdgcn_s_sleep(2);
+    ready = true;
+#pragma unroll
+    for (int a = 0; a < DIM; ++a)
+      if (src[a])
+#pragma unroll
+        for (int tt = 0; tt < F; ++tt)
+          if (b[a][tt] == kDenseTraceEmpty) b[a][tt] = dense_peek_trace(src[a] + tt);
+#pragma unroll
+    for (int a = 0; a < DIM; ++a)
+      if (src[a])
+#pragma unroll
+        for (int tt = 0; tt < F; ++tt) ready = ready && b[a][tt] != kDenseTraceEmpty;
+    if (ready) return;
     if (wall_clock64() - t_start > 100000000ull ||
         __hip_atomic_load(err_flag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0) {
       __hip_atomic_fetch_or(err_flag, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-      return 0.0;
+#pragma unroll
+      for (int a = 0; a < DIM; ++a)
+#pragma unroll
+        for (int tt = 0; tt < F; ++tt)
+          if (b[a][tt] == kDenseTraceEmpty) b[a][tt] = 0;
+      return;
     }
   }
 }
@@ -776,14 +806,22 @@ __device__ inline void dense_put_trace(uint64_t *p, double v) {
   __hip_atomic_exchange(p, (uint64_t)__double_as_longlong(v), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
-// One wave per tile.  The tile index is claimed by lane 0 from a counter that
-// hands out tiles in dependency order (upwind tiles first) and broadcast with
-// readfirstlane, so it is wave-uniform: descriptors and operator rows are read
-// through scalar loads and all control flow that depends on the tile is
-// uniform.  Inside the tile the cells are solved diagonal by diagonal; the
-// inflow traces of a cell come from the previous diagonal through LDS, from an
-// upwind tile through the trace slots, or from the domain inflow data.
-template <int PREC, int NP, int DIM>
+// One wave per tile, in one of two schedules:
+// * claimed (LEVEL = false): one launch for all tiles.  The tile index is
+//   claimed by lane 0 from a counter that hands out tiles in dependency order
+//   (upwind tiles first) and broadcast with readfirstlane, so it is
+//   wave-uniform; inflow traces arrive through the atomic slots above, cell by
+//   cell, so a tile starts as soon as its first upwind cells are done.
+// * levelled (LEVEL = true): one launch per tile diagonal; the launch's tiles
+//   are order[0 .. n_tiles).  Upwind tiles belong to earlier launches, whose
+//   writes the kernel boundary makes visible: plain loads and stores, no
+//   waiting.
+// Either way descriptors and operator rows are read through scalar loads and
+// all control flow that depends on the tile is uniform.  Inside the tile the
+// cells are solved diagonal by diagonal; the inflow traces of a cell come from
+// the previous diagonal through LDS, from an upwind tile through the trace
+// slots, or from the domain inflow data.
+template <int PREC, int NP, int DIM, bool LEVEL>
 __global__ __launch_bounds__(kDenseThreads) void dense_sweep_kernel(
     const DenseTile *__restrict__ tiles, const int32_t *__restrict__ order, const DenseFam *__restrict__ fams,
     const DenseDesc *__restrict__ descs, const double *__restrict__ table, int dt_idx,
@@ -796,12 +834,14 @@ __global__ __launch_bounds__(kDenseThreads) void dense_sweep_kernel(
   constexpr int F = DIM == 2 ? NP : NP * NP;
   __shared__ Rt otr[3][kDenseThreads][F];  // outflow traces per axis of every cell of the tile
   const int t = threadIdx.x;
-  int claim = 0;
-  if (t == 0) claim = atomicAdd(counter, 1);
-  claim = __builtin_amdgcn_readfirstlane(claim);
-  if (claim >= n_tiles) {  // the counter was not reset: report, do nothing
-    if (t == 0) __hip_atomic_fetch_or(err_flag, 2, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    return;
+  int claim = blockIdx.x;
+  if (!LEVEL) {
+    if (t == 0) claim = atomicAdd(counter, 1);
+    claim = __builtin_amdgcn_readfirstlane(claim);
+    if (claim >= n_tiles) {  // the counter was not reset: report, do nothing
+      if (t == 0) __hip_atomic_fetch_or(err_flag, 2, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      return;
+    }
   }
   const int tile = order[claim];
   const DenseTile tl = tiles[tile];
@@ -891,42 +931,70 @@ __global__ __launch_bounds__(kDenseThreads) void dense_sweep_kernel(
       diag += cl[a];
       ndiag += d.T[a] - 1;
     }
+  // Inflow data of the faces that are not fed from inside the tile: domain
+  // inflow (always ready), or, in the levelled schedule, the traces of an
+  // upwind tile of an earlier launch.  Both are fetched before the diagonal
+  // loop, so that the loop issues no global load it would have to wait for.
+  Rt uin[DIM][F];
+  uint64_t *rsrc[DIM];
+#pragma unroll
+  for (int a = 0; a < DIM; ++a) {
+    rsrc[a] = nullptr;
+#pragma unroll
+    for (int tt = 0; tt < F; ++tt) uin[a][tt] = (Rt)0;
+    if (!active || d.sgn[a] == 0 || cl[a] > 0) continue;
+    if (tl.up[a] >= 0) {
+      // face cell index of this cell on faces normal to a (tile-local)
+      int fc = 0, fs = 1;
+#pragma unroll
+      for (int b = 0; b < DIM; ++b)
+        if (b != a && d.sgn[b] != 0) {
+          fc += cl[b] * fs;
+          fs *= d.T[b];
+        }
+      rsrc[a] = traces + tl.trace_off + (int64_t)a * tl.slot + fc * F;
+      if (LEVEL)
+#pragma unroll
+        for (int tt = 0; tt < F; ++tt) uin[a][tt] = (Rt)__longlong_as_double((long long)rsrc[a][tt]);
+    } else {
+      // domain inflow face: transverse cell index over the other axes
+      int64_t tau = 0, ts = 1;
+#pragma unroll
+      for (int b = 0; b < DIM; ++b)
+        if (b != a) {
+          tau += x[b] * ts;
+          ts *= d.n[b];
+        }
+      const int64_t base = fm.fb_base + d.fb_axis_off[a] + tau;
+#pragma unroll
+      for (int tt = 0; tt < F; ++tt) {
+        const int64_t k = base + (int64_t)d.fb_t[a][tt] * d.fb_ntc[a];
+        uin[a][tt] = th * (Rt)fb_new[k] + omt * (Rt)fb_old[k];
+      }
+    }
+  }
+
   for (int s = 0; s < ndiag; ++s) {
     if (active && diag == s) {
+      if (!LEVEL) {
+        uint64_t rb[DIM][F];
+        dense_take_faces<DIM, F>(rsrc, rb, err_flag);
+#pragma unroll
+        for (int a = 0; a < DIM; ++a)
+          if (rsrc[a])
+#pragma unroll
+            for (int tt = 0; tt < F; ++tt) uin[a][tt] = (Rt)__longlong_as_double((long long)rb[a][tt]);
+      }
 #pragma unroll
       for (int a = 0; a < DIM; ++a) {
         if (d.sgn[a] == 0) continue;
-        // face cell index of this cell on faces normal to a (tile-local)
-        int fc = 0, fs = 1;
-#pragma unroll
-        for (int b = 0; b < DIM; ++b)
-          if (b != a && d.sgn[b] != 0) {
-            fc += cl[b] * fs;
-            fs *= d.T[b];
-          }
         Rt u[F];
         if (cl[a] > 0) {
 #pragma unroll
           for (int tt = 0; tt < F; ++tt) u[tt] = otr[a][t - tstride[a]][tt];
-        } else if (tl.up[a] >= 0) {
-          uint64_t *src = traces + tl.trace_off + (int64_t)a * tl.slot + fc * F;
-#pragma unroll
-          for (int tt = 0; tt < F; ++tt) u[tt] = (Rt)dense_take_trace(src + tt, err_flag);
         } else {
-          // domain inflow face: transverse cell index over the other axes
-          int64_t tau = 0, ts = 1;
 #pragma unroll
-          for (int b = 0; b < DIM; ++b)
-            if (b != a) {
-              tau += x[b] * ts;
-              ts *= d.n[b];
-            }
-          const int64_t base = fm.fb_base + d.fb_axis_off[a] + tau;
-#pragma unroll
-          for (int tt = 0; tt < F; ++tt) {
-            const int64_t k = base + (int64_t)d.fb_t[a][tt] * d.fb_ntc[a];
-            u[tt] = th * (Rt)fb_new[k] + omt * (Rt)fb_old[k];
-          }
+          for (int tt = 0; tt < F; ++tt) u[tt] = uin[a][tt];
         }
 #pragma unroll
         for (int i = 0; i < N; ++i) {
@@ -960,11 +1028,22 @@ __global__ __launch_bounds__(kDenseThreads) void dense_sweep_kernel(
           const int q = face_node<NP, DIM>(b, tt, NP - 1);
           const Rt o = th * y[q] + omt * fv[q];
           otr[b][t][tt] = o;
-          if (to_next) dense_put_trace(dst + tt, (double)o);
+          if (to_next) {
+            if (LEVEL)
+              dst[tt] = (uint64_t)__double_as_longlong((double)o);
+            else
+              dense_put_trace(dst + tt, (double)o);
+          }
         }
       }
     }
-    __syncthreads();
+    // The next diagonal reads this one's outflow traces from LDS.  The
+    // workgroup is a single wave, whose LDS accesses execute in order, so
+    // only the compiler has to be kept from moving them across the step;
+    // global stores stay in flight (a workgroup barrier would wait for them).
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
   }
 }
 
@@ -1124,24 +1203,29 @@ hipError_t launch_dense_invert(double *table, const int64_t *row_off, const Dens
 }
 
 template <int PREC, int NP, int DIM>
-hipError_t go_dense(const DenseTile *tiles, const int32_t *order, int n_tiles, const DenseFam *fams,
+hipError_t go_dense(bool level, const DenseTile *tiles, const int32_t *order, int n_tiles, const DenseFam *fams,
                     const DenseDesc *descs, const double *table, int dt_idx, void *f, const double *fb_old,
                     const double *fb_new, uint64_t *traces, int32_t *counter, int32_t *err, hipStream_t st) {
   using St = typename Pol<PREC>::St;
-  // one wave per tile; the counter hands the tiles out in dependency order
-  hipLaunchKernelGGL((dense_sweep_kernel<PREC, NP, DIM>), dim3(n_tiles), dim3(kDenseThreads), 0, st, tiles, order,
-                     fams, descs, table, dt_idx, static_cast<St *>(f), fb_old, fb_new, traces, counter, err, n_tiles);
+  if (level)
+    hipLaunchKernelGGL((dense_sweep_kernel<PREC, NP, DIM, true>), dim3(n_tiles), dim3(kDenseThreads), 0, st, tiles,
+                       order, fams, descs, table, dt_idx, static_cast<St *>(f), fb_old, fb_new, traces, counter, err,
+                       n_tiles);
+  else
+    hipLaunchKernelGGL((dense_sweep_kernel<PREC, NP, DIM, false>), dim3(n_tiles), dim3(kDenseThreads), 0, st, tiles,
+                       order, fams, descs, table, dt_idx, static_cast<St *>(f), fb_old, fb_new, traces, counter, err,
+                       n_tiles);
   return hipGetLastError();
 }
 
 template <int PREC>
-hipError_t go_dense_shape(int np, int dim, const DenseTile *tiles, const int32_t *order, int n_tiles,
+hipError_t go_dense_shape(bool level, int np, int dim, const DenseTile *tiles, const int32_t *order, int n_tiles,
                           const DenseFam *fams, const DenseDesc *descs, const double *table, int dt_idx, void *f,
                           const double *fb_old, const double *fb_new, uint64_t *traces, int32_t *counter,
                           int32_t *err, hipStream_t st) {
 #define PDG_DENSE_CASE(NPV, DIMV)                                                                             \
   if (np == NPV && dim == DIMV)                                                                               \
-    return go_dense<PREC, NPV, DIMV>(tiles, order, n_tiles, fams, descs, table, dt_idx, f, fb_old, fb_new,   \
+    return go_dense<PREC, NPV, DIMV>(level, tiles, order, n_tiles, fams, descs, table, dt_idx, f, fb_old, fb_new,   \
                                      traces, counter, err, st);
   PDG_DENSE_CASE(2, 2)
   PDG_DENSE_CASE(3, 2)
@@ -1153,15 +1237,15 @@ hipError_t go_dense_shape(int np, int dim, const DenseTile *tiles, const int32_t
   return hipErrorInvalidValue;
 }
 
-hipError_t launch_dense_sweep(int prec, int np, int dim, const DenseTile *tiles, const int32_t *order,
+hipError_t launch_dense_sweep(int prec, bool level, int np, int dim, const DenseTile *tiles, const int32_t *order,
                               int n_tiles, const DenseFam *fams, const DenseDesc *descs, const double *table,
                               int dt_idx, void *f, const double *fb_old, const double *fb_new, uint64_t *traces,
                               int32_t *counter, int32_t *err_flag, hipStream_t st) {
   if (n_tiles <= 0) return hipSuccess;
   switch (prec) {
-    case kF64: return go_dense_shape<kF64>(np, dim, tiles, order, n_tiles, fams, descs, table, dt_idx, f, fb_old, fb_new, traces, counter, err_flag, st);
-    case kF32: return go_dense_shape<kF32>(np, dim, tiles, order, n_tiles, fams, descs, table, dt_idx, f, fb_old, fb_new, traces, counter, err_flag, st);
-    case kRefine: return go_dense_shape<kRefine>(np, dim, tiles, order, n_tiles, fams, descs, table, dt_idx, f, fb_old, fb_new, traces, counter, err_flag, st);
+    case kF64: return go_dense_shape<kF64>(level, np, dim, tiles, order, n_tiles, fams, descs, table, dt_idx, f, fb_old, fb_new, traces, counter, err_flag, st);
+    case kF32: return go_dense_shape<kF32>(level, np, dim, tiles, order, n_tiles, fams, descs, table, dt_idx, f, fb_old, fb_new, traces, counter, err_flag, st);
+    case kRefine: return go_dense_shape<kRefine>(level, np, dim, tiles, order, n_tiles, fams, descs, table, dt_idx, f, fb_old, fb_new, traces, counter, err_flag, st);
     default: return hipErrorInvalidValue;
   }
 }

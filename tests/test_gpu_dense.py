@@ -77,17 +77,27 @@ def _run(lib, torch, case, prec, theta=0.5, half=False, seed=0):
     return rel_errors(got, want), per_v
 
 
+@pytest.fixture(params=["level", "claim"])
+def schedule(request, monkeypatch):
+    """Dense-tile schedule: one launch per tile diagonal, or one launch whose
+    tiles are claimed in dependency order and hand traces over through
+    atomics.  Read by the library when a problem is prepared."""
+    monkeypatch.setenv("PDG_DENSE_SCHEDULE", request.param)
+    return request.param
+
+
 @pytest.mark.parametrize("case", CASES, ids=[c[0] for c in CASES])
 @pytest.mark.parametrize("prec", [0, 2, 1], ids=["fp64", "fp32refine", "fp32"])
-def test_dense_sweep_matches_oracle(lib, case, prec):
+def test_dense_sweep_matches_oracle(lib, case, prec, schedule):
     torch = pytest.importorskip("torch")
+    print(f"schedule={schedule}", flush=True)
     (l2, mx), per_v = _run(lib, torch, case, prec)
     print(f"  rel L2 {l2:.3e} max {mx:.3e}; worst velocity {max(per_v):.3e}")
     assert l2 <= BARS[prec] and mx <= 10 * BARS[prec] and max(per_v) <= 10 * BARS[prec]
 
 
 @pytest.mark.parametrize("theta,half", [(1.0, False), (0.5, True), (0.6, False)])
-def test_dense_sweep_theta_and_half_step(lib, theta, half):
+def test_dense_sweep_theta_and_half_step(lib, theta, half, schedule):
     torch = pytest.importorskip("torch")
     (l2, mx), _ = _run(lib, torch, CASES[1], 0, theta, half, seed=4)
     assert l2 <= 1e-12 and mx <= 1e-11
