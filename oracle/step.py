@@ -27,6 +27,15 @@ The collision over h uses omega(h) = 2h / (2 tau + h) (eq. collision_cn); the
 omega given for dt fixes tau (omega = 2: tau = 0, then omega(h) = 2 for all h).
 The inflow data f^b is time independent (Sec. 2).
 
+With a source (the D2Q9 gravity model of Sec. 5.1) every collision C(h) of
+the compositions becomes S(a) C(h) S(b) with source step S of Sec. 3.2:
+* LIE:               T(dt) S(dt) C(dt), the paper's M_1^s order;
+* STRANG:            T(dt/2) S(dt/2) C(dt) S(dt/2) T(dt/2), the paper's M_2^s;
+* STRANG_COLLAPSED:  M_2^s with the inner transports fused, as in Sec. 5.1;
+* KIN, KIN4:         each C(h/2) of M_2^kin(h) becomes S(h/4) C(h/2) S(h/4).
+                     The paper does not give M_2^kin with a source; this
+                     symmetric placement keeps the composition palindromic.
+
 Pins: a constant equilibrium state is preserved over several steps (scalar
 and Euler), second-order convergence in dt of the collapsed scheme for scalar
 advection, and the involution C(C(f)) = f at omega = 2.
@@ -58,8 +67,10 @@ class Problem:
         self.vel = np.asarray(vel, dtype=float).reshape(-1, self.mesh.dim)
         self.nv = self.vel.shape[0]
         self.m = int(m)
-        self.feq_kind = feq_kind            # "advection" or "euler"
+        self.feq_kind = feq_kind            # "advection", "euler" or "d2q9"
         self.feq_param = dict(feq_param)
+        if feq_kind == "d2q9" and (self.m != 1 or self.mesh.dim != 2):
+            raise ValueError("the D2Q9 model has one component per velocity in 2D")
         self._levels = {}
         self._entries = {}
 
@@ -76,7 +87,19 @@ class Problem:
         raise ValueError(self.feq_kind)
 
     def feq(self, w):
+        if self.feq_kind == "d2q9":
+            return _relax.d2q9_equilibrium(w, self.vel, self.lam)
         return _relax.equilibrium(w, self.vel, self.flux(w), self.lam)
+
+    def moments(self, f):
+        """w = P f (Sec. 2): per-component sums, or the D2Q9 matrix P."""
+        if self.feq_kind == "d2q9":
+            return _relax.d2q9_moments(f, self.vel)
+        return _relax.moments(f)
+
+    @property
+    def has_source(self):
+        return self.feq_kind == "d2q9" and self.feq_param.get("g", 0.0) != 0.0
 
     # ---- per-velocity data ----------------------------------------------
     def levels(self, i):
@@ -113,7 +136,18 @@ class Problem:
         return out
 
     def collide(self, f, omega):
-        return _relax.relax(f, omega, self.feq)
+        f = np.asarray(f, dtype=float)
+        return f + omega * (self.feq(self.moments(f)) - f)
+
+    def source(self, f, h):
+        """S_2(h) (Sec. 3.2): gravity on the equilibrium part; identity without a source."""
+        if not self.has_source or h == 0.0:
+            return np.array(f, dtype=float, copy=True)
+        return _relax.source_step(f, h, self.feq_param["g"], self.moments, self.feq)
+
+    def local(self, f, h_pre, omega, h_post):
+        """S(h_pre) C S(h_post): the node-local part of a composition."""
+        return self.source(self.collide(self.source(f, h_pre), omega), h_post)
 
 
 def run(prob, f0, fb, dt, theta, omega, scheme, nsteps, method="sweep"):
@@ -124,11 +158,11 @@ def run(prob, f0, fb, dt, theta, omega, scheme, nsteps, method="sweep"):
     if scheme == LIE:
         for _ in range(nsteps):
             f = prob.transport(f, fb, fb, dt, theta, method)
-            f = prob.collide(f, omega)
+            f = prob.local(f, dt, omega, 0.0)
     elif scheme == STRANG:
         for _ in range(nsteps):
             f = prob.transport(f, fb, fb, dt / 2, theta, method)
-            f = prob.collide(f, omega)
+            f = prob.local(f, dt / 2, omega, dt / 2)
             f = prob.transport(f, fb, fb, dt / 2, theta, method)
     elif scheme in (KIN, KIN4):
         subs = [1.0] if scheme == KIN else [TRIPLE_JUMP_G1, TRIPLE_JUMP_G2, TRIPLE_JUMP_G1]
@@ -137,16 +171,16 @@ def run(prob, f0, fb, dt, theta, omega, scheme, nsteps, method="sweep"):
                 h = g * dt
                 wh = omega_for(h / 2, dt, omega)
                 f = prob.transport(f, fb, fb, h / 4, theta, method)
-                f = prob.collide(f, wh)
+                f = prob.local(f, h / 4, wh, h / 4)
                 f = prob.transport(f, fb, fb, h / 2, theta, method)
-                f = prob.collide(f, wh)
+                f = prob.local(f, h / 4, wh, h / 4)
                 f = prob.transport(f, fb, fb, h / 4, theta, method)
     elif scheme == STRANG_COLLAPSED:
         f = prob.transport(f, fb, fb, dt / 2, theta, method)
-        f = prob.collide(f, omega)
+        f = prob.local(f, dt / 2, omega, dt / 2)
         for _ in range(nsteps - 1):
             f = prob.transport(f, fb, fb, dt, theta, method)
-            f = prob.collide(f, omega)
+            f = prob.local(f, dt / 2, omega, dt / 2)
         f = prob.transport(f, fb, fb, dt / 2, theta, method)
     else:
         raise ValueError("unknown scheme")
