@@ -6,7 +6,10 @@
  *
  * Model (Sec. 2, eq. kin_bgk).  nv transport equations at constant velocities
  * v_i, each carrying m components f_{i,k}, coupled by the relaxation
- * f <- f + omega (f^eq(w) - f) with w_k = sum_i f_{i,k} (eq. micro_to_macro).
+ * f <- f + omega (f^eq(w) - f) with w = P f (eq. micro_to_macro): w_k =
+ * sum_i f_{i,k} for the vector kinetic models, or the 3 x 9 matrix P of the
+ * D2Q9 lattice model of the isothermal Euler equations with gravity (Sec. 5.1),
+ * whose constant gravity enters through the source step S_2 (Sec. 3.2).
  * Space: nodal DG on Gauss-Lobatto points of uniform Cartesian hexahedra
  * (Sec. 3.1, eq. DG_reduit).  Time: the theta-scheme transport step
  * (eq. transport_cn, theta = 1/2 gives T_2) and the collision update
@@ -41,7 +44,8 @@
  *      node j   = jx + (d+1) jy + (d+1)^2 jz          (Gauss-Lobatto tensor index)
  *      cell c   = x + nx y + nx ny z                   (lexicographic, x fastest)
  *      f[v][k][j][c]      nv * m * Nd * Nc values, Nd = (d+1)^D, Nc = nx ny nz
- *      w[k][j][c]         m * Nd * Nc values
+ *      w[k][j][c]         nw * Nd * Nc values (nw = m moments per node; 3 for
+ *                         PDG_FEQ_D2Q9: rho, rho u_x, rho u_y)
  *      fb[v][k][t][tau]   inflow boundary values of velocity v: for an axis-a
  *                         velocity, t enumerates the node indices of the other
  *                         axes (increasing axis order, first fastest) and tau
@@ -79,7 +83,14 @@ typedef enum {
 
 typedef enum {
   PDG_FEQ_ADVECTION = 0, /* q^k(w) = a_k w; feq_param = {a_1, .., a_D} */
-  PDG_FEQ_EULER = 1      /* compressible Euler, m = D + 2; feq_param = {gamma} */
+  PDG_FEQ_EULER = 1,     /* compressible Euler, m = D + 2; feq_param = {gamma} */
+  PDG_FEQ_D2Q9 = 2       /* isothermal Euler on the D2Q9 lattice (Sec. 5.1): D = 2, m = 1, nv = 9
+                            velocities lambda x {0, +-e_x, +-e_y, (+-1, +-1)} in any order;
+                            w = (rho, rho u_x, rho u_y); with c^2 = lambda^2 / 3,
+                            f_i^eq = wt_i rho (1 + u.v_i/c^2 + (u.v_i)^2/(2c^4) - u.u/(2c^2)),
+                            wt = 4/9 (rest), 1/9 (axis), 1/36 (diagonal);
+                            feq_param = {g}: constant gravity -g e_y (0: no source).
+                            A malformed velocity set is PDG_EINVAL at setup. */
 } pdg_feq_kind;
 
 typedef enum {
@@ -181,9 +192,11 @@ pdg_status pdg_prepare(pdg_ctx *c, double dt, double theta, double omega, pdg_sc
  * f in the state precision).  Sets an initial state (Sec. 2). */
 pdg_status pdg_equilibrium(pdg_ctx *c, const double *w, void *f, void *stream);
 
-/* fb[v][k][t][tau] = f^eq_{v,k}(w_inflow[v][:][t][tau]) (device, binary64):
- * w_inflow has the fb layout with m values per (v, t, tau) taken from the
- * macroscopic field at the inflow points of velocity v. */
+/* fb = f^eq_{v}(w) at the inflow points of every velocity (device, binary64):
+ * w_inflow holds, per instance and velocity v (in that order), nw blocks
+ * (one per moment) of the macroscopic field at v's inflow points, in the
+ * point order of v's fb block.  With nw = m this is exactly the fb layout;
+ * for PDG_FEQ_D2Q9 it holds 3 values per inflow point (size 3 * fb_elems). */
 pdg_status pdg_inflow_equilibrium(pdg_ctx *c, const double *w_inflow, double *fb, void *stream);
 
 /* One theta-scheme transport step of size dt_sub (dt or dt/2 as prepared) for
@@ -198,9 +211,19 @@ pdg_status pdg_transport_sweep(pdg_ctx *c, void *f, const double *fb_old, const 
                                double dt_sub, void *stream);
 
 /* Collision step (eq. collision_cn, Sec. 4.4): at every node
- * w = sum_i f_i (compensated binary64 sum), then f_i <- f_i + omega (f_i^eq(w) - f_i).
+ * w = P f (compensated binary64 sums), then f_i <- f_i + omega (f_i^eq(w) - f_i).
  * w_out (nullable, device binary64, w layout) receives w. */
 pdg_status pdg_relax(pdg_ctx *c, void *f, double *w_out, void *stream);
+
+/* Source step S_2(h) (Sec. 3.2) of the instances with a source (PDG_FEQ_D2Q9
+ * with g != 0; the others are left untouched): the Crank-Nicolson integrator
+ * of w' = w + h/2 (S(w) + S(w')), S(w) = (0, 0, -g rho), which keeps rho and
+ * is therefore solved exactly (rho u_y -= h g rho), applied to the
+ * equilibrium part of f: f <- f + f^eq(w') - f^eq(w) (Sec. 5.1).  Node-local,
+ * in place; any finite h (h < 0 inverts the step h > 0).  pdg_step applies
+ * it around each collision: T(dt) S(dt) C(dt) for PDG_LIE, S(dt/2) C(dt)
+ * S(dt/2) for the Strang schemes, S(h/4) C(h/2) S(h/4) inside M_2^kin(h). */
+pdg_status pdg_source(pdg_ctx *c, void *f, double h, void *stream);
 
 /* n_steps time steps of the prepared scheme with time-independent inflow fb
  * (Sec. 3.2 and Sec. 5.1).  The repeated part of the scheme (one step; for

@@ -17,12 +17,12 @@ LIB_PATH = os.path.join(_HERE, "_lib", "libpdg.so")
 
 PDG_OK, PDG_EINVAL, PDG_EUNSUPPORTED, PDG_ENOTDAG, PDG_ESINGULAR, PDG_ENOMEM, PDG_EDEVICE, PDG_ESTATE = range(8)
 PDG_FP64, PDG_FP32, PDG_FP32_REFINE = 0, 1, 2
-PDG_FEQ_ADVECTION, PDG_FEQ_EULER = 0, 1
+PDG_FEQ_ADVECTION, PDG_FEQ_EULER, PDG_FEQ_D2Q9 = 0, 1, 2
 PDG_LIE, PDG_STRANG, PDG_STRANG_COLLAPSED, PDG_KIN, PDG_KIN4 = 0, 1, 2, 3, 4
 
 EXPORTED = ("pdg_setup_mesh", "pdg_layout", "pdg_node_coords", "pdg_levels", "pdg_topo_levels", "pdg_line_operator", "pdg_cell_operator",
             "pdg_prepare", "pdg_equilibrium", "pdg_inflow_equilibrium", "pdg_transport_sweep",
-            "pdg_relax", "pdg_step", "pdg_autotune", "pdg_get_tiles", "pdg_set_tiles", "pdg_last_refine_correction", "pdg_sync_status", "pdg_status_string", "pdg_error_detail", "pdg_destroy")
+            "pdg_relax", "pdg_source", "pdg_step", "pdg_autotune", "pdg_get_tiles", "pdg_set_tiles", "pdg_last_refine_correction", "pdg_sync_status", "pdg_status_string", "pdg_error_detail", "pdg_destroy")
 
 
 class PdgError(RuntimeError):
@@ -63,6 +63,7 @@ def _load():
         "pdg_inflow_equilibrium": (i32, [p, p, p, p]),
         "pdg_transport_sweep": (i32, [p, p, p, p, d, p]),
         "pdg_relax": (i32, [p, p, p, p]),
+        "pdg_source": (i32, [p, p, d, p]),
         "pdg_step": (i32, [p, p, p, i32, p]),
         "pdg_autotune": (i32, [p, p, p, i32, p]),
         "pdg_get_tiles": (i32, [p, ctypes.POINTER(i32), p]),
@@ -117,7 +118,7 @@ def _stream(stream):
 # ---------------------------------------------------------------------------
 def pdg_setup_mesh(instances):
     """instances: list of dicts with dim, n, degree, v (nv x dim), m, lo, hi,
-    feq ('advection'|'euler'), feq_param.  Returns an opaque context handle."""
+    feq ('advection'|'euler'|'d2q9'), feq_param.  Returns an opaque context handle."""
     import numpy as np
     arr = (pdg_instance_desc * len(instances))()
     keep = []
@@ -130,7 +131,7 @@ def pdg_setup_mesh(instances):
         hi = (list(ins.get("hi", [1.0] * 3)) + [1.0] * 3)[:3]
         par = (list(ins.get("feq_param", [])) + [0.0] * 4)[:4]
         feq = ins.get("feq", "advection")
-        feq = {"advection": PDG_FEQ_ADVECTION, "euler": PDG_FEQ_EULER}.get(feq, feq)
+        feq = {"advection": PDG_FEQ_ADVECTION, "euler": PDG_FEQ_EULER, "d2q9": PDG_FEQ_D2Q9}.get(feq, feq)
         nv = v.shape[0] if v.ndim == 2 else 0
         arr[i] = pdg_instance_desc(dim, (ctypes.c_int32 * 3)(*n), int(ins["degree"]), nv, int(ins["m"]),
                                    (ctypes.c_double * 3)(*lo), (ctypes.c_double * 3)(*hi),
@@ -195,6 +196,10 @@ def pdg_transport_sweep(ctx, f, fb_old, fb_new, dt_sub, stream=None):
 
 def pdg_relax(ctx, f, w_out=None, stream=None):
     _check(_lib.pdg_relax(ctx, _ptr(f), _ptr(w_out), _stream(stream)), "pdg_relax")
+
+
+def pdg_source(ctx, f, h, stream=None):
+    _check(_lib.pdg_source(ctx, _ptr(f), float(h), _stream(stream)), "pdg_source")
 
 
 def pdg_step(ctx, f, fb, n_steps, stream=None):
@@ -286,6 +291,9 @@ class Problem:
 
     def relax(self, f, w_out=None, stream=None):
         pdg_relax(self.ctx, f, w_out, stream)
+
+    def source(self, f, h, stream=None):
+        pdg_source(self.ctx, f, h, stream)
 
     def step(self, f, fb, n_steps, stream=None):
         pdg_step(self.ctx, f, fb, n_steps, stream)

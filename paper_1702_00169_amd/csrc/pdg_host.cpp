@@ -40,6 +40,9 @@ struct Instance {
   std::vector<int> sign;
   std::vector<int> ndep;            // per velocity: number of non-zero components
   std::vector<std::array<int, 3>> sgn;  // per velocity and axis: sign of the component (0 if zero)
+  int nw = 0;                       // moments per node: m, or 3 for the D2Q9 model
+  double lat_lambda = 0.0;          // D2Q9: lambda, velocity i = lambda (lat[i][0], lat[i][1])
+  std::vector<std::array<int, 2>> lat;
   double h[3];
   int64_t n[3];
 };
@@ -52,6 +55,7 @@ struct Group {
 struct RelaxGroup {
   int nv, m;
   int64_t first, count;
+  int lattice;  // 1: D2Q9 lattice kernel, 0: {+-lambda e_k} kernel
 };
 
 // Dense launch group: tiles of one (d+1, D) kernel instantiation.
@@ -554,6 +558,34 @@ pdg_status pdg_setup_mesh(const pdg_instance_desc *descs, int32_t n_inst, pdg_ct
         delete c;
         return PDG_EINVAL;
       }
+    in.nw = d.m;
+    if (d.feq == PDG_FEQ_D2Q9) {
+      // the D2Q9 lattice of Sec. 5.1: lambda x {0, +-e_x, +-e_y, (+-1, +-1)}, any order
+      bool ok = d.dim == 2 && d.nv == 9 && d.m == 1;
+      double lam = 0.0;
+      for (int v = 0; v < d.nv && ok; ++v) lam = std::max(lam, std::fabs(in.v[(size_t)v * 2]));
+      int seen[3][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}};
+      for (int v = 0; v < d.nv && ok && lam > 0.0; ++v) {
+        std::array<int, 2> cc{0, 0};
+        for (int k = 0; k < 2; ++k) {
+          const double q = in.v[(size_t)v * 2 + k] / lam;
+          if (q == 1.0) cc[k] = 1;
+          else if (q == -1.0) cc[k] = -1;
+          else if (q != 0.0) ok = false;
+        }
+        if (ok) seen[cc[0] + 1][cc[1] + 1]++;
+        in.lat.push_back(cc);
+      }
+      for (int a = 0; a < 3 && ok; ++a)
+        for (int b = 0; b < 3; ++b)
+          if (seen[a][b] != 1) ok = false;
+      if (!ok || !(lam > 0.0) || !is_finite(d.feq_param[0])) {
+        delete c;
+        return PDG_EINVAL;
+      }
+      in.lat_lambda = lam;
+      in.nw = 3;
+    }
     in.np = d.degree + 1;
     in.nd = 1;
     in.nc = 1;
@@ -621,7 +653,7 @@ pdg_status pdg_setup_mesh(const pdg_instance_desc *descs, int32_t n_inst, pdg_ct
     in.w_off = w_off;
     in.fb_off = fb_off;
     f_off += (int64_t)d.nv * d.m * in.nd * in.nc;
-    w_off += (int64_t)d.m * in.nd * in.nc;
+    w_off += (int64_t)in.nw * in.nd * in.nc;
     fb_off += fbo;
     c->inst.push_back(std::move(in));
   }
@@ -1053,10 +1085,12 @@ pdg_status pdg_prepare(pdg_ctx *c, double dt, double theta, double omega, pdg_sc
 
   // ---- relax tables --------------------------------------------------------
   std::vector<RelaxDesc> rdesc;
-  std::map<std::pair<int, int>, std::vector<RelaxItem>> ritems_by;
+  // items grouped by kernel: (lattice, nv, m)
+  std::map<std::array<int, 3>, std::vector<RelaxItem>> ritems_by;
   std::vector<InflowDesc> idesc_all;
-  std::map<std::pair<int, int>, std::vector<InflowDesc>> iby;
+  std::map<std::array<int, 3>, std::vector<InflowDesc>> iby;
   bool relax_ok = true;
+  int64_t w_inflow_off = 0;
   for (size_t ii = 0; ii < c->inst.size(); ++ii) {
     const Instance &in = c->inst[ii];
     RelaxDesc rd;
@@ -1069,57 +1103,70 @@ pdg_status pdg_prepare(pdg_ctx *c, double dt, double theta, double omega, pdg_sc
     rd.m = in.d.m;
     rd.dim = in.d.dim;
     rd.feq = in.d.feq;
-    // the equilibrium needs the full {+-lambda e_k} set
-    bool ok = in.d.nv == 2 * in.d.dim;
-    for (int v = 0; v < in.d.nv; ++v)
-      if (in.axis[v] < 0) ok = false;
-    const double lam = ok ? std::fabs(in.v[(size_t)0 * in.d.dim + in.axis[0]]) : 0.0;
-    int seen[3][2] = {{0, 0}, {0, 0}, {0, 0}};
-    for (int v = 0; v < in.d.nv && ok; ++v) {
-      const double sp = std::fabs(in.v[(size_t)v * in.d.dim + in.axis[v]]);
-      if (sp != lam) ok = false;
-      rd.axis[v] = (int8_t)in.axis[v];
-      rd.sign[v] = (int8_t)in.sign[v];
-      seen[in.axis[v]][in.sign[v] > 0]++;
+    const int lattice = in.d.feq == PDG_FEQ_D2Q9 ? 1 : 0;
+    bool ok = true;
+    if (lattice) {
+      // validated at setup
+      rd.lambda = in.lat_lambda;
+      for (int v = 0; v < 9; ++v) {
+        rd.cx[v] = (int8_t)in.lat[v][0];
+        rd.cy[v] = (int8_t)in.lat[v][1];
+      }
+    } else {
+      // the equilibrium needs the full {+-lambda e_k} set
+      ok = in.d.nv == 2 * in.d.dim;
+      for (int v = 0; v < in.d.nv; ++v)
+        if (in.axis[v] < 0) ok = false;
+      const double lam = ok ? std::fabs(in.v[(size_t)0 * in.d.dim + in.axis[0]]) : 0.0;
+      int seen[3][2] = {{0, 0}, {0, 0}, {0, 0}};
+      for (int v = 0; v < in.d.nv && ok; ++v) {
+        const double sp = std::fabs(in.v[(size_t)v * in.d.dim + in.axis[v]]);
+        if (sp != lam) ok = false;
+        rd.axis[v] = (int8_t)in.axis[v];
+        rd.sign[v] = (int8_t)in.sign[v];
+        seen[in.axis[v]][in.sign[v] > 0]++;
+      }
+      for (int k = 0; k < in.d.dim && ok; ++k)
+        if (seen[k][0] != 1 || seen[k][1] != 1) ok = false;
+      if (in.d.feq == PDG_FEQ_EULER && in.d.m != in.d.dim + 2) ok = false;
+      if (in.d.feq != PDG_FEQ_EULER && in.d.feq != PDG_FEQ_ADVECTION) ok = false;
+      rd.lambda = lam;
     }
-    for (int k = 0; k < in.d.dim && ok; ++k)
-      if (seen[k][0] != 1 || seen[k][1] != 1) ok = false;
-    if (in.d.feq == PDG_FEQ_EULER && in.d.m != in.d.dim + 2) ok = false;
-    if (in.d.feq != PDG_FEQ_EULER && in.d.feq != PDG_FEQ_ADVECTION) ok = false;
-    rd.lambda = lam;
     if (!ok) relax_ok = false;
     const int di = (int)rdesc.size();
     rdesc.push_back(rd);
+    const std::array<int, 3> key{lattice, rd.nv, rd.m};
     const int64_t chunk = 4 * kBlock;
     for (int64_t n0 = 0; n0 < rd.nodes; n0 += chunk) {
       RelaxItem it;
       it.node0 = n0;
       it.desc = di;
       it.count = (int32_t)std::min<int64_t>(chunk, rd.nodes - n0);
-      ritems_by[{rd.nv, rd.m}].push_back(it);
+      ritems_by[key].push_back(it);
     }
+    // inflow points of every velocity; w_inflow holds nw moments per point
     for (int v = 0; v < in.d.nv; ++v) {
       InflowDesc idd;
-      int64_t tnodes = 1;
-      for (int k = 0; k < in.d.dim - 1; ++k) tnodes *= in.np;
-      idd.per_comp = tnodes * (in.nc / in.n[in.axis[v]]);
+      idd.per_comp = (in.fb_vel_off[v + 1] - in.fb_vel_off[v]) / in.d.m;
       idd.fb_base = in.fb_off + in.fb_vel_off[v];
+      idd.w_base = w_inflow_off;
       idd.relax_desc = di;
       idd.vel = v;
-      iby[{rd.nv, rd.m}].push_back(idd);
+      w_inflow_off += (int64_t)in.nw * idd.per_comp;
+      if (idd.per_comp > 0) iby[key].push_back(idd);
     }
   }
   std::vector<RelaxItem> ritems;
   std::vector<RelaxGroup> rgroups, igroups;
   if (relax_ok) {
     for (auto &kv : ritems_by) {
-      rgroups.push_back(RelaxGroup{kv.first.first, kv.first.second, (int64_t)ritems.size(),
-                                   (int64_t)kv.second.size()});
+      rgroups.push_back(RelaxGroup{kv.first[1], kv.first[2], (int64_t)ritems.size(), (int64_t)kv.second.size(),
+                                   kv.first[0]});
       ritems.insert(ritems.end(), kv.second.begin(), kv.second.end());
     }
     for (auto &kv : iby) {
-      igroups.push_back(RelaxGroup{kv.first.first, kv.first.second, (int64_t)idesc_all.size(),
-                                   (int64_t)kv.second.size()});
+      igroups.push_back(RelaxGroup{kv.first[1], kv.first[2], (int64_t)idesc_all.size(), (int64_t)kv.second.size(),
+                                   kv.first[0]});
       idesc_all.insert(idesc_all.end(), kv.second.begin(), kv.second.end());
     }
   }
@@ -1271,25 +1318,39 @@ pdg_status do_sweep(pdg_ctx *c, void *f, const double *fb_old, const double *fb_
   return PDG_OK;
 }
 
-pdg_status do_relax(pdg_ctx *c, void *f, double *w_out, double omega, hipStream_t st) {
+// The node-local part of a composition: S(h_pre) C(omega) S(h_post) (Sec. 3.2).
+// The source terms act only on instances with a source (D2Q9 with gravity);
+// with source_only the collision-only instances are left alone.
+pdg_status do_local(pdg_ctx *c, void *f, double *w_out, double omega, double h_pre, double h_post,
+                    bool source_only, hipStream_t st) {
   if (c->rgroups.empty()) return PDG_EUNSUPPORTED;
   for (const RelaxGroup &g : c->rgroups) {
-    hipError_t e = launch_relax(c->prec, g.nv, g.m, c->ritems.p + g.first, (int)g.count, c->rdesc.p, f, w_out,
-                                nullptr, omega, 0, st);
+    hipError_t e;
+    if (g.lattice)
+      e = launch_lattice(c->prec, c->ritems.p + g.first, (int)g.count, c->rdesc.p, f, w_out, nullptr, omega, h_pre,
+                         h_post, 0, st);
+    else if (source_only)
+      e = hipSuccess;
+    else
+      e = launch_relax(c->prec, g.nv, g.m, c->ritems.p + g.first, (int)g.count, c->rdesc.p, f, w_out, nullptr,
+                       omega, 0, st);
     if (e != hipSuccess) return from_hip(e);
   }
   return PDG_OK;
 }
 
 struct StepOp {
-  int kind;      // 0: transport sweep, 1: relaxation
-  int dt_idx;    // sweep: index into the prepared sub-steps
-  double omega;  // relaxation factor
+  int kind;       // 0: transport sweep, 1: node-local step S(h_pre) C(omega) S(h_post)
+  int dt_idx;     // sweep: index into the prepared sub-steps
+  double omega;   // relaxation factor
+  double h_pre;   // source sub-steps around the collision
+  double h_post;
 };
 
 pdg_status run_ops(pdg_ctx *c, const std::vector<StepOp> &ops, void *f, const double *fb, hipStream_t st) {
   for (const StepOp &o : ops) {
-    const pdg_status s = o.kind == 0 ? do_sweep(c, f, fb, fb, o.dt_idx, st) : do_relax(c, f, nullptr, o.omega, st);
+    const pdg_status s = o.kind == 0 ? do_sweep(c, f, fb, fb, o.dt_idx, st)
+                                     : do_local(c, f, nullptr, o.omega, o.h_pre, o.h_post, false, st);
     if (s != PDG_OK) return s;
   }
   return PDG_OK;
@@ -1316,7 +1377,14 @@ pdg_status pdg_transport_sweep(pdg_ctx *c, void *f, const double *fb_old, const 
 pdg_status pdg_relax(pdg_ctx *c, void *f, double *w_out, void *stream) {
   if (!c || !f) return PDG_EINVAL;
   if (!c->prepared) return PDG_ESTATE;
-  return do_relax(c, f, w_out, c->omega, static_cast<hipStream_t>(stream));
+  return do_local(c, f, w_out, c->omega, 0.0, 0.0, false, static_cast<hipStream_t>(stream));
+}
+
+pdg_status pdg_source(pdg_ctx *c, void *f, double h, void *stream) {
+  if (!c || !f || !is_finite(h)) return PDG_EINVAL;
+  if (!c->prepared) return PDG_ESTATE;
+  if (h == 0.0) return PDG_OK;
+  return do_local(c, f, nullptr, 0.0, h, 0.0, true, static_cast<hipStream_t>(stream));
 }
 
 pdg_status pdg_equilibrium(pdg_ctx *c, const double *w, void *f, void *stream) {
@@ -1324,8 +1392,10 @@ pdg_status pdg_equilibrium(pdg_ctx *c, const double *w, void *f, void *stream) {
   if (!c->prepared) return PDG_ESTATE;
   if (c->rgroups.empty()) return PDG_EUNSUPPORTED;
   for (const RelaxGroup &g : c->rgroups) {
-    hipError_t e = launch_relax(c->prec, g.nv, g.m, c->ritems.p + g.first, (int)g.count, c->rdesc.p, f, nullptr, w,
-                                1.0, 1, static_cast<hipStream_t>(stream));
+    hipError_t e = g.lattice ? launch_lattice(c->prec, c->ritems.p + g.first, (int)g.count, c->rdesc.p, f, nullptr,
+                                              w, 1.0, 0.0, 0.0, 1, static_cast<hipStream_t>(stream))
+                             : launch_relax(c->prec, g.nv, g.m, c->ritems.p + g.first, (int)g.count, c->rdesc.p, f,
+                                            nullptr, w, 1.0, 1, static_cast<hipStream_t>(stream));
     if (e != hipSuccess) return from_hip(e);
   }
   return PDG_OK;
@@ -1336,8 +1406,10 @@ pdg_status pdg_inflow_equilibrium(pdg_ctx *c, const double *w_inflow, double *fb
   if (!c->prepared) return PDG_ESTATE;
   if (c->igroups.empty()) return PDG_EUNSUPPORTED;
   for (const RelaxGroup &g : c->igroups) {
-    hipError_t e = launch_inflow_eq(g.nv, g.m, c->idesc.p + g.first, (int)g.count, c->rdesc.p, w_inflow, fb,
-                                    static_cast<hipStream_t>(stream));
+    hipError_t e = g.lattice ? launch_lattice_inflow(c->idesc.p + g.first, (int)g.count, c->rdesc.p, w_inflow, fb,
+                                                     static_cast<hipStream_t>(stream))
+                             : launch_inflow_eq(g.nv, g.m, c->idesc.p + g.first, (int)g.count, c->rdesc.p, w_inflow,
+                                                fb, static_cast<hipStream_t>(stream));
     if (e != hipSuccess) return from_hip(e);
   }
   return PDG_OK;
@@ -1354,31 +1426,38 @@ pdg_status pdg_step(pdg_ctx *c, void *f, const double *fb, int32_t n_steps, void
   int reps = n_steps;
   const double w = c->omega;
   auto om = [c](double h) { return c->tau == 0.0 ? 2.0 : 2.0 * h / (2.0 * c->tau + h); };
+  // With a source every collision C(h) becomes S(a) C(h) S(b) (Sec. 3.2, Sec. 5.1):
+  // Lie T(dt) S(dt) C(dt); Strang T(dt/2) S(dt/2) C(dt) S(dt/2) T(dt/2); each
+  // C(h/2) of M_2^kin(h) becomes S(h/4) C(h/2) S(h/4).  Without a source the
+  // source fractions are ignored.
+  const double dt = c->dt;
   switch (c->scheme) {
-    case PDG_LIE: body = {{0, 0, 0.0}, {1, 0, w}}; break;
-    case PDG_STRANG: body = {{0, 1, 0.0}, {1, 0, w}, {0, 1, 0.0}}; break;
+    case PDG_LIE: body = {{0, 0, 0.0, 0.0, 0.0}, {1, 0, w, dt, 0.0}}; break;
+    case PDG_STRANG: body = {{0, 1, 0.0, 0.0, 0.0}, {1, 0, w, 0.5 * dt, 0.5 * dt}, {0, 1, 0.0, 0.0, 0.0}}; break;
     case PDG_STRANG_COLLAPSED:
       // T(dt/2) C [T(dt) C]^(N-1) T(dt/2)
-      pro = {{0, 1, 0.0}, {1, 0, w}};
-      body = {{0, 0, 0.0}, {1, 0, w}};
-      epi = {{0, 1, 0.0}};
+      pro = {{0, 1, 0.0, 0.0, 0.0}, {1, 0, w, 0.5 * dt, 0.5 * dt}};
+      body = {{0, 0, 0.0, 0.0, 0.0}, {1, 0, w, 0.5 * dt, 0.5 * dt}};
+      epi = {{0, 1, 0.0, 0.0, 0.0}};
       reps = n_steps - 1;
       break;
-    case PDG_KIN:
+    case PDG_KIN: {
       // M_2^kin(dt) = T(dt/4) C(dt/2) T(dt/2) C(dt/2) T(dt/4)
-      body = {{0, 2, 0.0}, {1, 0, om(0.5 * c->dt)}, {0, 1, 0.0}, {1, 0, om(0.5 * c->dt)}, {0, 2, 0.0}};
+      const double wc = om(0.5 * dt), q = 0.25 * dt;
+      body = {{0, 2, 0.0, 0.0, 0.0}, {1, 0, wc, q, q}, {0, 1, 0.0, 0.0, 0.0}, {1, 0, wc, q, q}, {0, 2, 0.0, 0.0, 0.0}};
       break;
+    }
     case PDG_KIN4: {
       // M_2^kin(g1 dt) M_2^kin(g2 dt) M_2^kin(g1 dt); sub-steps 2..5 = g1/4, g1/2, g2/4, g2/2
       const double g[3] = {kTripleJump1, kTripleJump2, kTripleJump1};
       const int q[3] = {2, 4, 2};
       for (int j = 0; j < 3; ++j) {
-        const double wc = om(0.5 * g[j] * c->dt);
-        body.push_back({0, q[j], 0.0});
-        body.push_back({1, 0, wc});
-        body.push_back({0, q[j] + 1, 0.0});
-        body.push_back({1, 0, wc});
-        body.push_back({0, q[j], 0.0});
+        const double wc = om(0.5 * g[j] * dt), hq = 0.25 * g[j] * dt;
+        body.push_back({0, q[j], 0.0, 0.0, 0.0});
+        body.push_back({1, 0, wc, hq, hq});
+        body.push_back({0, q[j] + 1, 0.0, 0.0, 0.0});
+        body.push_back({1, 0, wc, hq, hq});
+        body.push_back({0, q[j], 0.0, 0.0, 0.0});
       }
       break;
     }

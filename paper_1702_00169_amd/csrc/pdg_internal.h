@@ -69,11 +69,13 @@ struct RelaxDesc {
   int64_t f_base;      // element offset of the instance in f
   int64_t w_base;      // element offset of the instance in w
   int64_t nodes;       // Nd * Nc
-  double param[4];     // advection: a_k; Euler: gamma
+  double param[4];     // advection: a_k; Euler: gamma; D2Q9: gravity g
   double lambda;
   int32_t nv, m, dim, feq;
-  int8_t axis[kMaxNV]; // velocity i = sign[i] * lambda * e_axis[i]
+  int8_t axis[kMaxNV]; // {+-lambda e_k} sets: velocity i = sign[i] * lambda * e_axis[i]
   int8_t sign[kMaxNV];
+  int8_t cx[kMaxNV];   // D2Q9: velocity i = lambda (cx[i], cy[i])
+  int8_t cy[kMaxNV];
   int16_t pad;
 };
 
@@ -86,7 +88,8 @@ struct RelaxItem {
 // Inflow-equilibrium items: one per (instance, velocity).
 struct InflowDesc {
   int64_t fb_base;     // fb offset of (instance, v, k=0)
-  int64_t per_comp;    // values per component
+  int64_t w_base;      // w_inflow offset of (instance, v, moment 0)
+  int64_t per_comp;    // inflow points of the velocity (values per component)
   int32_t relax_desc;
   int32_t vel;
 };
@@ -158,6 +161,14 @@ hipError_t launch_relax(int prec, int nv, int m, const RelaxItem *items, int n_i
 hipError_t launch_inflow_eq(int nv, int m, const InflowDesc *items, int n_items, const RelaxDesc *descs,
                             const double *w_inflow, double *fb, hipStream_t st);
 
+// D2Q9 lattice instances (Sec. 5.1): mode 0 applies S(h_pre) C(omega)
+// S(h_post) at every node (the source terms only where the instance has
+// gravity), mode 1 sets f = f^eq(w_in).
+hipError_t launch_lattice(int prec, const RelaxItem *items, int n_items, const RelaxDesc *descs, void *f,
+                          double *w_out, const double *w_in, double omega, double h_pre, double h_post, int mode,
+                          hipStream_t st);
+hipError_t launch_lattice_inflow(const InflowDesc *items, int n_items, const RelaxDesc *descs, const double *w_in,
+                                 double *fb, hipStream_t st);
 hipError_t launch_fill(double *p, int64_t n, double value, hipStream_t st);
 hipError_t launch_fill_int(int32_t *p, int64_t n, int32_t value, hipStream_t st);
 hipError_t launch_fill_u64(uint64_t *p, int64_t n, uint64_t value, hipStream_t st);

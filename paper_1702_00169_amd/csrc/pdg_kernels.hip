@@ -604,7 +604,7 @@ __global__ __launch_bounds__(kBlock) void inflow_eq_kernel(const InflowDesc *__r
   for (int64_t e = (int64_t)blockIdx.x * kBlock + threadIdx.x; e < it.per_comp; e += (int64_t)gridDim.x * kBlock) {
     double w[M];
 #pragma unroll
-    for (int k = 0; k < M; ++k) w[k] = w_inflow[it.fb_base + k * it.per_comp + e];
+    for (int k = 0; k < M; ++k) w[k] = w_inflow[it.w_base + k * it.per_comp + e];
     double fe[NV][M];
     equilibrium<NV, M>(d, w, fe);
 #pragma unroll
@@ -613,6 +613,122 @@ __global__ __launch_bounds__(kBlock) void inflow_eq_kernel(const InflowDesc *__r
 #pragma unroll
         for (int k = 0; k < M; ++k) fb[it.fb_base + k * it.per_comp + e] = fe[i][k];
       }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// D2Q9 lattice model of the isothermal Euler equations with gravity (Sec. 5.1)
+// ---------------------------------------------------------------------------
+// w = P f = (rho, rho u_x, rho u_y); with c^2 = lambda^2 / 3 and
+// s_i = (c_i . u) / lambda for v_i = lambda c_i:
+//   f_i^eq = wt_i rho (1 + 3 s_i + 9/2 s_i^2 - 3/2 |u|^2 / lambda^2),
+// wt = 4/9 (c_i = 0), 1/9 (|c_i| = 1), 1/36 (|c_i|^2 = 2).
+__device__ inline double lattice_weight(int cx, int cy) {
+  const int r = cx * cx + cy * cy;
+  return r == 0 ? 4.0 / 9.0 : (r == 1 ? 1.0 / 9.0 : 1.0 / 36.0);
+}
+
+__device__ inline double lattice_feq(double wt, int cx, int cy, double rho, double jx, double jy, double inv_l) {
+  const double ux = jx / rho, uy = jy / rho;
+  const double s = (cx * ux + cy * uy) * inv_l;
+  const double uu = (ux * ux + uy * uy) * inv_l * inv_l;
+  return wt * rho * (1.0 + 3.0 * s + 4.5 * s * s - 1.5 * uu);
+}
+
+// Source step S_2(h) on the equilibrium part (Sec. 3.2): the moments move by
+// h S(w), S = (0, 0, -g rho), which keeps rho, so the Crank-Nicolson update
+// is exact; f moves by f^eq(w') - f^eq(w).
+__device__ inline void lattice_source(const RelaxDesc &d, double (&fv)[9], const double (&wt)[9], double rho,
+                                      double jx, double &jy, double h, double inv_l) {
+  const double jy2 = jy - h * d.param[0] * rho;
+#pragma unroll
+  for (int i = 0; i < 9; ++i)
+    fv[i] += lattice_feq(wt[i], d.cx[i], d.cy[i], rho, jx, jy2, inv_l) -
+             lattice_feq(wt[i], d.cx[i], d.cy[i], rho, jx, jy, inv_l);
+  jy = jy2;
+}
+
+template <int PREC>
+__global__ __launch_bounds__(kBlock) void lattice_kernel(const RelaxItem *__restrict__ items,
+                                                        const RelaxDesc *__restrict__ descs,
+                                                        typename Pol<PREC>::St *__restrict__ f,
+                                                        double *__restrict__ w_out, const double *__restrict__ w_in,
+                                                        double omega, double h_pre, double h_post, int mode) {
+  using St = typename Pol<PREC>::St;
+  const RelaxItem it = items[blockIdx.x];
+  const RelaxDesc d = descs[it.desc];
+  const int64_t nodes = d.nodes;
+  St *fi = f + d.f_base;
+  const double lam = d.lambda;
+  const double inv_l = 1.0 / lam;
+  const bool source = d.param[0] != 0.0;
+  double wt[9];
+#pragma unroll
+  for (int i = 0; i < 9; ++i) wt[i] = lattice_weight(d.cx[i], d.cy[i]);
+  for (int64_t node = it.node0 + threadIdx.x; node < it.node0 + it.count; node += kBlock) {
+    double fv[9];
+    double rho, jx, jy;
+    if (mode == 0) {
+#pragma unroll
+      for (int i = 0; i < 9; ++i) fv[i] = (double)ld_state(fi + (int64_t)i * nodes + node);
+      // moments: Neumaier compensated sums in a fixed order
+      double acc[3] = {fv[0], fv[0] * d.cx[0], fv[0] * d.cy[0]};
+      double comp[3] = {0.0, 0.0, 0.0};
+#pragma unroll
+      for (int i = 1; i < 9; ++i) {
+        const double x[3] = {fv[i], fv[i] * d.cx[i], fv[i] * d.cy[i]};
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+          const double tt = acc[k] + x[k];
+          comp[k] += (fabs(acc[k]) >= fabs(x[k])) ? ((acc[k] - tt) + x[k]) : ((x[k] - tt) + acc[k]);
+          acc[k] = tt;
+        }
+      }
+      rho = acc[0] + comp[0];
+      jx = lam * (acc[1] + comp[1]);
+      jy = lam * (acc[2] + comp[2]);
+    } else {
+      rho = w_in[d.w_base + node];
+      jx = w_in[d.w_base + nodes + node];
+      jy = w_in[d.w_base + 2 * nodes + node];
+#pragma unroll
+      for (int i = 0; i < 9; ++i) fv[i] = 0.0;
+    }
+    if (mode == 1) {
+#pragma unroll
+      for (int i = 0; i < 9; ++i)
+        st_state(fi + (int64_t)i * nodes + node, (St)lattice_feq(wt[i], d.cx[i], d.cy[i], rho, jx, jy, inv_l));
+      continue;
+    }
+    if (source && h_pre != 0.0) lattice_source(d, fv, wt, rho, jx, jy, h_pre, inv_l);
+#pragma unroll
+    for (int i = 0; i < 9; ++i)
+      fv[i] = fma(omega, lattice_feq(wt[i], d.cx[i], d.cy[i], rho, jx, jy, inv_l) - fv[i], fv[i]);
+    if (source && h_post != 0.0) lattice_source(d, fv, wt, rho, jx, jy, h_post, inv_l);
+#pragma unroll
+    for (int i = 0; i < 9; ++i) st_state(fi + (int64_t)i * nodes + node, (St)fv[i]);
+    if (w_out != nullptr) {
+      w_out[d.w_base + node] = rho;
+      w_out[d.w_base + nodes + node] = jx;
+      w_out[d.w_base + 2 * nodes + node] = jy;
+    }
+  }
+}
+
+__global__ __launch_bounds__(kBlock) void lattice_inflow_kernel(const InflowDesc *__restrict__ items,
+                                                               const RelaxDesc *__restrict__ descs,
+                                                               const double *__restrict__ w_inflow,
+                                                               double *__restrict__ fb) {
+  const InflowDesc it = items[blockIdx.y];
+  const RelaxDesc d = descs[it.relax_desc];
+  const int cx = d.cx[it.vel], cy = d.cy[it.vel];
+  const double wt = lattice_weight(cx, cy);
+  const double inv_l = 1.0 / d.lambda;
+  for (int64_t e = (int64_t)blockIdx.x * kBlock + threadIdx.x; e < it.per_comp; e += (int64_t)gridDim.x * kBlock) {
+    const double rho = w_inflow[it.w_base + e];
+    const double jx = w_inflow[it.w_base + it.per_comp + e];
+    const double jy = w_inflow[it.w_base + 2 * it.per_comp + e];
+    fb[it.fb_base + e] = lattice_feq(wt, cx, cy, rho, jx, jy, inv_l);
   }
 }
 
@@ -1248,6 +1364,35 @@ hipError_t launch_dense_sweep(int prec, bool level, int np, int dim, const Dense
     case kRefine: return go_dense_shape<kRefine>(level, np, dim, tiles, order, n_tiles, fams, descs, table, dt_idx, f, fb_old, fb_new, traces, counter, err_flag, st);
     default: return hipErrorInvalidValue;
   }
+}
+
+hipError_t launch_lattice(int prec, const RelaxItem *items, int n_items, const RelaxDesc *descs, void *f,
+                          double *w_out, const double *w_in, double omega, double h_pre, double h_post, int mode,
+                          hipStream_t st) {
+  if (n_items <= 0) return hipSuccess;
+  switch (prec) {
+    case kF64:
+      hipLaunchKernelGGL(lattice_kernel<kF64>, dim3(n_items), dim3(kBlock), 0, st, items, descs,
+                         static_cast<double *>(f), w_out, w_in, omega, h_pre, h_post, mode);
+      break;
+    case kF32:
+      hipLaunchKernelGGL(lattice_kernel<kF32>, dim3(n_items), dim3(kBlock), 0, st, items, descs,
+                         static_cast<float *>(f), w_out, w_in, omega, h_pre, h_post, mode);
+      break;
+    case kRefine:
+      hipLaunchKernelGGL(lattice_kernel<kRefine>, dim3(n_items), dim3(kBlock), 0, st, items, descs,
+                         static_cast<double *>(f), w_out, w_in, omega, h_pre, h_post, mode);
+      break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_lattice_inflow(const InflowDesc *items, int n_items, const RelaxDesc *descs, const double *w_in,
+                                 double *fb, hipStream_t st) {
+  if (n_items <= 0) return hipSuccess;
+  hipLaunchKernelGGL(lattice_inflow_kernel, dim3(64, n_items), dim3(kBlock), 0, st, items, descs, w_in, fb);
+  return hipGetLastError();
 }
 
 hipError_t launch_fill(double *p, int64_t n, double value, hipStream_t st) {

@@ -14,6 +14,8 @@ from oracle import step as ost
 def inst_dict(inst):
     if inst.feq_kind == "advection":
         par = list(inst.feq_param["a"])
+    elif inst.feq_kind == "d2q9":
+        par = [inst.feq_param["g"]]
     else:
         par = [inst.feq_param["gamma"]]
     return dict(dim=inst.dim, n=list(inst.n), degree=inst.degree, v=np.asarray(inst.vel, float), m=inst.m,
@@ -72,6 +74,19 @@ def oracle_fb_from_function(oprob, i, fn_of_inst_v):
     return [fn_of_inst_v(i, v, oprob.entries(v)["coords"]) for v in range(oprob.nv)]
 
 
+def gpu_w_inflow_from_function(prob, insts, fn_of_inst_v, nw):
+    """w_inflow (numpy) for pdg_inflow_equilibrium: per instance and velocity,
+    nw blocks of the velocity's inflow points; fn(i, v, pts) -> (nw_i, npts)."""
+    blocks = []
+    for i, inst in enumerate(insts):
+        for v, faces in enumerate(gpu_inflow_points(prob, i, inst)):
+            if not faces:
+                continue
+            vals = [fn_of_inst_v(i, v, pts) for pts in faces]
+            blocks.append(np.concatenate(vals, axis=1).ravel())
+    return np.concatenate(blocks) if blocks else np.zeros(0)
+
+
 def gpu_to_oracle(f_flat, inst, f_off=0):
     nc, nd = sizes(inst)
     nv, m = inst.vel.shape[0], inst.m
@@ -92,14 +107,15 @@ def rel_errors(got, want):
 
 
 def gpu_initial_state(prob, insts, torch, dtype):
-    """f = f^eq(w0), fb = f^eq(w0 on the inflow points), built by the library."""
+    """f = f^eq(w0), fb = f^eq(w0 on the inflow points), built by the library
+    (w0 gives m moments per point, or 3 for the D2Q9 model)."""
     w = np.zeros(prob.layout["w_elems"])
     for i, inst in enumerate(insts):
         vol, _ = prob.node_coords(i)
         pts = vol.reshape(inst.dim, -1).T
         vals = inst.w0(pts)                            # (m, nd*nc)
         w[prob.layout["w_off"][i]:prob.layout["w_off"][i + 1]] = vals.ravel()
-    fbw = gpu_fb_from_function(prob, insts, lambda i, v, pts: insts[i].w0(pts))
+    fbw = gpu_w_inflow_from_function(prob, insts, lambda i, v, pts: insts[i].w0(pts), None)
     dev = "cuda"
     w_t = torch.tensor(w, device=dev)
     fbw_t = torch.tensor(fbw, device=dev)
@@ -113,5 +129,5 @@ def gpu_initial_state(prob, insts, torch, dtype):
 
 def oracle_initial_state(oprob, inst):
     x = oprob.mesh.node_coords().reshape(-1, oprob.mesh.dim)
-    w = inst.w0(x).reshape(oprob.m, oprob.mesh.nc, oprob.mesh.nd)
+    w = inst.w0(x).reshape(-1, oprob.mesh.nc, oprob.mesh.nd)
     return oprob.feq(w), oprob.inflow_from_w(inst.w0)

@@ -272,3 +272,45 @@ def _split_faces(flat, vel, n, npn):
         out.append(flat[off:off + dim * npts].reshape(dim, npts))
         off += dim * npts
     return out
+
+
+def _d2q9_desc(**kw):
+    d = dict(dim=2, n=[5, 4], degree=2, v=np.array(D2Q9, float) * 1.5, m=1, feq="d2q9", feq_param=[0.7])
+    d.update(kw)
+    return d
+
+
+def test_d2q9_model_layout_has_three_moments(lib):
+    prob = lib.Problem([_d2q9_desc(), _desc()])
+    lay = prob.layout
+    nodes = 20 * 9
+    assert lay["w_off"][1] == 3 * nodes                 # rho, rho u_x, rho u_y
+    assert lay["w_elems"] == 3 * nodes + 12 * 9       # then the scalar instance (m = 1)
+    assert lay["f_elems"] == 9 * nodes + 4 * 12 * 9
+    prob.close()
+
+
+@pytest.mark.parametrize("kw", [
+    dict(m=2), dict(v=np.array(D2Q9[:8] + [[2, 0]], float)), dict(v=np.array(D2Q9, float) * [1.0, 2.0]),
+    dict(v=np.array(D2Q9[:8] + [[1, 1]], float)), dict(feq_param=[float("inf")]),
+    dict(v=np.zeros((9, 2))),
+])
+def test_d2q9_model_rejects_a_malformed_lattice(lib, kw):
+    with pytest.raises(lib.PdgError) as e:
+        lib.Problem([_d2q9_desc(**kw)])
+    assert e.value.status == lib.PDG_EINVAL
+
+
+def test_d2q9_model_accepts_any_velocity_order(lib):
+    perm = np.random.default_rng(0).permutation(9)
+    prob = lib.Problem([_d2q9_desc(v=np.array(D2Q9, float)[perm] * 0.5)])
+    assert prob.layout["w_elems"] == 3 * 20 * 9
+    prob.close()
+
+
+def test_source_before_prepare_is_a_state_error(lib):
+    prob = lib.Problem([_d2q9_desc()])
+    assert lib._lib.pdg_source(prob.ctx, ctypes.c_void_p(8), 0.1, None) == lib.PDG_ESTATE
+    assert lib._lib.pdg_source(None, ctypes.c_void_p(8), 0.1, None) == lib.PDG_EINVAL
+    assert lib._lib.pdg_source(prob.ctx, None, 0.1, None) == lib.PDG_EINVAL
+    prob.close()

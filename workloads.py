@@ -10,7 +10,9 @@ and f^b = f^eq(w_0) on the inflow boundary with its own code.
 The paper's meshes and physics runs are not available, so these workloads
 stand in for them: 2D and 3D uniform meshes, the {+-lambda e_k} velocity sets
 (the first 2D / 6 points of the paper's D2Q9 / D3Q27 lists), scalar advection
-and compressible Euler equilibria, and smooth seeded data.
+and compressible Euler equilibria, and smooth seeded data; and the D2Q9
+isothermal gravity test of Sec. 5.1 (the paper's velocity list and its
+hydrostatic steady state rho_0 exp(-g y / c^2), c^2 = lambda^2 / 3).
 """
 
 import math
@@ -21,21 +23,25 @@ D2Q4 = np.array([[1.0, 0.0], [0.0, 1.0], [-1.0, 0.0], [0.0, -1.0]])
 D3Q6 = np.array([[1.0, 0.0, 0.0], [0.0, 1.0, 0.0], [-1.0, 0.0, 0.0],
                  [0.0, -1.0, 0.0], [0.0, 0.0, -1.0], [0.0, 0.0, 1.0]])
 
+D2Q9 = np.array([[0.0, 0.0], [1.0, 0.0], [0.0, 1.0], [-1.0, 0.0], [0.0, -1.0],
+                 [1.0, 1.0], [-1.0, 1.0], [-1.0, -1.0], [1.0, -1.0]])
+
 GAMMA = 1.4
 
 
 class Instance:
     """One independent kinetic problem on the unit box."""
 
-    def __init__(self, dim, n, degree, lam, m, feq_kind, feq_param, w0, name=""):
+    def __init__(self, dim, n, degree, lam, m, feq_kind, feq_param, w0, name="", vel=None):
         self.dim = dim
         self.n = tuple(n)
         self.degree = degree
         self.lam = float(lam)
-        self.vel = (D2Q4 if dim == 2 else D3Q6) * self.lam
+        base = (D2Q4 if dim == 2 else D3Q6) if vel is None else np.asarray(vel, dtype=float)
+        self.vel = base * self.lam
         self.m = m
-        self.feq_kind = feq_kind        # "advection" | "euler"
-        self.feq_param = feq_param      # {"a": [...]} or {"gamma": g}
+        self.feq_kind = feq_kind        # "advection" | "euler" | "d2q9"
+        self.feq_param = feq_param      # {"a": [...]}, {"gamma": g} or {"g": gravity}
         self.w0 = w0                    # callable (N, dim) -> (m, N)
         self.lo = np.zeros(dim)
         self.hi = np.ones(dim)
@@ -124,6 +130,28 @@ def euler_at_rest(rho_fn, p_fn, dim, gamma=GAMMA):
     return w0
 
 
+def hydrostatic_d2q9(rho0, g, lam, bump=0.0, centre=(0.5, 0.5), width2=40.0):
+    """(rho, rho u_x, rho u_y) of the fluid at rest in gravity -g e_y,
+    rho = rho0 exp(-g y / c^2), c^2 = lambda^2 / 3 (Sec. 5.1), times an
+    optional density bump 1 + bump exp(-|x - centre|^2 width2)."""
+    c2 = lam * lam / 3.0
+    centre = np.asarray(centre, dtype=float)
+
+    def w0(x):
+        x = np.asarray(x, dtype=float)
+        rho = rho0 * np.exp(-g * x[:, 1] / c2)
+        if bump:
+            rho = rho * (1.0 + bump * np.exp(-width2 * np.sum((x - centre) ** 2, axis=1)))
+        return np.stack([rho, np.zeros_like(rho), np.zeros_like(rho)])
+    return w0
+
+
+def gravity2d_instance(n, degree, lam=1.0, g=1.0, rho0=1.0, bump=0.0):
+    """The D2Q9 isothermal gravity problem of Sec. 5.1 on the unit square."""
+    return Instance(2, (n, n), degree, lam, 1, "d2q9", {"g": g}, hydrostatic_d2q9(rho0, g, lam, bump),
+                    name=f"gravity2d_n{n}_d{degree}", vel=D2Q9)
+
+
 def uniform_state(values):
     values = np.asarray(values, dtype=float)
 
@@ -183,6 +211,12 @@ def make(name, seed=0, scale=None):
                         name=f"euler3d_n{n}_d2")
         return Workload(name, [inst], dt=(1.0 / n) / 3.0, steps=20,
                         description="3D Euler, D3Q6 lambda=3, m=5, 128^3 cells, degree 2, density/pressure bumps")
+    if name == "gravity2d_256":
+        n = scale or 256
+        inst = gravity2d_instance(n, 3, lam=1.0, g=1.0, bump=0.05)
+        return Workload(name, [inst], dt=1.0 / n, steps=10,
+                        description="2D isothermal Euler with gravity, D2Q9 lambda=1 (c^2=1/3), g=1, "
+                                    "256^2 cells, degree 3, hydrostatic state with a 5% density bump")
     if name == "batch96":
         count = 96 if scale is None else scale
         insts = []
