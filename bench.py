@@ -39,19 +39,21 @@ DEFAULT_WORKLOAD = "adv3d_64"
 
 
 def inst_dict(inst):
-    par = list(inst.feq_param["a"]) if inst.feq_kind == "advection" else [inst.feq_param["gamma"]]
+    par = {"advection": lambda p: list(p["a"]), "euler": lambda p: [p["gamma"]],
+           "d2q9": lambda p: [p["g"]]}[inst.feq_kind](inst.feq_param)
     return dict(dim=inst.dim, n=list(inst.n), degree=inst.degree, v=np.asarray(inst.vel, float), m=inst.m,
                 lo=list(inst.lo), hi=list(inst.hi), feq=inst.feq_kind, feq_param=par)
 
 
 def initial_state(pdg, prob, insts, torch, dtype):
-    """f = f^eq(w0) and fb = f^eq(w0 at the inflow points), built on the device."""
+    """f = f^eq(w0) and fb = f^eq(w0 at the inflow points), built on the device.
+    w_inflow holds, per instance and velocity, the moments of w0 at the
+    velocity's inflow points (m moments, or 3 for the D2Q9 model)."""
     w = np.empty(prob.layout["w_elems"])
-    fbw = np.empty(prob.layout["fb_elems"])
+    fbw_blocks = []
     for i, inst in enumerate(insts):
         vol, inflow = prob.node_coords(i)
         w[prob.layout["w_off"][i]:prob.layout["w_off"][i + 1]] = inst.w0(vol.reshape(inst.dim, -1).T).ravel()
-        off = prob.layout["fb_off"][i]
         ioff = 0
         nc = int(np.prod(inst.n))
         for v in range(inst.vel.shape[0]):
@@ -64,9 +66,8 @@ def initial_state(pdg, prob, insts, torch, dtype):
                 blocks.append(inst.w0(pts))
                 ioff += inst.dim * npts
             if blocks:
-                vals = np.concatenate(blocks, axis=1)   # fb block [k][face][t][tau]
-                fbw[off:off + vals.size] = vals.ravel()
-                off += vals.size
+                fbw_blocks.append(np.concatenate(blocks, axis=1).ravel())   # [k][face][t][tau]
+    fbw = np.concatenate(fbw_blocks) if fbw_blocks else np.zeros(1)
     f = torch.empty(prob.layout["f_elems"], dtype=dtype, device="cuda")
     fb = torch.empty(prob.layout["fb_elems"], dtype=torch.float64, device="cuda")
     w_t = torch.from_numpy(w).cuda()
@@ -78,10 +79,17 @@ def initial_state(pdg, prob, insts, torch, dtype):
 
 
 def kernel_source_hash():
+    """Hash of the sources that define the axis-aligned sweep kernel: its
+    translation unit, the device helpers, and the part of the internal header
+    that holds its item and operator layouts (up to the node-local structs)."""
+    csrc = os.path.join(ROOT, "paper_1702_00169_amd", "csrc")
     h = hashlib.sha256()
-    for name in ("pdg_kernels.hip", "pdg_internal.h", "pdg_host.cpp"):
-        with open(os.path.join(ROOT, "paper_1702_00169_amd", "csrc", name), "rb") as fh:
+    for name in ("pdg_sweep.hip", "pdg_device.h"):
+        with open(os.path.join(csrc, name), "rb") as fh:
             h.update(fh.read())
+    with open(os.path.join(csrc, "pdg_internal.h"), "rb") as fh:
+        text = fh.read()
+    h.update(text.split(b"// Per-instance data of the node-local kernels.")[0])
     return h.hexdigest()[:16]
 
 
@@ -174,11 +182,11 @@ def cpu_baseline(wl_name, seed, target_s):
         inst = wl.instances[0]
         prob = ost.Problem(inst.n, inst.lo, inst.hi, inst.degree, inst.vel, inst.m, inst.feq_kind, inst.feq_param)
         x = prob.mesh.node_coords().reshape(-1, inst.dim)
-        f0 = prob.feq(inst.w0(x).reshape(inst.m, prob.mesh.nc, prob.mesh.nd))
+        f0 = prob.feq(inst.w0(x).reshape(-1, prob.mesh.nc, prob.mesh.nd))
         fb = prob.inflow_from_w(inst.w0)
         t0 = time.perf_counter()
         f = prob.transport(f0, fb, fb, wl.dt, wl.theta)
-        prob.collide(f, wl.omega)
+        prob.local(f, wl.dt / 2, wl.omega, wl.dt / 2)   # S C S; the source is the identity without one
         return inst, time.perf_counter() - t0
 
     # calibrate the oracle's rate on a small mesh, then size the sample for ~target_s
@@ -276,9 +284,11 @@ def main():
                                                "the other precisions are compared with it after the same steps")
 
     traffic = traffic_for(args.workload, PREC_NAMES[prec_main])  # HBM bytes per sweep launch, or None
+    # velocities with two or three non-zero components go through the dense tiled sweep
+    dense = any(np.count_nonzero(v) >= 2 for inst in wl.instances for v in inst.vel)
     roof = {"bound": "hbm", "achieved": main_res["sweep_gbs"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": main_res["sweep_gbs"] / HBM_PEAK_GBS, "traffic": traffic,
-            "kernel": "sweep_kernel", "algorithmic_bytes_per_launch": main_res["bytes_per_sweep"],
+            "kernel": "transport sweep (sweep_kernel" + (" + dense_sweep_kernel)" if dense else ")"), "algorithmic_bytes_per_launch": main_res["bytes_per_sweep"],
             "launch_us": main_res["sweep_us"], "device_copy_gbs": copy_gbs,
             "traffic_over_algorithmic": (traffic / main_res["bytes_per_sweep"]) if traffic else None,
             "step_gbs_at_32B_per_dof": main_res["value"] * 4 * (4 if prec_main == pdg.PDG_FP32 else 8) / 1e9}
@@ -287,7 +297,8 @@ def main():
               "instances": len(wl.instances), "cells": list(inst0.n) if len(wl.instances) == 1 else "per instance",
               "degree": inst0.degree if len(wl.instances) == 1 else "per instance",
               "nv": int(inst0.vel.shape[0]), "m": inst0.m, "dt": wl.dt, "theta": wl.theta, "omega": wl.omega,
-              "scheme": "collapsed Strang", "precision": PREC_NAMES[prec_main], "seed": args.seed}
+              "scheme": "collapsed Strang" + (" with source" if inst0.feq_kind == "d2q9" else ""),
+              "precision": PREC_NAMES[prec_main], "seed": args.seed}
     out = {"metric": METRIC, "value": main_res["value"], "unit": "DoF-updates/s", "n_gpus": 1,
            "steps": args.steps, "warmup": args.warmup, "ms_per_step": main_res["ms_per_step"],
            "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": DTYPE_NAMES[prec_main],

@@ -1,0 +1,495 @@
+// gfx950 kernels of the transport sweep for velocities with two or three
+// non-zero components: dense cell blocks in a tiled wavefront.
+
+#include "pdg_device.h"
+
+namespace pdg {
+namespace {
+
+// ---------------------------------------------------------------------------
+// dense path: velocities with two or three non-zero components
+// ---------------------------------------------------------------------------
+// Operator row layout (doubles): M (N x N) | G_0 G_1 G_2 (N x F each) | A | B | Ainv
+struct DenseRowLayout {
+  int64_t n, f;
+  __host__ __device__ int64_t g(int a) const { return n * n + a * n * f; }
+  __host__ __device__ int64_t a_off() const { return n * n + 3 * n * f; }
+  __host__ __device__ int64_t b_off() const { return 2 * n * n + 3 * n * f; }
+  __host__ __device__ int64_t ai_off() const { return 3 * n * n + 3 * n * f; }
+};
+
+__global__ __launch_bounds__(kDenseThreads) void dense_invert_kernel(double *table, const int64_t *row_off,
+                                                                    const DenseDesc *descs,
+                                                                    const int32_t *row_desc, const double *c0,
+                                                                    int32_t *flags, int n, int F) {
+  __shared__ double a[kDenseMaxN][kDenseMaxN + 1];
+  __shared__ double inv[kDenseMaxN][kDenseMaxN + 1];
+  __shared__ double fct[kDenseMaxN];
+  __shared__ double norm;
+  __shared__ int piv, sing;
+  const int r = blockIdx.x;
+  const int t = threadIdx.x;
+  double *row = table + row_off[r];
+  const DenseRowLayout L{n, F};
+  for (int e = t; e < n * n; e += kDenseThreads) {
+    const int i = e / n, j = e - (e / n) * n;
+    a[i][j] = row[L.a_off() + e];
+    inv[i][j] = (i == j) ? 1.0 : 0.0;
+  }
+  __syncthreads();
+  if (t == 0) {
+    double m = 0.0;
+    for (int i = 0; i < n; ++i)
+      for (int j = 0; j < n; ++j) m = fmax(m, fabs(a[i][j]));
+    norm = m;
+    sing = 0;
+  }
+  __syncthreads();
+  for (int col = 0; col < n; ++col) {
+    if (t == 0) {
+      int pv = col;
+      for (int i = col + 1; i < n; ++i)
+        if (fabs(a[i][col]) > fabs(a[pv][col])) pv = i;
+      piv = pv;
+      if (!(fabs(a[pv][col]) > 1e-300 * norm)) sing = 1;
+    }
+    __syncthreads();
+    if (sing) break;
+    if (piv != col) {
+      for (int j = t; j < n; j += kDenseThreads) {
+        double tmp = a[col][j];
+        a[col][j] = a[piv][j];
+        a[piv][j] = tmp;
+        tmp = inv[col][j];
+        inv[col][j] = inv[piv][j];
+        inv[piv][j] = tmp;
+      }
+    }
+    __syncthreads();
+    const double rp = 1.0 / a[col][col];
+    __syncthreads();
+    for (int j = t; j < n; j += kDenseThreads) {
+      a[col][j] *= rp;
+      inv[col][j] *= rp;
+    }
+    __syncthreads();
+    for (int i = t; i < n; i += kDenseThreads) fct[i] = (i == col) ? 0.0 : a[i][col];
+    __syncthreads();
+    for (int e = t; e < n * n; e += kDenseThreads) {
+      const int i = e / n, j = e - (e / n) * n;
+      if (i == col) continue;
+      a[i][j] = fma(-fct[i], a[col][j], a[i][j]);
+      inv[i][j] = fma(-fct[i], inv[col][j], inv[i][j]);
+    }
+    __syncthreads();
+  }
+  if (t == 0) flags[r] = sing;
+  if (sing) return;
+  const DenseDesc &d = descs[row_desc[r]];
+  for (int e = t; e < n * n; e += kDenseThreads) {
+    const int i = e / n, j = e - (e / n) * n;
+    double acc = 0.0;
+    for (int k = 0; k < n; ++k) acc = fma(inv[i][k], row[L.b_off() + (int64_t)k * n + j], acc);
+    row[e] = acc;                       // M = Ainv B
+    row[L.ai_off() + e] = inv[i][j];    // Ainv
+  }
+  for (int e = t; e < 3 * n * F; e += kDenseThreads) {
+    const int ax = e / (n * F);
+    const int rem = e - ax * n * F;
+    const int i = rem / F, tt = rem - (rem / F) * F;
+    const double c = c0[3 * r + ax];
+    row[L.g(ax) + (int64_t)i * F + tt] = (c == 0.0) ? 0.0 : c * inv[i][d.face_q[ax][tt]];
+  }
+}
+
+// downwind-local node index of face node t on the face q_a = qa of axis a
+template <int NP, int DIM>
+__device__ constexpr int face_node(int a, int t, int qa) {
+  int q = 0, stride = 1, rem = t;
+  for (int b = 0; b < DIM; ++b) {
+    int qb = 0;
+    if (b == a) {
+      qb = qa;
+    } else {
+      qb = rem % NP;
+      rem /= NP;
+    }
+    q += qb * stride;
+    stride *= NP;
+  }
+  return q;
+}
+
+// Cross-tile hand-off.  A tile's inflow traces are written by its upwind
+// tiles, which may run on another XCD (each XCD has its own L2).  Every trace
+// value is written once per sweep, into a slot that was filled with a
+// signalling-NaN sentinel before the launch; arithmetic never produces a
+// signalling NaN, so a slot that no longer holds the sentinel holds its final
+// value.  Both sides use device-scope atomic read-modify-writes, which are
+// performed at the device's point of coherence, so no cache-wide write-back or
+// invalidation is needed and each cell waits only for its own upwind cell.
+// Current content of a trace slot, read with a compare-and-swap that writes
+// the sentinel back only where it already is (an idempotent or-with-zero
+// would be turned into a plain load by the compiler).
+__device__ inline uint64_t dense_peek_trace(uint64_t *p) {
+  uint64_t cur = kDenseTraceEmpty;
+  __hip_atomic_compare_exchange_strong(p, &cur, kDenseTraceEmpty, __ATOMIC_RELAXED, __ATOMIC_RELAXED,
+                                       __HIP_MEMORY_SCOPE_AGENT);
+  return cur;
+}
+
+// The inflow traces a cell needs from upwind tiles (up to one face per axis).
+// Every slot is requested at once, so a ready face costs one round trip; the
+// slots still empty are polled again after a short sleep.  The producer was
+// claimed earlier and is resident, so the wait ends; the wall-clock bound
+// (1 s at the 100 MHz constant clock) and the shared error flag turn a logic
+// error into one reported failure instead of a hang.
+template <int DIM, int F>
+__device__ inline void dense_take_faces(uint64_t *const (&src)[DIM], uint64_t (&b)[DIM][F], int32_t *err_flag) {
+  bool ready = true;
+#pragma unroll
+  for (int a = 0; a < DIM; ++a)
+    if (src[a])
+#pragma unroll
+      for (int tt = 0; tt < F; ++tt) b[a][tt] = dense_peek_trace(src[a] + tt);
+#pragma unroll
+  for (int a = 0; a < DIM; ++a)
+    if (src[a])
+#pragma unroll
+      for (int tt = 0; tt < F; ++tt) ready = ready && b[a][tt] != kDenseTraceEmpty;
+  if (ready) return;
+  const uint64_t t_start = wall_clock64();
+  for (;;) {
+    __builtin_amdgcn_s_sleep(2);
+    ready = true;
+#pragma unroll
+    for (int a = 0; a < DIM; ++a)
+      if (src[a])
+#pragma unroll
+        for (int tt = 0; tt < F; ++tt)
+          if (b[a][tt] == kDenseTraceEmpty) b[a][tt] = dense_peek_trace(src[a] + tt);
+#pragma unroll
+    for (int a = 0; a < DIM; ++a)
+      if (src[a])
+#pragma unroll
+        for (int tt = 0; tt < F; ++tt) ready = ready && b[a][tt] != kDenseTraceEmpty;
+    if (ready) return;
+    if (wall_clock64() - t_start > 100000000ull ||
+        __hip_atomic_load(err_flag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0) {
+      __hip_atomic_fetch_or(err_flag, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+#pragma unroll
+      for (int a = 0; a < DIM; ++a)
+#pragma unroll
+        for (int tt = 0; tt < F; ++tt)
+          if (b[a][tt] == kDenseTraceEmpty) b[a][tt] = 0;
+      return;
+    }
+  }
+}
+
+__device__ inline void dense_put_trace(uint64_t *p, double v) {
+  __hip_atomic_exchange(p, (uint64_t)__double_as_longlong(v), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// One wave per tile, in one of two schedules:
+// * claimed (LEVEL = false): one launch for all tiles.  The tile index is
+//   claimed by lane 0 from a counter that hands out tiles in dependency order
+//   (upwind tiles first) and broadcast with readfirstlane, so it is
+//   wave-uniform; inflow traces arrive through the atomic slots above, cell by
+//   cell, so a tile starts as soon as its first upwind cells are done.
+// * levelled (LEVEL = true): one launch per tile diagonal; the launch's tiles
+//   are order[0 .. n_tiles).  Upwind tiles belong to earlier launches, whose
+//   writes the kernel boundary makes visible: plain loads and stores, no
+//   waiting.
+// Either way descriptors and operator rows are read through scalar loads and
+// all control flow that depends on the tile is uniform.  Inside the tile the
+// cells are solved diagonal by diagonal; the inflow traces of a cell come from
+// the previous diagonal through LDS, from an upwind tile through the trace
+// slots, or from the domain inflow data.
+template <int PREC, int NP, int DIM, bool LEVEL>
+__global__ __launch_bounds__(kDenseThreads) void dense_sweep_kernel(
+    const DenseTile *__restrict__ tiles, const int32_t *__restrict__ order, const DenseFam *__restrict__ fams,
+    const DenseDesc *__restrict__ descs, const double *__restrict__ table, int dt_idx,
+    typename Pol<PREC>::St *__restrict__ f, const double *__restrict__ fb_old, const double *__restrict__ fb_new,
+    uint64_t *traces, int32_t *counter, int32_t *err_flag, int n_tiles) {
+  static_assert(kDenseThreads == 64, "one workgroup is one wave");
+  using St = typename Pol<PREC>::St;
+  using Rt = typename Pol<PREC>::Rt;
+  constexpr int N = DIM == 2 ? NP * NP : NP * NP * NP;
+  constexpr int F = DIM == 2 ? NP : NP * NP;
+  __shared__ Rt otr[3][kDenseThreads][F];  // outflow traces per axis of every cell of the tile
+  const int t = threadIdx.x;
+  int claim = blockIdx.x;
+  if (!LEVEL) {
+    if (t == 0) claim = atomicAdd(counter, 1);
+    claim = __builtin_amdgcn_readfirstlane(claim);
+    if (claim >= n_tiles) {  // the counter was not reset: report, do nothing
+      if (t == 0) __hip_atomic_fetch_or(err_flag, 2, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      return;
+    }
+  }
+  const int tile = order[claim];
+  const DenseTile tl = tiles[tile];
+  const DenseFam fm = fams[tl.fam];
+  const DenseDesc &d = descs[fm.desc];
+
+  // this thread's cell: local coordinates over the non-zero components
+  int cl[3] = {0, 0, 0}, tstride[3] = {0, 0, 0};
+  int rem = t, st_acc = 1;
+  bool active = true;
+#pragma unroll
+  for (int a = 0; a < DIM; ++a) {
+    if (d.sgn[a] == 0) continue;
+    cl[a] = rem % d.T[a];
+    rem /= d.T[a];
+    tstride[a] = st_acc;
+    st_acc *= d.T[a];
+  }
+  if (rem != 0) active = false;
+  int x[3] = {0, 0, 0};
+#pragma unroll
+  for (int a = 0; a < DIM; ++a) {
+    if (d.sgn[a] == 0) {
+      x[a] = (a == d.trans_axis) ? fm.slice : 0;
+    } else {
+      const int p = tl.tc[a] * d.T[a] + cl[a];
+      if (p >= d.n[a]) active = false;
+      x[a] = d.sgn[a] > 0 ? p : d.n[a] - 1 - p;
+    }
+  }
+  const int64_t cell = x[0] + (int64_t)d.n[0] * (x[1] + (int64_t)d.n[1] * x[2]);
+  const double *row = table + d.op_off + (int64_t)dt_idx * d.op_stride;
+  const DenseRowLayout L{N, F};
+
+  // load the cell and apply the local block
+  Rt fv[N], y[N];
+#pragma unroll
+  for (int q = 0; q < N; ++q) fv[q] = active ? (Rt)ld_state(f + fm.f_base + d.plane_off[q] + cell) : (Rt)0;
+  if (PREC == kRefine) {
+    double r[N];
+    float r32[N], y1[N];
+#pragma unroll
+    for (int i = 0; i < N; ++i) {
+      double acc = 0.0;
+#pragma unroll
+      for (int j = 0; j < N; ++j) acc = fma(row[L.b_off() + i * N + j], (double)fv[j], acc);
+      r[i] = acc;
+      r32[i] = (float)acc;
+    }
+#pragma unroll
+    for (int i = 0; i < N; ++i) {
+      float acc = 0.f;
+#pragma unroll
+      for (int j = 0; j < N; ++j) acc = fmaf((float)row[L.ai_off() + i * N + j], r32[j], acc);
+      y1[i] = acc;
+    }
+#pragma unroll
+    for (int i = 0; i < N; ++i) {
+      double acc = r[i];
+#pragma unroll
+      for (int j = 0; j < N; ++j) acc = fma(-row[L.a_off() + i * N + j], (double)y1[j], acc);
+      r32[i] = (float)acc;
+    }
+#pragma unroll
+    for (int i = 0; i < N; ++i) {
+      float acc = 0.f;
+#pragma unroll
+      for (int j = 0; j < N; ++j) acc = fmaf((float)row[L.ai_off() + i * N + j], r32[j], acc);
+      y[i] = (Rt)((double)y1[i] + (double)acc);
+    }
+  } else {
+#pragma unroll
+    for (int i = 0; i < N; ++i) {
+      Rt acc = 0;
+#pragma unroll
+      for (int j = 0; j < N; ++j) acc = fma((Rt)row[i * N + j], fv[j], acc);
+      y[i] = acc;
+    }
+  }
+  const Rt th = (Rt)d.theta;
+  const Rt omt = (Rt)1 - th;
+
+  int diag = 0, ndiag = 1;
+#pragma unroll
+  for (int a = 0; a < DIM; ++a)
+    if (d.sgn[a] != 0) {
+      diag += cl[a];
+      ndiag += d.T[a] - 1;
+    }
+  // Inflow data of the faces that are not fed from inside the tile: domain
+  // inflow (always ready), or, in the levelled schedule, the traces of an
+  // upwind tile of an earlier launch.  Both are fetched before the diagonal
+  // loop, so that the loop issues no global load it would have to wait for.
+  Rt uin[DIM][F];
+  uint64_t *rsrc[DIM];
+#pragma unroll
+  for (int a = 0; a < DIM; ++a) {
+    rsrc[a] = nullptr;
+#pragma unroll
+    for (int tt = 0; tt < F; ++tt) uin[a][tt] = (Rt)0;
+    if (!active || d.sgn[a] == 0 || cl[a] > 0) continue;
+    if (tl.up[a] >= 0) {
+      // face cell index of this cell on faces normal to a (tile-local)
+      int fc = 0, fs = 1;
+#pragma unroll
+      for (int b = 0; b < DIM; ++b)
+        if (b != a && d.sgn[b] != 0) {
+          fc += cl[b] * fs;
+          fs *= d.T[b];
+        }
+      rsrc[a] = traces + tl.trace_off + (int64_t)a * tl.slot + fc * F;
+      if (LEVEL)
+#pragma unroll
+        for (int tt = 0; tt < F; ++tt) uin[a][tt] = (Rt)__longlong_as_double((long long)rsrc[a][tt]);
+    } else {
+      // domain inflow face: transverse cell index over the other axes
+      int64_t tau = 0, ts = 1;
+#pragma unroll
+      for (int b = 0; b < DIM; ++b)
+        if (b != a) {
+          tau += x[b] * ts;
+          ts *= d.n[b];
+        }
+      const int64_t base = fm.fb_base + d.fb_axis_off[a] + tau;
+#pragma unroll
+      for (int tt = 0; tt < F; ++tt) {
+        const int64_t k = base + (int64_t)d.fb_t[a][tt] * d.fb_ntc[a];
+        uin[a][tt] = th * (Rt)fb_new[k] + omt * (Rt)fb_old[k];
+      }
+    }
+  }
+
+  for (int s = 0; s < ndiag; ++s) {
+    if (active && diag == s) {
+      if (!LEVEL) {
+        uint64_t rb[DIM][F];
+        dense_take_faces<DIM, F>(rsrc, rb, err_flag);
+#pragma unroll
+        for (int a = 0; a < DIM; ++a)
+          if (rsrc[a])
+#pragma unroll
+            for (int tt = 0; tt < F; ++tt) uin[a][tt] = (Rt)__longlong_as_double((long long)rb[a][tt]);
+      }
+#pragma unroll
+      for (int a = 0; a < DIM; ++a) {
+        if (d.sgn[a] == 0) continue;
+        Rt u[F];
+        if (cl[a] > 0) {
+#pragma unroll
+          for (int tt = 0; tt < F; ++tt) u[tt] = otr[a][t - tstride[a]][tt];
+        } else {
+#pragma unroll
+          for (int tt = 0; tt < F; ++tt) u[tt] = uin[a][tt];
+        }
+#pragma unroll
+        for (int i = 0; i < N; ++i) {
+          Rt acc = y[i];
+#pragma unroll
+          for (int tt = 0; tt < F; ++tt) acc = fma((Rt)row[L.g(a) + i * F + tt], u[tt], acc);
+          y[i] = acc;
+        }
+      }
+#pragma unroll
+      for (int q = 0; q < N; ++q) st_state(f + fm.f_base + d.plane_off[q] + cell, (St)y[q]);
+      // outflow traces: theta x + (1 - theta) f^n on each downwind face
+#pragma unroll
+      for (int b = 0; b < DIM; ++b) {
+        if (d.sgn[b] == 0) continue;
+        int fc = 0, fs = 1;
+#pragma unroll
+        for (int a2 = 0; a2 < DIM; ++a2)
+          if (a2 != b && d.sgn[a2] != 0) {
+            fc += cl[a2] * fs;
+            fs *= d.T[a2];
+          }
+        const bool to_next = cl[b] == d.T[b] - 1 && tl.down[b] >= 0;
+        uint64_t *dst = nullptr;
+        if (to_next) {
+          const DenseTile &dn = tiles[tl.down[b]];
+          dst = traces + dn.trace_off + (int64_t)b * dn.slot + fc * F;
+        }
+#pragma unroll
+        for (int tt = 0; tt < F; ++tt) {
+          const int q = face_node<NP, DIM>(b, tt, NP - 1);
+          const Rt o = th * y[q] + omt * fv[q];
+          otr[b][t][tt] = o;
+          if (to_next) {
+            if (LEVEL)
+              dst[tt] = (uint64_t)__double_as_longlong((double)o);
+            else
+              dense_put_trace(dst + tt, (double)o);
+          }
+        }
+      }
+    }
+    // The next diagonal reads this one's outflow traces from LDS.  The
+    // workgroup is a single wave, whose LDS accesses execute in order, so
+    // only the compiler has to be kept from moving them across the step;
+    // global stores stay in flight (a workgroup barrier would wait for them).
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+  }
+}
+
+}  // namespace
+
+hipError_t launch_dense_invert(double *table, const int64_t *row_off, const DenseDesc *descs,
+                               const int32_t *row_desc, const double *c0, int32_t *flags, int n_rows, int n,
+                               int F, hipStream_t st) {
+  if (n_rows <= 0) return hipSuccess;
+  if (n > kDenseMaxN || F > kDenseMaxF) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(dense_invert_kernel, dim3(n_rows), dim3(kDenseThreads), 0, st, table, row_off, descs, row_desc,
+                     c0, flags, n, F);
+  return hipGetLastError();
+}
+
+template <int PREC, int NP, int DIM>
+hipError_t go_dense(bool level, const DenseTile *tiles, const int32_t *order, int n_tiles, const DenseFam *fams,
+                    const DenseDesc *descs, const double *table, int dt_idx, void *f, const double *fb_old,
+                    const double *fb_new, uint64_t *traces, int32_t *counter, int32_t *err, hipStream_t st) {
+  using St = typename Pol<PREC>::St;
+  if (level)
+    hipLaunchKernelGGL((dense_sweep_kernel<PREC, NP, DIM, true>), dim3(n_tiles), dim3(kDenseThreads), 0, st, tiles,
+                       order, fams, descs, table, dt_idx, static_cast<St *>(f), fb_old, fb_new, traces, counter, err,
+                       n_tiles);
+  else
+    hipLaunchKernelGGL((dense_sweep_kernel<PREC, NP, DIM, false>), dim3(n_tiles), dim3(kDenseThreads), 0, st, tiles,
+                       order, fams, descs, table, dt_idx, static_cast<St *>(f), fb_old, fb_new, traces, counter, err,
+                       n_tiles);
+  return hipGetLastError();
+}
+
+template <int PREC>
+hipError_t go_dense_shape(bool level, int np, int dim, const DenseTile *tiles, const int32_t *order, int n_tiles,
+                          const DenseFam *fams, const DenseDesc *descs, const double *table, int dt_idx, void *f,
+                          const double *fb_old, const double *fb_new, uint64_t *traces, int32_t *counter,
+                          int32_t *err, hipStream_t st) {
+#define PDG_DENSE_CASE(NPV, DIMV)                                                                             \
+  if (np == NPV && dim == DIMV)                                                                               \
+    return go_dense<PREC, NPV, DIMV>(level, tiles, order, n_tiles, fams, descs, table, dt_idx, f, fb_old, fb_new,   \
+                                     traces, counter, err, st);
+  PDG_DENSE_CASE(2, 2)
+  PDG_DENSE_CASE(3, 2)
+  PDG_DENSE_CASE(4, 2)
+  PDG_DENSE_CASE(5, 2)
+  PDG_DENSE_CASE(2, 3)
+  PDG_DENSE_CASE(3, 3)
+#undef PDG_DENSE_CASE
+  return hipErrorInvalidValue;
+}
+
+hipError_t launch_dense_sweep(int prec, bool level, int np, int dim, const DenseTile *tiles, const int32_t *order,
+                              int n_tiles, const DenseFam *fams, const DenseDesc *descs, const double *table,
+                              int dt_idx, void *f, const double *fb_old, const double *fb_new, uint64_t *traces,
+                              int32_t *counter, int32_t *err_flag, hipStream_t st) {
+  if (n_tiles <= 0) return hipSuccess;
+  switch (prec) {
+    case kF64: return go_dense_shape<kF64>(level, np, dim, tiles, order, n_tiles, fams, descs, table, dt_idx, f, fb_old, fb_new, traces, counter, err_flag, st);
+    case kF32: return go_dense_shape<kF32>(level, np, dim, tiles, order, n_tiles, fams, descs, table, dt_idx, f, fb_old, fb_new, traces, counter, err_flag, st);
+    case kRefine: return go_dense_shape<kRefine>(level, np, dim, tiles, order, n_tiles, fams, descs, table, dt_idx, f, fb_old, fb_new, traces, counter, err_flag, st);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+}  // namespace pdg

@@ -1,5 +1,7 @@
 // Internal data structures shared by the host runtime (pdg_host.cpp) and the
-// gfx950 kernels (pdg_kernels.hip).  Not part of the public ABI.
+// gfx950 kernels (pdg_sweep.hip: axis-aligned transport; pdg_local.hip:
+// node-local steps; pdg_dense.hip: dense transport).  Not part of the public
+// ABI.
 #pragma once
 
 #include <stdint.h>
@@ -143,7 +145,7 @@ struct DenseTile {
   int32_t pad;
 };
 
-// ---- kernel launchers (pdg_kernels.hip) ----------------------------------
+// ---- kernel launchers ------------------------------------------------------
 enum Prec { kF64 = 0, kF32 = 1, kRefine = 2 };
 
 hipError_t launch_invert(OpEntry *ops, int n_ops, hipStream_t st);

@@ -230,7 +230,7 @@ def make(name, seed=0, scale=None):
     raise KeyError(name)
 
 
-WORKLOADS = ("adv2d_16", "adv3d_64", "euler2d_256", "euler3d_128", "batch96")
+WORKLOADS = ("adv2d_16", "adv3d_64", "euler2d_256", "euler3d_128", "batch96", "gravity2d_256")
 
 
 # ---------------------------------------------------------------------------
