@@ -120,6 +120,57 @@ __device__ constexpr int face_node(int a, int t, int qa) {
   return q;
 }
 
+// y = A^{-1} B f of one cell in the precision of the policy.  Binary32 +
+// refinement: binary32 solve, binary64 residual B f - A y, one binary32
+// correction.
+template <int PREC, int N, int F>
+__device__ __forceinline__ void dense_local_solve(const double *row, const typename Pol<PREC>::Rt (&fv)[N],
+                                                  typename Pol<PREC>::Rt (&y)[N]) {
+  using Rt = typename Pol<PREC>::Rt;
+  const DenseRowLayout L{N, F};
+  if (PREC == kRefine) {
+    double r[N];
+    float r32[N], y1[N];
+#pragma unroll
+    for (int i = 0; i < N; ++i) {
+      double acc = 0.0;
+#pragma unroll
+      for (int j = 0; j < N; ++j) acc = fma(row[L.b_off() + i * N + j], (double)fv[j], acc);
+      r[i] = acc;
+      r32[i] = (float)acc;
+    }
+#pragma unroll
+    for (int i = 0; i < N; ++i) {
+      float acc = 0.f;
+#pragma unroll
+      for (int j = 0; j < N; ++j) acc = fmaf((float)row[L.ai_off() + i * N + j], r32[j], acc);
+      y1[i] = acc;
+    }
+#pragma unroll
+    for (int i = 0; i < N; ++i) {
+      double acc = r[i];
+#pragma unroll
+      for (int j = 0; j < N; ++j) acc = fma(-row[L.a_off() + i * N + j], (double)y1[j], acc);
+      r32[i] = (float)acc;
+    }
+#pragma unroll
+    for (int i = 0; i < N; ++i) {
+      float acc = 0.f;
+#pragma unroll
+      for (int j = 0; j < N; ++j) acc = fmaf((float)row[L.ai_off() + i * N + j], r32[j], acc);
+      y[i] = (Rt)((double)y1[i] + (double)acc);
+    }
+  } else {
+#pragma unroll
+    for (int i = 0; i < N; ++i) {
+      Rt acc = 0;
+#pragma unroll
+      for (int j = 0; j < N; ++j) acc = fma((Rt)row[i * N + j], fv[j], acc);
+      y[i] = acc;
+    }
+  }
+}
+
 // Cross-tile hand-off.  A tile's inflow traces are written by its upwind
 // tiles, which may run on another XCD (each XCD has its own L2).  Every trace
 // value is written once per sweep, into a slot that was filled with a
@@ -265,47 +316,7 @@ __global__ __launch_bounds__(kDenseThreads) void dense_sweep_kernel(
   Rt fv[N], y[N];
 #pragma unroll
   for (int q = 0; q < N; ++q) fv[q] = active ? (Rt)ld_state(f + fm.f_base + d.plane_off[q] + cell) : (Rt)0;
-  if (PREC == kRefine) {
-    double r[N];
-    float r32[N], y1[N];
-#pragma unroll
-    for (int i = 0; i < N; ++i) {
-      double acc = 0.0;
-#pragma unroll
-      for (int j = 0; j < N; ++j) acc = fma(row[L.b_off() + i * N + j], (double)fv[j], acc);
-      r[i] = acc;
-      r32[i] = (float)acc;
-    }
-#pragma unroll
-    for (int i = 0; i < N; ++i) {
-      float acc = 0.f;
-#pragma unroll
-      for (int j = 0; j < N; ++j) acc = fmaf((float)row[L.ai_off() + i * N + j], r32[j], acc);
-      y1[i] = acc;
-    }
-#pragma unroll
-    for (int i = 0; i < N; ++i) {
-      double acc = r[i];
-#pragma unroll
-      for (int j = 0; j < N; ++j) acc = fma(-row[L.a_off() + i * N + j], (double)y1[j], acc);
-      r32[i] = (float)acc;
-    }
-#pragma unroll
-    for (int i = 0; i < N; ++i) {
-      float acc = 0.f;
-#pragma unroll
-      for (int j = 0; j < N; ++j) acc = fmaf((float)row[L.ai_off() + i * N + j], r32[j], acc);
-      y[i] = (Rt)((double)y1[i] + (double)acc);
-    }
-  } else {
-#pragma unroll
-    for (int i = 0; i < N; ++i) {
-      Rt acc = 0;
-#pragma unroll
-      for (int j = 0; j < N; ++j) acc = fma((Rt)row[i * N + j], fv[j], acc);
-      y[i] = acc;
-    }
-  }
+  dense_local_solve<PREC, N, F>(row, fv, y);
   const Rt th = (Rt)d.theta;
   const Rt omt = (Rt)1 - th;
 

@@ -902,6 +902,7 @@ pdg_status pdg_prepare(pdg_ctx *c, double dt, double theta, double omega, pdg_sc
 
   // ---- dense path tables -----------------------------------------------------
   std::vector<DenseDesc> ddesc;
+  std::vector<std::pair<int, int>> ddshape;  // (np, dim) per descriptor
   std::vector<DenseFam> dfam;
   std::vector<DenseTile> dtile;
   std::vector<double> dtable;
@@ -991,6 +992,7 @@ pdg_status pdg_prepare(pdg_ctx *c, double dt, double theta, double omega, pdg_sc
         for (int a = 0; a < 3; ++a) drow_c0.push_back(ds * kappa[a]);
       }
       ddesc.push_back(dd);
+      ddshape.push_back({np, dim});
       // families (component x transverse slice) and their tiles
       const int nslice = dd.trans_axis >= 0 ? (int)in.n[dd.trans_axis] : 1;
       int ntile[3];
@@ -1207,17 +1209,7 @@ pdg_status pdg_prepare(pdg_ctx *c, double dt, double theta, double omega, pdg_sc
   if (!drow_off.empty()) {
     std::map<std::pair<int, int>, std::vector<size_t>> rows_by_shape;
     for (size_t r = 0; r < drow_off.size(); ++r) {
-      const DenseDesc &dd = ddesc[drow_desc[r]];
-      int np2 = 0, dim2 = 0;
-      // recover (d+1, D) from the descriptor's instance
-      for (size_t f2 = 0; f2 < dfam.size(); ++f2)
-        if (dfam[f2].desc == drow_desc[r]) {
-          np2 = dshape[f2].first;
-          dim2 = dshape[f2].second;
-          break;
-        }
-      (void)dd;
-      rows_by_shape[{np2, dim2}].push_back(r);
+      rows_by_shape[ddshape[drow_desc[r]]].push_back(r);
     }
     for (auto &kv : rows_by_shape) {
       const int np2 = kv.first.first, dim2 = kv.first.second;
