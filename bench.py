@@ -108,6 +108,55 @@ def traffic_for(workload, prec_name):
     return ent.get("bytes_per_launch")
 
 
+def record_traffic(workload, prec_name, fetch_csv, write_csv):
+    """Turn two rocprofv3 --pmc runs of this script (FETCH_SIZE, then
+    WRITE_SIZE, each with --copy-probe-mib 1024 and fixed --tiles) into HBM
+    bytes per sweep launch, and store them in profiles/sweep_traffic.json
+    keyed by the sweep kernel's source hash.  Both counters are calibrated on
+    the 1 GiB device copy of the same run (it reads and writes 1 GiB)."""
+    import csv
+
+    def rows(path):
+        with open(path) as fh:
+            return list(csv.DictReader(fh))
+
+    f, w = rows(fetch_csv), rows(write_csv)
+    copy_bytes = 1024 * 2 ** 20
+
+    def values(rs, name, floor=0.0):
+        return [float(r["Counter_Value"]) for r in rs if name in r["Kernel_Name"] and float(r["Counter_Value"]) > floor]
+
+    cf, cw = values(f, "copyBuffer", 1e5), values(w, "copyBuffer", 1e5)
+    fetch_factor = copy_bytes / (sum(cf) / len(cf) * 1024)
+    write_factor = copy_bytes / (sum(cw) / len(cw) * 1024)
+    wl = W.make(workload)
+    state_b = 4 if prec_name == "fp32" else 8
+    alg_write_kib = wl.n_dof * state_b / 1024
+    sf, sw = values(f, "sweep_kernel"), values(w, "sweep_kernel")
+    # the full sweep launches (steps and timing loop) write the whole state;
+    # both runs issue the same dispatch sequence, so they are the same tail
+    ntail = 0
+    while ntail < len(sw) and abs(sw[-1 - ntail] - alg_write_kib) / alg_write_kib < 0.02:
+        ntail += 1
+    if ntail == 0:
+        raise SystemExit("no full sweep launch found in the counter runs")
+    full_f, full_w = sf[len(sf) - ntail:], sw[len(sw) - ntail:]
+    fetch_b = sum(full_f) / len(full_f) * 1024 * fetch_factor
+    write_b = sum(full_w) / len(full_w) * 1024 * write_factor
+    path = os.path.join(ROOT, "profiles", "sweep_traffic.json")
+    rec = {}
+    if os.path.exists(path):
+        with open(path) as fh:
+            rec = json.load(fh)
+    rec[f"{workload}/{prec_name}"] = {
+        "source_hash": kernel_source_hash(), "bytes_per_launch": fetch_b + write_b, "fetch_bytes": fetch_b,
+        "write_bytes": write_b, "fetch_factor": fetch_factor, "write_factor": write_factor,
+        "full_launches": ntail, "algorithmic_bytes_per_launch": 2 * wl.n_dof * state_b}
+    with open(path, "w") as fh:
+        json.dump(rec, fh, indent=1)
+    print(json.dumps(rec[f"{workload}/{prec_name}"], indent=1))
+
+
 def measure(pdg, torch, wl, prec, steps, warmup, reps, keep_state=False, autotune=True, tiles=None):
     insts = wl.instances
     prob = pdg.Problem([inst_dict(i) for i in insts])
@@ -226,7 +275,13 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="size of the plain device copy (bandwidth reference and counter calibration)")
+    ap.add_argument("--record-traffic", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"), default=None,
+                    help="store the HBM traffic of the sweep from two rocprofv3 --pmc runs (no GPU work)")
     args = ap.parse_args()
+
+    if args.record_traffic:
+        record_traffic(args.workload, args.precision, *args.record_traffic)
+        return
 
     if args.gpus != 1:
         print(f"bench.py measures one GPU: this build has no multi-GPU path (asked for --gpus {args.gpus}); "
