@@ -152,6 +152,22 @@ def gravity2d_instance(n, degree, lam=1.0, g=1.0, rho0=1.0, bump=0.0):
                     name=f"gravity2d_n{n}_d{degree}", vel=D2Q9)
 
 
+def graded_edges(n, lo, hi, stretch=1.5, jitter=0.0, seed=0):
+    """n + 1 increasing cell edges on [lo, hi]: exponentially stretched
+    (cells grow by about exp(stretch / n) from one to the next; 0 = uniform),
+    optionally with seeded random jitter of each interior edge by up to
+    jitter x the local cell size."""
+    s = np.arange(n + 1) / n
+    if stretch:
+        s = np.expm1(stretch * s) / np.expm1(stretch)
+    e = lo + (hi - lo) * s
+    if jitter and n > 1:
+        rng = np.random.default_rng(seed)
+        h = np.diff(e)
+        e[1:-1] += jitter * np.minimum(h[:-1], h[1:]) * rng.uniform(-1.0, 1.0, n - 1)
+    return e
+
+
 def uniform_state(values):
     values = np.asarray(values, dtype=float)
 
