@@ -42,7 +42,8 @@ def inst_dict(inst):
     par = {"advection": lambda p: list(p["a"]), "euler": lambda p: [p["gamma"]],
            "d2q9": lambda p: [p["g"]]}[inst.feq_kind](inst.feq_param)
     return dict(dim=inst.dim, n=list(inst.n), degree=inst.degree, v=np.asarray(inst.vel, float), m=inst.m,
-                lo=list(inst.lo), hi=list(inst.hi), feq=inst.feq_kind, feq_param=par)
+                lo=list(inst.lo), hi=list(inst.hi), feq=inst.feq_kind, feq_param=par,
+                edges=getattr(inst, "edges", None))
 
 
 def initial_state(pdg, prob, insts, torch, dtype):

@@ -123,6 +123,12 @@ typedef struct {
   const double *v;      /* host, nv * dim, row-major; copied */
   int32_t feq;          /* pdg_feq_kind */
   double feq_param[4];  /* see pdg_feq_kind */
+  const double *edges[3]; /* optional, host: cell edges along axis k (n[k] + 1 strictly increasing
+                             finite values; copied), a tensor-product graded mesh of box cells;
+                             NULL: uniform cells on [lo[k], hi[k]].  Given edges replace lo/hi.
+                             Velocities with two or three non-zero components along a graded
+                             axis are PDG_EUNSUPPORTED at prepare (their dense cell blocks would
+                             differ from cell to cell). */
 } pdg_instance_desc;
 
 /* Build a context for n_inst independent instances (Sec. 4.1): validate the
@@ -156,7 +162,8 @@ pdg_status pdg_topo_levels(int32_t n_nodes, int64_t n_edges, const int32_t *src,
 
 /* Host introspection of the cell operator used for (inst, vel): the
  * one-dimensional block Gamma (row-major (d+1) x (d+1), downwind-local node
- * order: node 0 on the inflow face) of eq. DG_reduit along the velocity axis,
+ * order: node 0 on the inflow face) of eq. DG_reduit along the velocity axis
+ * (on a graded axis: of the chain's upwind-most cell),
  * and the inflow coefficient kappa such that the upwind coupling
  * Gamma_{L<-R} is -kappa at the inflow node.  The full cell block is the
  * Kronecker product of this block with the identity on the transverse nodes.

@@ -36,7 +36,8 @@ class pdg_instance_desc(ctypes.Structure):
     _fields_ = [("dim", ctypes.c_int32), ("n", ctypes.c_int32 * 3), ("degree", ctypes.c_int32),
                 ("nv", ctypes.c_int32), ("m", ctypes.c_int32), ("lo", ctypes.c_double * 3),
                 ("hi", ctypes.c_double * 3), ("v", ctypes.POINTER(ctypes.c_double)),
-                ("feq", ctypes.c_int32), ("feq_param", ctypes.c_double * 4)]
+                ("feq", ctypes.c_int32), ("feq_param", ctypes.c_double * 4),
+                ("edges", ctypes.POINTER(ctypes.c_double) * 3)]
 
 
 def _load():
@@ -118,7 +119,8 @@ def _stream(stream):
 # ---------------------------------------------------------------------------
 def pdg_setup_mesh(instances):
     """instances: list of dicts with dim, n, degree, v (nv x dim), m, lo, hi,
-    feq ('advection'|'euler'|'d2q9'), feq_param.  Returns an opaque context handle."""
+    feq ('advection'|'euler'|'d2q9'), feq_param and optionally edges (per
+    axis None or n[k] + 1 cell edges).  Returns an opaque context handle."""
     import numpy as np
     arr = (pdg_instance_desc * len(instances))()
     keep = []
@@ -133,10 +135,18 @@ def pdg_setup_mesh(instances):
         feq = ins.get("feq", "advection")
         feq = {"advection": PDG_FEQ_ADVECTION, "euler": PDG_FEQ_EULER, "d2q9": PDG_FEQ_D2Q9}.get(feq, feq)
         nv = v.shape[0] if v.ndim == 2 else 0
+        # optional per-axis cell edges (graded mesh); None = uniform on [lo, hi]
+        edges = (list(ins.get("edges") or []) + [None] * 3)[:3]
+        eptr = (ctypes.POINTER(ctypes.c_double) * 3)()
+        for k, e in enumerate(edges):
+            if e is not None:
+                e = np.ascontiguousarray(np.asarray(e, dtype=np.float64))
+                keep.append(e)
+                eptr[k] = e.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
         arr[i] = pdg_instance_desc(dim, (ctypes.c_int32 * 3)(*n), int(ins["degree"]), nv, int(ins["m"]),
                                    (ctypes.c_double * 3)(*lo), (ctypes.c_double * 3)(*hi),
                                    v.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), int(feq),
-                                   (ctypes.c_double * 4)(*par))
+                                   (ctypes.c_double * 4)(*par), eptr)
     ctx = ctypes.c_void_p()
     _check(_lib.pdg_setup_mesh(arr, len(instances), ctypes.byref(ctx)), "pdg_setup_mesh")
     return ctx

@@ -45,6 +45,8 @@ struct Instance {
   std::vector<std::array<int, 2>> lat;
   double h[3];
   int64_t n[3];
+  bool graded[3] = {false, false, false};  // cell edges given along this axis
+  std::vector<double> edge[3];             // graded axes: n[k] + 1 cell edges
 };
 
 struct Group {
@@ -381,6 +383,11 @@ int pow2_ceil(int x) {
 // workgroup as that allows.  `PDG_TILE_X` / `PDG_TILE_Y` ("C,S") override it.
 void default_tile(LaunchClass &k) {
   const int smax = sweep_smax(k.np);
+  if (k.x_kind == 2) {  // graded chains: one thread per chain
+    k.C = kBlock;
+    k.S = 1;
+    return;
+  }
   if (k.x_kind) {
     int C = 64;
     while (C > 1 && ((int64_t)C * k.n_max > 4096 || k.chains / C < 2048)) C >>= 1;
@@ -410,7 +417,7 @@ void default_tile(LaunchClass &k) {
 // Segment length of a strided family under its class tile: the smallest
 // power of two covering the chain in one window, capped by the class.
 int family_S(const LaunchClass &k, int n_a) {
-  if (k.x_kind) return 1;
+  if (k.x_kind) return 1;  // x rows and graded chains
   const int P = kBlock / k.C;
   int S = 1;
   while (S < k.S && P * S < n_a) S <<= 1;
@@ -439,8 +446,9 @@ void build_items(pdg_ctx *c, std::vector<SweepItem> &items) {
         if (&c->classes[fm.cls] != &k) continue;
         const int C = k.C;
         const int S = family_S(k, fm.n_a);
-        const int cost = fm.x_kind ? (int)((C * (int64_t)fm.n_a + kBlock - 1) / kBlock)
-                                   : ((fm.n_a + (kBlock / C) * S - 1) / ((kBlock / C) * S)) * S;
+        const int cost = fm.x_kind == 2 ? fm.n_a
+                         : fm.x_kind ? (int)((C * (int64_t)fm.n_a + kBlock - 1) / kBlock)
+                                     : ((fm.n_a + (kBlock / C) * S - 1) / ((kBlock / C) * S)) * S;
         for (int kk = 0; kk < fm.m; ++kk)
           for (int64_t t = 0; t < fm.tnodes; ++t) {
             const int64_t base = fm.f_vel + kk * fm.comp_stride + fm.plane_off[t];
@@ -452,7 +460,7 @@ void build_items(pdg_ctx *c, std::vector<SweepItem> &items) {
               item.desc = fm.desc;
               item.tau0 = (int32_t)tau0;
               item.count = (int32_t)std::min<int64_t>(C, fm.ntc - tau0);
-              item.C = (int16_t)(fm.x_kind ? 0 : C);
+              item.C = (int16_t)(fm.x_kind == 1 ? 0 : C);
               item.S = (int8_t)S;
               item.xk = (int8_t)fm.x_kind;
               list.push_back({cost, item});
@@ -544,7 +552,15 @@ pdg_status pdg_setup_mesh(const pdg_instance_desc *descs, int32_t n_inst, pdg_ct
     if (err == PDG_OK && d.degree > 4) err = PDG_EUNSUPPORTED;
     if (err == PDG_OK) {
       for (int k = 0; k < d.dim; ++k) {
-        if (d.n[k] < 1 || !is_finite(d.lo[k]) || !is_finite(d.hi[k]) || !(d.hi[k] > d.lo[k])) err = PDG_EINVAL;
+        if (d.n[k] < 1) {
+          err = PDG_EINVAL;
+        } else if (d.edges[k]) {
+          // graded axis: n[k] + 1 strictly increasing finite edges
+          for (int i = 0; i <= d.n[k] && err == PDG_OK; ++i)
+            if (!is_finite(d.edges[k][i]) || (i > 0 && !(d.edges[k][i] > d.edges[k][i - 1]))) err = PDG_EINVAL;
+        } else if (!is_finite(d.lo[k]) || !is_finite(d.hi[k]) || !(d.hi[k] > d.lo[k])) {
+          err = PDG_EINVAL;
+        }
       }
     }
     if (err != PDG_OK) {
@@ -552,6 +568,15 @@ pdg_status pdg_setup_mesh(const pdg_instance_desc *descs, int32_t n_inst, pdg_ct
       return err;
     }
     in.d.v = nullptr;
+    for (int k = 0; k < 3; ++k) {
+      in.d.edges[k] = nullptr;
+      if (k < d.dim && d.edges[k]) {
+        in.graded[k] = true;
+        in.edge[k].assign(d.edges[k], d.edges[k] + d.n[k] + 1);
+        in.d.lo[k] = in.edge[k].front();
+        in.d.hi[k] = in.edge[k].back();
+      }
+    }
     in.v.assign(d.v, d.v + (size_t)d.nv * d.dim);
     for (double x : in.v)
       if (!is_finite(x)) {
@@ -687,6 +712,10 @@ pdg_status pdg_node_coords(const pdg_ctx *c, int32_t inst, double *vol_xyz, doub
   std::vector<double> x, w;
   gauss_lobatto(in.d.degree, x, w);
   auto pos = [&](int k, int64_t cell, int node) {
+    if (in.graded[k]) {
+      const double a = in.edge[k][cell], b = in.edge[k][cell + 1];
+      return a + 0.5 * (x[node] + 1.0) * (b - a);
+    }
     return in.d.lo[k] + ((double)cell + 0.5 * (x[node] + 1.0)) * in.h[k];
   };
   if (vol_xyz) {
@@ -749,7 +778,13 @@ pdg_status pdg_line_operator(const pdg_ctx *c, int32_t inst, int32_t vel, double
   const int ax = in.axis[vel];
   if (ax < 0) return PDG_EUNSUPPORTED;
   std::vector<double> gam;
-  line_block(in.d.degree, std::fabs(in.v[(size_t)vel * in.d.dim + ax]), in.h[ax], gam, *kappa);
+  // graded axis: the block of the chain's first (upwind-most) cell
+  double h = in.h[ax];
+  if (in.graded[ax]) {
+    const int64_t first = in.sign[vel] > 0 ? 0 : in.n[ax] - 1;
+    h = in.edge[ax][first + 1] - in.edge[ax][first];
+  }
+  line_block(in.d.degree, std::fabs(in.v[(size_t)vel * in.d.dim + ax]), h, gam, *kappa);
   std::memcpy(gamma, gam.data(), gam.size() * sizeof(double));
   return PDG_OK;
 }
@@ -772,8 +807,12 @@ pdg_status pdg_prepare(pdg_ctx *c, double dt, double theta, double omega, pdg_sc
   if (scheme < PDG_LIE || scheme > PDG_KIN4) return PDG_EINVAL;
   if (prec < PDG_FP64 || prec > PDG_FP32_REFINE) return PDG_EINVAL;
   for (const Instance &in : c->inst)
-    for (int v = 0; v < in.d.nv; ++v)
+    for (int v = 0; v < in.d.nv; ++v) {
       if (in.ndep[v] >= 2 && in.nd > kDenseMaxN) return PDG_EUNSUPPORTED;
+      // dense blocks on graded axes would differ from cell to cell
+      for (int k = 0; k < in.d.dim; ++k)
+        if (in.ndep[v] >= 2 && in.sgn[v][k] != 0 && in.graded[k]) return PDG_EUNSUPPORTED;
+    }
   hipStream_t st = static_cast<hipStream_t>(stream);
   c->release_device();
 
@@ -805,24 +844,34 @@ pdg_status pdg_prepare(pdg_ctx *c, double dt, double theta, double omega, pdg_sc
       if (in.ndep[v] != 1) continue;  // zero velocity: identity; two or more components: dense path
       const int ax = in.axis[v];
       const double V = std::fabs(in.v[(size_t)v * dim + ax]);
-      std::vector<double> gam;
-      double inflow = 0.0;
-      line_block(in.d.degree, V, in.h[ax], gam, inflow);
-      const int op_index = (int)ops.size();  // + index into dts
-      for (double ds : dts) {
-        OpEntry e;
-        std::memset(&e, 0, sizeof(e));
-        e.np = np;
-        e.theta = theta;
-        e.c0 = ds * inflow;
-        for (int i = 0; i < np; ++i)
-          for (int j = 0; j < np; ++j) {
-            const double id = i == j ? 1.0 : 0.0;
-            e.A[i * np + j] = id + theta * ds * gam[i * np + j];
-            e.B[i * np + j] = id - (1.0 - theta) * ds * gam[i * np + j];
+      // one operator row per sub-step; on a graded axis one per sub-step
+      // and downwind position (rows [dt_idx][l], l = 0 upwind-most)
+      const bool graded = in.graded[ax];
+      const int64_t npos = graded ? in.n[ax] : 1;
+      const int op_index = (int)ops.size();  // + dt_idx (* n_a + l when graded)
+      for (double ds : dts)
+        for (int64_t l = 0; l < npos; ++l) {
+          double h = in.h[ax];
+          if (graded) {
+            const int64_t phys = in.sign[v] > 0 ? l : in.n[ax] - 1 - l;
+            h = in.edge[ax][phys + 1] - in.edge[ax][phys];
           }
-        ops.push_back(e);
-      }
+          std::vector<double> gam;
+          double inflow = 0.0;
+          line_block(in.d.degree, V, h, gam, inflow);
+          OpEntry e;
+          std::memset(&e, 0, sizeof(e));
+          e.np = np;
+          e.theta = theta;
+          e.c0 = ds * inflow;
+          for (int i = 0; i < np; ++i)
+            for (int j = 0; j < np; ++j) {
+              const double id = i == j ? 1.0 : 0.0;
+              e.A[i * np + j] = id + theta * ds * gam[i * np + j];
+              e.B[i * np + j] = id - (1.0 - theta) * ds * gam[i * np + j];
+            }
+          ops.push_back(e);
+        }
       // chain addressing
       const int64_t nc = in.nc;
       const int64_t cstride = ax == 0 ? 1 : (ax == 1 ? in.n[0] : in.n[0] * in.n[1]);
@@ -837,7 +886,7 @@ pdg_status pdg_prepare(pdg_ctx *c, double dt, double theta, double omega, pdg_sc
       sd.plane_step = in.sign[v] > 0 ? pstride : -pstride;
       sd.plane0 = in.sign[v] > 0 ? 0 : (int64_t)(np - 1) * pstride;
       sd.op = op_index;
-      sd.x_kind = ax == 0 ? 1 : 0;
+      sd.x_kind = graded ? 2 : (ax == 0 ? 1 : 0);
       if (ax == 0) {
         sd.nx = 1;
         sd.hi_stride = in.n[0];
@@ -1516,6 +1565,7 @@ pdg_status upload_items(pdg_ctx *c, const std::vector<SweepItem> &items) {
 
 bool tile_valid(const LaunchClass &k, int C, int S) {
   if (C < 1 || C > kBlock || S < 1 || S > sweep_smax(k.np)) return false;
+  if (k.x_kind == 2) return C == kBlock && S == 1;
   if (k.x_kind) return (int64_t)C * k.n_max < 65536 && S == 1;
   return kBlock % C == 0;
 }
@@ -1533,6 +1583,7 @@ pdg_status pdg_autotune(pdg_ctx *c, void *f, const double *fb, int32_t reps, voi
   pdg_status status = PDG_OK;
   for (size_t ki = 0; ki < c->classes.size() && status == PDG_OK; ++ki) {
     LaunchClass &k = c->classes[ki];
+    if (k.x_kind == 2) continue;  // graded chains: one thread per chain, nothing to tune
     std::vector<std::pair<int, int>> cands;
     if (k.x_kind) {
       for (int C = 1; C <= 64; C <<= 1) cands.push_back({C, 1});

@@ -26,7 +26,8 @@ struct SweepDesc {
   int32_t nx;          // transverse decode: tau -> (tau % nx) + (tau / nx) * hi_stride
   int64_t hi_stride;
   int32_t op;          // operator-table row of dt_sub = dt; op + 1 is dt/2
-  int32_t x_kind;      // 1: chains along the contiguous axis
+  int32_t x_kind;      // 1: chains along the contiguous axis; 2: graded axis (operator
+                       // rows op + dt_idx * n_a + l, one thread per chain)
 };
 
 // One workgroup's share of a sweep: `count` consecutive chains (tau0 ..) of

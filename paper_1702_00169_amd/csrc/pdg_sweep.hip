@@ -240,6 +240,44 @@ __device__ __forceinline__ void sweep_rows(const SweepItem &it, const SweepDesc 
   }
 }
 
+// Chains on a graded axis (cell sizes vary along the chain, so does the cell
+// operator): one thread per chain walks its cells in downwind order, each
+// with the operator row of its position; all threads of a workgroup are at
+// the same position, so the row is read once for all of them.  Every cell
+// solves x_l = M_l f_l + g_l u_l and hands u_{l+1} = theta x_l,out +
+// (1 - theta) f_l,out to the next.
+template <int PREC, int NP>
+__device__ __forceinline__ void sweep_graded(const SweepItem &it, const SweepDesc &d, const OpEntry *__restrict__ ops,
+                                             int dt_idx, typename Pol<PREC>::St *__restrict__ f,
+                                             const double *__restrict__ fb_old, const double *__restrict__ fb_new,
+                                             typename Pol<PREC>::Rt theta, double &cmax, double &ymax) {
+  using St = typename Pol<PREC>::St;
+  using Rt = typename Pol<PREC>::Rt;
+  const int c = threadIdx.x;
+  if (c >= it.count) return;
+  const Rt omt = (Rt)1 - theta;
+  Rt u = theta * (Rt)fb_new[it.fb + c] + omt * (Rt)fb_old[it.fb + c];
+  const int tau = it.tau0 + c;
+  const int64_t chain = it.base + (int64_t)(tau % d.nx) + (int64_t)(tau / d.nx) * d.hi_stride + d.cell0 + d.plane0;
+  const OpEntry *row = ops + d.op + (int64_t)dt_idx * d.n_a;
+  for (int l = 0; l < d.n_a; ++l) {
+    CellOp<PREC, NP> op;
+    op.load(row[l]);
+    Rt fv[NP], y[NP];
+#pragma unroll
+    for (int q = 0; q < NP; ++q) fv[q] = (Rt)ld_state(f + chain + (int64_t)l * d.cell_step + q * d.plane_step);
+    op.solve(fv, y, cmax, ymax);
+    Rt xo = 0;
+#pragma unroll
+    for (int q = 0; q < NP; ++q) {
+      const Rt xv = fma(op.g[q], u, y[q]);
+      if (q == NP - 1) xo = xv;
+      st_state(f + chain + (int64_t)l * d.cell_step + q * d.plane_step, (St)xv);
+    }
+    u = theta * xo + omt * fv[NP - 1];
+  }
+}
+
 template <int PREC, int NP, int SMAX>
 __global__ __launch_bounds__(kBlock) void sweep_kernel(const SweepItem *__restrict__ items,
                                                       const SweepDesc *__restrict__ descs,
@@ -262,10 +300,12 @@ __global__ __launch_bounds__(kBlock) void sweep_kernel(const SweepItem *__restri
   const int t = threadIdx.x;
   double cmax = 0.0, ymax = 0.0;
 
-  if (it.xk) {
+  if (it.xk == 1) {
     __shared__ Rt wtot[2][4];
     __shared__ int wopen[2][4];
     sweep_rows<PREC, NP>(it, d, op, f, fb_old, fb_new, wtot, wopen, cmax, ymax);
+  } else if (it.xk == 2) {
+    sweep_graded<PREC, NP>(it, d, ops, dt_idx, f, fb_old, fb_new, theta, cmax, ymax);
   } else {
   // chains along a strided axis: thread (c, p) owns segment p of chain c
   const int C = it.C;        // chains per workgroup

@@ -19,11 +19,17 @@ def inst_dict(inst):
     else:
         par = [inst.feq_param["gamma"]]
     return dict(dim=inst.dim, n=list(inst.n), degree=inst.degree, v=np.asarray(inst.vel, float), m=inst.m,
-                lo=list(inst.lo), hi=list(inst.hi), feq=inst.feq_kind, feq_param=par)
+                lo=list(inst.lo), hi=list(inst.hi), feq=inst.feq_kind, feq_param=par,
+                edges=getattr(inst, "edges", None))
 
 
 def oracle_problem(inst):
-    return ost.Problem(inst.n, inst.lo, inst.hi, inst.degree, inst.vel, inst.m, inst.feq_kind, inst.feq_param)
+    edges = getattr(inst, "edges", None)
+    if edges is not None:
+        edges = [np.asarray(e, float) if e is not None else np.linspace(inst.lo[k], inst.hi[k], inst.n[k] + 1)
+                 for k, e in enumerate(edges)]
+    return ost.Problem(inst.n, inst.lo, inst.hi, inst.degree, inst.vel, inst.m, inst.feq_kind, inst.feq_param,
+                       edges)
 
 
 def sizes(inst):

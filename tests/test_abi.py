@@ -314,3 +314,85 @@ def test_source_before_prepare_is_a_state_error(lib):
     assert lib._lib.pdg_source(None, ctypes.c_void_p(8), 0.1, None) == lib.PDG_EINVAL
     assert lib._lib.pdg_source(prob.ctx, None, 0.1, None) == lib.PDG_EINVAL
     prob.close()
+
+
+# ---- graded meshes (per-axis cell edges) ------------------------------------
+import workloads as W  # noqa: E402
+
+
+def _graded_edges(n, hi, graded_axes):
+    return [W.graded_edges(n[k], 0.0, hi[k], 1.4, 0.25, seed=k) if k in graded_axes else None
+            for k in range(len(n))]
+
+
+@pytest.mark.parametrize("dim,n,degree,graded_axes", [
+    (2, (5, 4), 2, (0,)), (2, (4, 6), 3, (0, 1)), (3, (3, 4, 2), 1, (1, 2)), (3, (2, 3, 4), 2, (0, 1, 2)),
+])
+def test_graded_coordinates_match_oracle(lib, dim, n, degree, graded_axes):
+    vel = np.vstack([np.eye(dim), -np.eye(dim)])
+    hi = [1.0, 2.0, 0.5][:dim]
+    edges = _graded_edges(n, hi, graded_axes)
+    prob = lib.Problem([_desc(dim=dim, n=list(n), degree=degree, v=vel, hi=hi, lo=[0.0] * dim, edges=edges)])
+    vol, inflow = prob.node_coords(0)
+    full = [e if e is not None else np.linspace(0.0, hi[k], n[k] + 1) for k, e in enumerate(edges)]
+    m = omesh.Mesh(n, None, None, degree, full)
+    np.testing.assert_allclose(np.transpose(vol, (2, 1, 0)), m.node_coords(), atol=1e-14)
+    off = 0
+    for v in range(vel.shape[0]):
+        ent = otr.inflow_entries(m, vel[v])
+        npts = ent["coords"].shape[0]
+        pts = inflow[off:off + dim * npts].reshape(dim, npts).T
+        a = pts[np.lexsort(np.round(pts, 12).T[::-1])]
+        b = ent["coords"][np.lexsort(np.round(ent["coords"], 12).T[::-1])]
+        np.testing.assert_allclose(a, b, atol=1e-14)
+        off += dim * npts
+    prob.close()
+
+
+@pytest.mark.parametrize("degree", [1, 3])
+@pytest.mark.parametrize("vel", [(1.3, 0.0), (-0.7, 0.0), (0.0, 2.0), (0.0, -1.1)])
+def test_graded_line_operator_is_the_oracle_block_of_the_first_cell(lib, degree, vel):
+    n, hi = (4, 3), [1.0, 1.7]
+    edges = _graded_edges(n, hi, (0, 1))
+    prob = lib.Problem([_desc(dim=2, n=list(n), degree=degree, v=[list(vel)], hi=hi, lo=[0.0, 0.0], edges=edges)])
+    npn = degree + 1
+    gam = np.zeros(npn * npn)
+    kappa = lib.pdg_line_operator(prob.ctx, 0, 0, gam)
+    gam = gam.reshape(npn, npn)
+    m = omesh.Mesh(n, None, None, degree, edges)
+    ax = int(np.nonzero(vel)[0][0])
+    s = 1 if vel[ax] > 0 else -1
+    multi = [1, 1]
+    multi[ax] = 0 if s > 0 else n[ax] - 1                  # the chain's upwind-most cell
+    cell = multi[0] + n[0] * multi[1]
+    blk = otr.cell_blocks(m, np.array(vel), np.array([cell]))
+    idx = m.node_idx
+    want = blk.gll[0]
+    got = np.zeros_like(want)
+    for i in range(m.nd):
+        for j in range(m.nd):
+            if all(idx[i, k] == idx[j, k] for k in range(2) if k != ax):
+                qi = idx[i, ax] if s > 0 else degree - idx[i, ax]
+                qj = idx[j, ax] if s > 0 else degree - idx[j, ax]
+                got[i, j] = gam[qi, qj]
+    np.testing.assert_allclose(got, want, rtol=1e-13, atol=1e-13 * np.abs(want).max())
+    fc = [f for f in blk.faces if f["axis"] == ax and f["side"] == -s][0]
+    np.testing.assert_allclose(fc["coef"][0], -kappa, rtol=1e-13)
+    prob.close()
+
+
+@pytest.mark.parametrize("edges", [
+    [np.array([0.0, 0.5, 0.4, 1.0, 1.2, 1.5]), None], [np.array([0.0, 0.1, 0.2, 0.3, np.nan, 1.0]), None],
+    [np.array([0.0, 0.1, 0.2, 0.3, 0.4, 0.4]), None],
+])
+def test_graded_edges_are_validated(lib, edges):
+    with pytest.raises(lib.PdgError) as e:
+        lib.Problem([_desc(n=[5, 3], edges=edges)])
+    assert e.value.status == lib.PDG_EINVAL
+
+
+def test_dense_velocity_on_a_graded_axis_is_unsupported(lib):
+    edges = [W.graded_edges(5, 0.0, 1.0, 1.0), None]
+    prob = lib.Problem([_desc(n=[5, 3], v=[[1.0, 1.0], [1.0, 0.0]], edges=edges)])
+    assert lib._lib.pdg_prepare(prob.ctx, 0.01, 0.5, 2.0, 2, 0, None) == lib.PDG_EUNSUPPORTED
+    prob.close()

@@ -45,6 +45,7 @@ class Instance:
         self.w0 = w0                    # callable (N, dim) -> (m, N)
         self.lo = np.zeros(dim)
         self.hi = np.ones(dim)
+        self.edges = None               # optional per-axis cell edges (graded mesh)
         self.name = name
 
     @property
