@@ -230,7 +230,12 @@ def cpu_baseline(wl_name, seed, target_s):
     def one_step(scale):
         wl = W.make(wl_name, seed=seed, scale=scale)
         inst = wl.instances[0]
-        prob = ost.Problem(inst.n, inst.lo, inst.hi, inst.degree, inst.vel, inst.m, inst.feq_kind, inst.feq_param)
+        edges = None
+        if getattr(inst, "edges", None) is not None:
+            edges = [np.asarray(e, float) if e is not None else np.linspace(inst.lo[k], inst.hi[k], inst.n[k] + 1)
+                     for k, e in enumerate(inst.edges)]
+        prob = ost.Problem(inst.n, inst.lo, inst.hi, inst.degree, inst.vel, inst.m, inst.feq_kind, inst.feq_param,
+                           edges)
         x = prob.mesh.node_coords().reshape(-1, inst.dim)
         f0 = prob.feq(inst.w0(x).reshape(-1, prob.mesh.nc, prob.mesh.nd))
         fb = prob.inflow_from_w(inst.w0)

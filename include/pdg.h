@@ -251,7 +251,8 @@ pdg_status pdg_autotune(pdg_ctx *c, void *f_scratch, const double *fb, int32_t r
 
 /* Current tiles: *n_classes receives the number of launch classes; if
  * `tiles` is not NULL, up to the incoming *n_classes entries of 4 int32 each
- * are written: (d+1, chain kind (1 = x), C, S).  Host only. */
+ * are written: (d+1, chain kind (1 = x, 0 = strided axis, 2 = graded axis), C, S).
+ * Host only. */
 pdg_status pdg_get_tiles(const pdg_ctx *c, int32_t *n_classes, int32_t *tiles);
 
 /* Apply tiles (same 4-int format, e.g. a cached autotuner result); classes

@@ -52,6 +52,7 @@ struct Instance {
 struct Group {
   int np;                // node count of every item in the launch
   int64_t first, count;  // range in the item array
+  bool graded;           // chains on graded axes (their own kernel)
 };
 
 struct RelaxGroup {
@@ -382,13 +383,8 @@ int pow2_ceil(int x) {
 // workgroups to fill the 256 CUs several times over, as much work per
 // workgroup as that allows.  `PDG_TILE_X` / `PDG_TILE_Y` ("C,S") override it.
 void default_tile(LaunchClass &k) {
-  const int smax = sweep_smax(k.np);
-  if (k.x_kind == 2) {  // graded chains: one thread per chain
-    k.C = kBlock;
-    k.S = 1;
-    return;
-  }
-  if (k.x_kind) {
+  const int smax = class_smax(k.np, k.x_kind);
+  if (k.x_kind == 1) {
     int C = 64;
     while (C > 1 && ((int64_t)C * k.n_max > 4096 || k.chains / C < 2048)) C >>= 1;
     while (C > 1 && (int64_t)C * k.n_max >= 65536) C >>= 1;
@@ -400,11 +396,11 @@ void default_tile(LaunchClass &k) {
     k.C = C;
     k.S = smax;
   }
-  const char *env = std::getenv(k.x_kind ? "PDG_TILE_X" : "PDG_TILE_Y");
+  const char *env = std::getenv(k.x_kind == 1 ? "PDG_TILE_X" : "PDG_TILE_Y");
   if (!env) env = std::getenv("PDG_TILE");
   int c2 = 0, s2 = 0;
   if (env && std::sscanf(env, "%d,%d", &c2, &s2) == 2 && c2 > 0 && c2 <= kBlock && s2 > 0 && s2 <= smax) {
-    if (k.x_kind) {
+    if (k.x_kind == 1) {
       k.C = c2;
       while (k.C > 1 && (int64_t)k.C * k.n_max >= 65536) k.C >>= 1;
     } else if (kBlock % c2 == 0) {
@@ -417,7 +413,7 @@ void default_tile(LaunchClass &k) {
 // Segment length of a strided family under its class tile: the smallest
 // power of two covering the chain in one window, capped by the class.
 int family_S(const LaunchClass &k, int n_a) {
-  if (k.x_kind) return 1;  // x rows and graded chains
+  if (k.x_kind == 1) return 1;
   const int P = kBlock / k.C;
   int S = 1;
   while (S < k.S && P * S < n_a) S <<= 1;
@@ -429,13 +425,14 @@ int family_S(const LaunchClass &k, int n_a) {
 void build_items(pdg_ctx *c, std::vector<SweepItem> &items) {
   items.clear();
   std::vector<Group> groups;
-  std::map<int, int> group_of;
+  std::map<std::pair<int, bool>, int> group_of;
   for (LaunchClass &k : c->classes) {
-    if (!group_of.count(k.np)) {
-      group_of[k.np] = (int)groups.size();
-      groups.push_back(Group{k.np, 0, 0});
+    const std::pair<int, bool> key{k.np, k.x_kind == 2};
+    if (!group_of.count(key)) {
+      group_of[key] = (int)groups.size();
+      groups.push_back(Group{k.np, 0, 0, key.second});
     }
-    k.group = group_of[k.np];
+    k.group = group_of[key];
   }
   for (size_t g = 0; g < groups.size(); ++g) {
     groups[g].first = (int64_t)items.size();
@@ -446,9 +443,8 @@ void build_items(pdg_ctx *c, std::vector<SweepItem> &items) {
         if (&c->classes[fm.cls] != &k) continue;
         const int C = k.C;
         const int S = family_S(k, fm.n_a);
-        const int cost = fm.x_kind == 2 ? fm.n_a
-                         : fm.x_kind ? (int)((C * (int64_t)fm.n_a + kBlock - 1) / kBlock)
-                                     : ((fm.n_a + (kBlock / C) * S - 1) / ((kBlock / C) * S)) * S;
+        const int cost = fm.x_kind == 1 ? (int)((C * (int64_t)fm.n_a + kBlock - 1) / kBlock)
+                                        : ((fm.n_a + (kBlock / C) * S - 1) / ((kBlock / C) * S)) * S;
         for (int kk = 0; kk < fm.m; ++kk)
           for (int64_t t = 0; t < fm.tnodes; ++t) {
             const int64_t base = fm.f_vel + kk * fm.comp_stride + fm.plane_off[t];
@@ -1322,7 +1318,7 @@ namespace {
 pdg_status do_sweep(pdg_ctx *c, void *f, const double *fb_old, const double *fb_new, int dt_idx,
                     hipStream_t st) {
   for (const Group &g : c->groups) {
-    hipError_t e = launch_sweep(c->prec, g.np, c->sitems.p + g.first, (int)g.count, c->sdesc.p, c->ops.p, dt_idx, f,
+    hipError_t e = launch_sweep(c->prec, g.np, g.graded, c->sitems.p + g.first, (int)g.count, c->sdesc.p, c->ops.p, dt_idx, f,
                                 fb_old, fb_new, c->stats.p + 2 * g.first, st);
     if (e != hipSuccess) {
       char what[96];
@@ -1564,9 +1560,8 @@ pdg_status upload_items(pdg_ctx *c, const std::vector<SweepItem> &items) {
 }
 
 bool tile_valid(const LaunchClass &k, int C, int S) {
-  if (C < 1 || C > kBlock || S < 1 || S > sweep_smax(k.np)) return false;
-  if (k.x_kind == 2) return C == kBlock && S == 1;
-  if (k.x_kind) return (int64_t)C * k.n_max < 65536 && S == 1;
+  if (C < 1 || C > kBlock || S < 1 || S > class_smax(k.np, k.x_kind)) return false;
+  if (k.x_kind == 1) return (int64_t)C * k.n_max < 65536 && S == 1;
   return kBlock % C == 0;
 }
 
@@ -1583,13 +1578,12 @@ pdg_status pdg_autotune(pdg_ctx *c, void *f, const double *fb, int32_t reps, voi
   pdg_status status = PDG_OK;
   for (size_t ki = 0; ki < c->classes.size() && status == PDG_OK; ++ki) {
     LaunchClass &k = c->classes[ki];
-    if (k.x_kind == 2) continue;  // graded chains: one thread per chain, nothing to tune
     std::vector<std::pair<int, int>> cands;
-    if (k.x_kind) {
+    if (k.x_kind == 1) {
       for (int C = 1; C <= 64; C <<= 1) cands.push_back({C, 1});
     } else {
       for (int C = 8; C <= 64; C <<= 1)
-        for (int S = 1; S <= sweep_smax(k.np); S <<= 1) cands.push_back({C, S});
+        for (int S = 1; S <= class_smax(k.np, k.x_kind); S <<= 1) cands.push_back({C, S});
     }
     int bestC = k.C, bestS = k.S;
     float best = 1e30f;
@@ -1604,7 +1598,7 @@ pdg_status pdg_autotune(pdg_ctx *c, void *f, const double *fb, int32_t reps, voi
       for (int r = 0; r <= reps && e == hipSuccess; ++r) {
         if (r == 1) e = hipEventRecord(e0, st);
         if (e == hipSuccess)
-          e = launch_sweep(c->prec, g.np, c->sitems.p + k.first, (int)k.count, c->sdesc.p, c->ops.p, 0, f, fb, fb,
+          e = launch_sweep(c->prec, g.np, g.graded, c->sitems.p + k.first, (int)k.count, c->sdesc.p, c->ops.p, 0, f, fb, fb,
                            c->stats.p + 2 * k.first, st);
       }
       if (e == hipSuccess) e = hipEventRecord(e1, st);

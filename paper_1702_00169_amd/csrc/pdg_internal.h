@@ -26,8 +26,8 @@ struct SweepDesc {
   int32_t nx;          // transverse decode: tau -> (tau % nx) + (tau / nx) * hi_stride
   int64_t hi_stride;
   int32_t op;          // operator-table row of dt_sub = dt; op + 1 is dt/2
-  int32_t x_kind;      // 1: chains along the contiguous axis; 2: graded axis (operator
-                       // rows op + dt_idx * n_a + l, one thread per chain)
+  int32_t x_kind;      // 1: chains along the contiguous axis; 2: chains on a graded axis
+                       // (operator rows op + dt_idx * n_a + l; launched on their own)
 };
 
 // One workgroup's share of a sweep: `count` consecutive chains (tau0 ..) of
@@ -45,6 +45,10 @@ struct SweepItem {
 
 // Largest segment length compiled for a node count (register budget).
 constexpr int sweep_smax(int np) { return np <= 3 ? 8 : 4; }
+// Same for chains on graded axes, which also hold each cell's g and a.
+constexpr int sweep_smax_graded(int np) { return np <= 3 ? 4 : 2; }
+// Largest segment length of a launch class (chain kind 2: graded axis).
+constexpr int class_smax(int np, int x_kind) { return x_kind == 2 ? sweep_smax_graded(np) : sweep_smax(np); }
 
 // Operator table row: one (instance, velocity, dt_sub).  Downwind-local node
 // order (q = 0 inflow node, q = NP-1 outflow node).  Filled partly on the host
@@ -153,7 +157,7 @@ hipError_t launch_invert(OpEntry *ops, int n_ops, hipStream_t st);
 
 // Launch one sweep over items that share the node count np (any chain kind,
 // tile shape or instance).
-hipError_t launch_sweep(int prec, int np, const SweepItem *items, int n_items,
+hipError_t launch_sweep(int prec, int np, bool graded, const SweepItem *items, int n_items,
                         const SweepDesc *descs, const OpEntry *ops, int dt_idx, void *f, const double *fb_old,
                         const double *fb_new, double *stats, hipStream_t st);
 

@@ -240,44 +240,6 @@ __device__ __forceinline__ void sweep_rows(const SweepItem &it, const SweepDesc 
   }
 }
 
-// Chains on a graded axis (cell sizes vary along the chain, so does the cell
-// operator): one thread per chain walks its cells in downwind order, each
-// with the operator row of its position; all threads of a workgroup are at
-// the same position, so the row is read once for all of them.  Every cell
-// solves x_l = M_l f_l + g_l u_l and hands u_{l+1} = theta x_l,out +
-// (1 - theta) f_l,out to the next.
-template <int PREC, int NP>
-__device__ __forceinline__ void sweep_graded(const SweepItem &it, const SweepDesc &d, const OpEntry *__restrict__ ops,
-                                             int dt_idx, typename Pol<PREC>::St *__restrict__ f,
-                                             const double *__restrict__ fb_old, const double *__restrict__ fb_new,
-                                             typename Pol<PREC>::Rt theta, double &cmax, double &ymax) {
-  using St = typename Pol<PREC>::St;
-  using Rt = typename Pol<PREC>::Rt;
-  const int c = threadIdx.x;
-  if (c >= it.count) return;
-  const Rt omt = (Rt)1 - theta;
-  Rt u = theta * (Rt)fb_new[it.fb + c] + omt * (Rt)fb_old[it.fb + c];
-  const int tau = it.tau0 + c;
-  const int64_t chain = it.base + (int64_t)(tau % d.nx) + (int64_t)(tau / d.nx) * d.hi_stride + d.cell0 + d.plane0;
-  const OpEntry *row = ops + d.op + (int64_t)dt_idx * d.n_a;
-  for (int l = 0; l < d.n_a; ++l) {
-    CellOp<PREC, NP> op;
-    op.load(row[l]);
-    Rt fv[NP], y[NP];
-#pragma unroll
-    for (int q = 0; q < NP; ++q) fv[q] = (Rt)ld_state(f + chain + (int64_t)l * d.cell_step + q * d.plane_step);
-    op.solve(fv, y, cmax, ymax);
-    Rt xo = 0;
-#pragma unroll
-    for (int q = 0; q < NP; ++q) {
-      const Rt xv = fma(op.g[q], u, y[q]);
-      if (q == NP - 1) xo = xv;
-      st_state(f + chain + (int64_t)l * d.cell_step + q * d.plane_step, (St)xv);
-    }
-    u = theta * xo + omt * fv[NP - 1];
-  }
-}
-
 template <int PREC, int NP, int SMAX>
 __global__ __launch_bounds__(kBlock) void sweep_kernel(const SweepItem *__restrict__ items,
                                                       const SweepDesc *__restrict__ descs,
@@ -300,12 +262,10 @@ __global__ __launch_bounds__(kBlock) void sweep_kernel(const SweepItem *__restri
   const int t = threadIdx.x;
   double cmax = 0.0, ymax = 0.0;
 
-  if (it.xk == 1) {
+  if (it.xk) {
     __shared__ Rt wtot[2][4];
     __shared__ int wopen[2][4];
     sweep_rows<PREC, NP>(it, d, op, f, fb_old, fb_new, wtot, wopen, cmax, ymax);
-  } else if (it.xk == 2) {
-    sweep_graded<PREC, NP>(it, d, ops, dt_idx, f, fb_old, fb_new, theta, cmax, ymax);
   } else {
   // chains along a strided axis: thread (c, p) owns segment p of chain c
   const int C = it.C;        // chains per workgroup
@@ -377,6 +337,119 @@ __global__ __launch_bounds__(kBlock) void sweep_kernel(const SweepItem *__restri
 
   if (PREC == kRefine) {
     // block maxima of |correction| and |solution|, one pair per workgroup
+    __syncthreads();
+    double *red = reinterpret_cast<double *>(&xa[0][0]);
+    red[t] = cmax;
+    red[kBlock + t] = ymax;
+    __syncthreads();
+    for (int off = kBlock / 2; off > 0; off >>= 1) {
+      if (t < off) {
+        red[t] = fmax(red[t], red[t + off]);
+        red[kBlock + t] = fmax(red[kBlock + t], red[kBlock + t + off]);
+      }
+      __syncthreads();
+    }
+    if (t == 0) {
+      stats[2 * (int64_t)blockIdx.x] = red[0];
+      stats[2 * (int64_t)blockIdx.x + 1] = red[kBlock];
+    }
+  }
+}
+
+// Chains on a graded axis: the cell size, and with it the cell operator,
+// changes along the chain (operator row op + dt_idx * n_a + l for downwind
+// position l).  Same thread mapping as the strided chains above -- thread
+// (c, p) owns segment p of chain c, the segment maps are composed through
+// LDS -- with each cell's own M, g and a: the segment map is
+// u_out = (prod a_l) u_in + beta with beta_{l+1} = a_l beta_l + theta (M_l
+// f_l)_out + (1 - theta) f_l,out.  Used for chains along any axis.
+template <int PREC, int NP, int SMAX>
+__global__ __launch_bounds__(kBlock) void sweep_graded_kernel(const SweepItem *__restrict__ items,
+                                                             const SweepDesc *__restrict__ descs,
+                                                             const OpEntry *__restrict__ ops, int dt_idx,
+                                                             typename Pol<PREC>::St *__restrict__ f,
+                                                             const double *__restrict__ fb_old,
+                                                             const double *__restrict__ fb_new,
+                                                             double *__restrict__ stats) {
+  using St = typename Pol<PREC>::St;
+  using Rt = typename Pol<PREC>::Rt;
+  __shared__ Rt xa[2][kBlock];
+  __shared__ Rt xb[2][kBlock];
+  const SweepItem it = items[blockIdx.x];
+  const SweepDesc d = descs[it.desc];
+  const OpEntry *row = ops + d.op + (int64_t)dt_idx * d.n_a;
+  const Rt theta = (Rt)row[0].theta;
+  const Rt omt = (Rt)1 - theta;
+  const int t = threadIdx.x;
+  double cmax = 0.0, ymax = 0.0;
+  const int C = it.C;
+  const int S = it.S;
+  const int P = kBlock / C;
+  const int c = t % C;
+  const int p = t / C;
+  const bool active = c < it.count;
+  const int n = d.n_a;
+  const int window = P * S;
+  Rt u = 0;
+  if (active) u = theta * (Rt)fb_new[it.fb + c] + omt * (Rt)fb_old[it.fb + c];
+  const int tau = it.tau0 + c;
+  const int64_t chain = it.base + (int64_t)(tau % d.nx) + (int64_t)(tau / d.nx) * d.hi_stride + d.cell0 + d.plane0;
+  int wpar = 0;
+  for (int w0 = 0; w0 < n; w0 += window, wpar ^= 1) {
+    const int lb = w0 + p * S;
+    const int cnt = active ? max(0, min(S, n - lb)) : 0;
+    Rt y[SMAX][NP], gs[SMAX][NP];
+    Rt fo[SMAX], as[SMAX];
+#pragma unroll
+    for (int s = 0; s < SMAX; ++s) {
+      Rt fv[NP];
+      if (s < cnt) {
+#pragma unroll
+        for (int q = 0; q < NP; ++q) fv[q] = (Rt)ld_state(f + chain + (int64_t)(lb + s) * d.cell_step + q * d.plane_step);
+      } else {
+#pragma unroll
+        for (int q = 0; q < NP; ++q) fv[q] = 0;
+      }
+      fo[s] = fv[NP - 1];
+      CellOp<PREC, NP> op;
+      op.load(row[s < cnt ? lb + s : 0]);
+      op.solve(fv, y[s], cmax, ymax);
+#pragma unroll
+      for (int q = 0; q < NP; ++q) gs[s][q] = op.g[q];
+      as[s] = op.a;
+    }
+    Rt alpha = 1, beta = 0;
+#pragma unroll
+    for (int s = 0; s < SMAX; ++s) {
+      if (s < cnt) {
+        beta = fma(as[s], beta, theta * y[s][NP - 1] + omt * fo[s]);
+        alpha *= as[s];
+      }
+    }
+    xa[wpar][t] = alpha;
+    xb[wpar][t] = beta;
+    __syncthreads();
+    Rt uin = u;
+    for (int q = 0; q < p; ++q) uin = fma(xa[wpar][c + C * q], uin, xb[wpar][c + C * q]);
+    Rt unext = uin;
+    for (int q = p; q < P; ++q) unext = fma(xa[wpar][c + C * q], unext, xb[wpar][c + C * q]);
+    Rt uu = uin;
+#pragma unroll
+    for (int s = 0; s < SMAX; ++s) {
+      if (s < cnt) {
+        Rt xo = 0;
+#pragma unroll
+        for (int q = 0; q < NP; ++q) {
+          const Rt xv = fma(gs[s][q], uu, y[s][q]);
+          if (q == NP - 1) xo = xv;
+          st_state(f + chain + (int64_t)(lb + s) * d.cell_step + q * d.plane_step, (St)xv);
+        }
+        uu = theta * xo + omt * fo[s];
+      }
+    }
+    u = unext;
+  }
+  if (PREC == kRefine) {
     __syncthreads();
     double *red = reinterpret_cast<double *>(&xa[0][0]);
     red[t] = cmax;
@@ -469,25 +542,30 @@ __global__ void invert_kernel(OpEntry *ops, int n_ops) {
 // dispatch
 // ---------------------------------------------------------------------------
 template <int PREC, int NP>
-hipError_t go_sweep(const SweepItem *items, int n_items, const SweepDesc *descs, const OpEntry *ops,
+hipError_t go_sweep(bool graded, const SweepItem *items, int n_items, const SweepDesc *descs, const OpEntry *ops,
                     int dt_idx, void *f, const double *fb_old, const double *fb_new, double *stats,
                     hipStream_t st) {
   using St = typename Pol<PREC>::St;
   constexpr int SMAX = sweep_smax(NP);
-  hipLaunchKernelGGL((sweep_kernel<PREC, NP, SMAX>), dim3(n_items), dim3(kBlock), 0, st, items, descs, ops,
-                     dt_idx, static_cast<St *>(f), fb_old, fb_new, stats);
+  constexpr int SMAXG = sweep_smax_graded(NP);
+  if (graded)
+    hipLaunchKernelGGL((sweep_graded_kernel<PREC, NP, SMAXG>), dim3(n_items), dim3(kBlock), 0, st, items, descs, ops,
+                       dt_idx, static_cast<St *>(f), fb_old, fb_new, stats);
+  else
+    hipLaunchKernelGGL((sweep_kernel<PREC, NP, SMAX>), dim3(n_items), dim3(kBlock), 0, st, items, descs, ops,
+                       dt_idx, static_cast<St *>(f), fb_old, fb_new, stats);
   return hipGetLastError();
 }
 
 template <int PREC>
-hipError_t go_sweep_np(int np, const SweepItem *items, int n_items, const SweepDesc *descs,
+hipError_t go_sweep_np(bool graded, int np, const SweepItem *items, int n_items, const SweepDesc *descs,
                        const OpEntry *ops, int dt_idx, void *f, const double *fb_old, const double *fb_new,
                        double *stats, hipStream_t st) {
   switch (np) {
-    case 2: return go_sweep<PREC, 2>(items, n_items, descs, ops, dt_idx, f, fb_old, fb_new, stats, st);
-    case 3: return go_sweep<PREC, 3>(items, n_items, descs, ops, dt_idx, f, fb_old, fb_new, stats, st);
-    case 4: return go_sweep<PREC, 4>(items, n_items, descs, ops, dt_idx, f, fb_old, fb_new, stats, st);
-    case 5: return go_sweep<PREC, 5>(items, n_items, descs, ops, dt_idx, f, fb_old, fb_new, stats, st);
+    case 2: return go_sweep<PREC, 2>(graded, items, n_items, descs, ops, dt_idx, f, fb_old, fb_new, stats, st);
+    case 3: return go_sweep<PREC, 3>(graded, items, n_items, descs, ops, dt_idx, f, fb_old, fb_new, stats, st);
+    case 4: return go_sweep<PREC, 4>(graded, items, n_items, descs, ops, dt_idx, f, fb_old, fb_new, stats, st);
+    case 5: return go_sweep<PREC, 5>(graded, items, n_items, descs, ops, dt_idx, f, fb_old, fb_new, stats, st);
     default: return hipErrorInvalidValue;
   }
 }
@@ -500,14 +578,14 @@ hipError_t launch_invert(OpEntry *ops, int n_ops, hipStream_t st) {
   return hipGetLastError();
 }
 
-hipError_t launch_sweep(int prec, int np, const SweepItem *items, int n_items,
+hipError_t launch_sweep(int prec, int np, bool graded, const SweepItem *items, int n_items,
                         const SweepDesc *descs, const OpEntry *ops, int dt_idx, void *f, const double *fb_old,
                         const double *fb_new, double *stats, hipStream_t st) {
   if (n_items <= 0) return hipSuccess;
   switch (prec) {
-    case kF64: return go_sweep_np<kF64>(np, items, n_items, descs, ops, dt_idx, f, fb_old, fb_new, stats, st);
-    case kF32: return go_sweep_np<kF32>(np, items, n_items, descs, ops, dt_idx, f, fb_old, fb_new, stats, st);
-    case kRefine: return go_sweep_np<kRefine>(np, items, n_items, descs, ops, dt_idx, f, fb_old, fb_new, stats, st);
+    case kF64: return go_sweep_np<kF64>(graded, np, items, n_items, descs, ops, dt_idx, f, fb_old, fb_new, stats, st);
+    case kF32: return go_sweep_np<kF32>(graded, np, items, n_items, descs, ops, dt_idx, f, fb_old, fb_new, stats, st);
+    case kRefine: return go_sweep_np<kRefine>(graded, np, items, n_items, descs, ops, dt_idx, f, fb_old, fb_new, stats, st);
     default: return hipErrorInvalidValue;
   }
 }

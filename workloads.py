@@ -228,6 +228,16 @@ def make(name, seed=0, scale=None):
                         name=f"euler3d_n{n}_d2")
         return Workload(name, [inst], dt=(1.0 / n) / 3.0, steps=20,
                         description="3D Euler, D3Q6 lambda=3, m=5, 128^3 cells, degree 2, density/pressure bumps")
+    if name == "adv3d_64_graded":
+        # the adv3d_64 problem on a graded mesh: cells stretched along every
+        # axis (sizes from about 0.6 to 1.7 times the uniform size, jittered)
+        wl = make("adv3d_64", seed=seed, scale=scale)
+        inst = wl.instances[0]
+        inst.edges = [graded_edges(inst.n[k], 0.0, 1.0, 1.0, 0.2, seed=seed + k) for k in range(3)]
+        inst.name += "_graded"
+        return Workload(name, [inst], dt=wl.dt, steps=wl.steps,
+                        description="3D scalar advection, D3Q6 lambda=1, a=(0.3,0.2,0.1), 64^3 cells graded along "
+                                    "every axis (stretch 1.0, jitter 0.2), degree 2")
     if name == "gravity2d_256":
         n = scale or 256
         inst = gravity2d_instance(n, 3, lam=1.0, g=1.0, bump=0.05)
@@ -247,7 +257,7 @@ def make(name, seed=0, scale=None):
     raise KeyError(name)
 
 
-WORKLOADS = ("adv2d_16", "adv3d_64", "euler2d_256", "euler3d_128", "batch96", "gravity2d_256")
+WORKLOADS = ("adv2d_16", "adv3d_64", "euler2d_256", "euler3d_128", "batch96", "gravity2d_256", "adv3d_64_graded")
 
 
 # ---------------------------------------------------------------------------
