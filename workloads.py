@@ -230,7 +230,7 @@ def make(name, seed=0, scale=None):
                         description="3D Euler, D3Q6 lambda=3, m=5, 128^3 cells, degree 2, density/pressure bumps")
     if name == "adv3d_64_graded":
         # the adv3d_64 problem on a graded mesh: cells stretched along every
-        # axis (sizes from about 0.6 to 1.7 times the uniform size, jittered)
+        # axis (sizes from about 0.4 to 1.9 times the uniform size, jittered)
         wl = make("adv3d_64", seed=seed, scale=scale)
         inst = wl.instances[0]
         inst.edges = [graded_edges(inst.n[k], 0.0, 1.0, 1.0, 0.2, seed=seed + k) for k in range(3)]
