@@ -8,7 +8,8 @@ functions below at its own Gauss-Lobatto points and builds f^0 = f^eq(w_0)
 and f^b = f^eq(w_0) on the inflow boundary with its own code.
 
 The paper's meshes and physics runs are not available, so these workloads
-stand in for them: 2D and 3D uniform meshes, the {+-lambda e_k} velocity sets
+stand in for them: 2D and 3D uniform or graded (tensor-product) box meshes,
+the {+-lambda e_k} velocity sets
 (the first 2D / 6 points of the paper's D2Q9 / D3Q27 lists), scalar advection
 and compressible Euler equilibria, and smooth seeded data; and the D2Q9
 isothermal gravity test of Sec. 5.1 (the paper's velocity list and its
@@ -178,7 +179,7 @@ def uniform_state(values):
 
 
 # ---------------------------------------------------------------------------
-# the five workloads
+# the workloads
 # ---------------------------------------------------------------------------
 def adv2d_instance(rng, n, degree, a, lam=1.0):
     amp = 1.0 + 0.1 * rng.uniform(-1.0, 1.0)
