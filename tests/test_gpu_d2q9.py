@@ -216,3 +216,27 @@ def test_hydrostatic_run_matches_oracle_and_converges_at_second_order(lib):
     rate = np.log2(errs[0] / errs[1])
     print(f"  errors vs the steady state {errs}, rate {rate:.2f}")
     assert 1.8 <= rate <= 2.3
+
+
+@pytest.mark.parametrize("schedule", ["level", "claim"])
+def test_gravity_graph_replay_equals_eager(lib, monkeypatch, schedule):
+    """The captured step (dense tiles with their fill kernels, chains, the
+    S C S node kernel) replays to the same bits as the eager launches."""
+    torch = pytest.importorskip("torch")
+    print(f"d2q9 graph replay schedule={schedule}", flush=True)
+    monkeypatch.setenv("PDG_DENSE_SCHEDULE", schedule)
+    inst = _inst(n=(20, 13), degree=2)
+    outs = []
+    for no_graph in (False, True):
+        if no_graph:
+            monkeypatch.setenv("PDG_NO_GRAPH", "1")
+        prob = lib.Problem([inst_dict(inst)])
+        prob.prepare(0.02, scheme=2)
+        f, fb = gpu_initial_state(prob, [inst], torch, torch.float64)
+        prob.step(f, fb, 2)
+        torch.cuda.synchronize()
+        prob.step(f, fb, 4)
+        prob.sync_status()
+        outs.append(f.clone())
+        prob.close()
+    assert torch.equal(outs[0], outs[1])

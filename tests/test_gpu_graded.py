@@ -149,3 +149,50 @@ def test_batch_mixing_graded_and_uniform_instances(lib):
         print(f"  instance {i}: rel L2 {l2:.3e}")
         assert l2 <= 1e-12 and mx <= 1e-11
     prob.close()
+
+
+def test_graded_autotune_and_tiles(lib):
+    """Graded chains are tuned like strided chains (class kind 2); any valid
+    tile solves the same system, up to the rounding of the segment combine."""
+    torch = pytest.importorskip("torch")
+    print("graded autotune", flush=True)
+    inst = _instance(CASES[4])
+    prob = lib.Problem([inst_dict(inst)])
+    prob.prepare(0.02)
+    scratch = torch.zeros(prob.layout["f_elems"], dtype=torch.float64, device="cuda")
+    fb = torch.ones(prob.layout["fb_elems"], dtype=torch.float64, device="cuda")
+    tiles = prob.autotune(scratch, fb, reps=1)
+    assert {(t["np"], t["x_kind"]) for t in tiles} == {(3, 2)}
+    results = []
+    f0 = torch.tensor(W.random_state(5, (prob.layout["f_elems"],)), device="cuda")
+    for C, S in [(64, 4), (16, 1), (8, 2)]:
+        prob.set_tiles([dict(np=3, x_kind=2, C=C, S=S)])
+        f = f0.clone()
+        prob.transport_sweep(f, fb, fb, 0.02)
+        prob.sync_status()
+        results.append(f.cpu().numpy())
+    with pytest.raises(lib.PdgError):
+        prob.set_tiles([dict(np=3, x_kind=2, C=64, S=8)])     # longer than a graded segment
+    for r in results[1:]:
+        assert rel_errors(r, results[0])[0] <= 1e-14
+    prob.close()
+
+
+def test_graded_graph_replay_equals_eager(lib, monkeypatch):
+    torch = pytest.importorskip("torch")
+    print("graded graph replay", flush=True)
+    inst, wl = _euler_graded(12, 2, (0, 1))
+    outs = []
+    for no_graph in (False, True):
+        if no_graph:
+            monkeypatch.setenv("PDG_NO_GRAPH", "1")
+        prob = lib.Problem([inst_dict(inst)])
+        prob.prepare(wl.dt)
+        f, fb = gpu_initial_state(prob, [inst], torch, torch.float64)
+        prob.step(f, fb, 2)
+        torch.cuda.synchronize()
+        prob.step(f, fb, 4)
+        torch.cuda.synchronize()
+        outs.append(f.clone())
+        prob.close()
+    assert torch.equal(outs[0], outs[1])
