@@ -120,6 +120,27 @@ __device__ constexpr int face_node(int a, int t, int qa) {
   return q;
 }
 
+// number of nodes on the downwind faces: NP^DIM - (NP-1)^DIM
+template <int NP, int DIM>
+__device__ constexpr int dense_out_nodes() {
+  int all = 1, inner = 1;
+  for (int b = 0; b < DIM; ++b) {
+    all *= NP;
+    inner *= NP - 1;
+  }
+  return all - inner;
+}
+
+// true when node q lies on a downwind face (some coordinate equals NP - 1)
+template <int NP, int DIM>
+__device__ constexpr bool on_out_face(int q) {
+  for (int b = 0; b < DIM; ++b) {
+    if (q % NP == NP - 1) return true;
+    q /= NP;
+  }
+  return false;
+}
+
 // y = A^{-1} B f of one cell in the precision of the policy.  Binary32 +
 // refinement: binary32 solve, binary64 residual B f - A y, one binary32
 // correction.
@@ -189,39 +210,43 @@ __device__ inline uint64_t dense_peek_trace(uint64_t *p) {
   return cur;
 }
 
-// The inflow traces a cell needs from upwind tiles (up to one face per axis).
+// The inflow traces a cell needs from upwind tiles (up to one face per axis,
+// at traces + src[a]; src[a] < 0 where the face is not fed by a tile).
 // Every slot is requested at once, so a ready face costs one round trip; the
 // slots still empty are polled again after a short sleep.  The producer was
 // claimed earlier and is resident, so the wait ends; the wall-clock bound
 // (1 s at the 100 MHz constant clock) and the shared error flag turn a logic
 // error into one reported failure instead of a hang.
 template <int DIM, int F>
-__device__ inline void dense_take_faces(uint64_t *const (&src)[DIM], uint64_t (&b)[DIM][F], int32_t *err_flag) {
+__device__ inline void dense_take_faces(uint64_t *traces, const int64_t (&src)[DIM], uint64_t (&b)[DIM][F],
+                                        int32_t *err_flag) {
   bool ready = true;
 #pragma unroll
   for (int a = 0; a < DIM; ++a)
-    if (src[a])
+    if (src[a] >= 0)
 #pragma unroll
-      for (int tt = 0; tt < F; ++tt) b[a][tt] = dense_peek_trace(src[a] + tt);
+      for (int tt = 0; tt < F; ++tt) b[a][tt] = dense_peek_trace(traces + src[a] + tt);
 #pragma unroll
   for (int a = 0; a < DIM; ++a)
-    if (src[a])
+    if (src[a] >= 0)
 #pragma unroll
       for (int tt = 0; tt < F; ++tt) ready = ready && b[a][tt] != kDenseTraceEmpty;
   if (ready) return;
   const uint64_t t_start = wall_clock64();
-  for (;;) {
-    __builtin_amdgcn_s_sleep(2);
+  for (int naps = 1;; naps = naps < 8 ? 2 * naps : 8) {
+    // back off (up to ~0.4 us between polls): the waiting waves would
+    // otherwise keep the atomic units busy for the waves that produce
+    for (int k = 0; k < naps; ++k) __builtin_amdgcn_s_sleep(2);
     ready = true;
 #pragma unroll
     for (int a = 0; a < DIM; ++a)
-      if (src[a])
+      if (src[a] >= 0)
 #pragma unroll
         for (int tt = 0; tt < F; ++tt)
-          if (b[a][tt] == kDenseTraceEmpty) b[a][tt] = dense_peek_trace(src[a] + tt);
+          if (b[a][tt] == kDenseTraceEmpty) b[a][tt] = dense_peek_trace(traces + src[a] + tt);
 #pragma unroll
     for (int a = 0; a < DIM; ++a)
-      if (src[a])
+      if (src[a] >= 0)
 #pragma unroll
         for (int tt = 0; tt < F; ++tt) ready = ready && b[a][tt] != kDenseTraceEmpty;
     if (ready) return;
@@ -269,6 +294,7 @@ __global__ __launch_bounds__(kDenseThreads) void dense_sweep_kernel(
   constexpr int N = DIM == 2 ? NP * NP : NP * NP * NP;
   constexpr int F = DIM == 2 ? NP : NP * NP;
   __shared__ Rt otr[3][kDenseThreads][F];  // outflow traces per axis of every cell of the tile
+  __shared__ Rt gl[DIM][N][F];             // G_a of the tile's operator row
   const int t = threadIdx.x;
   int claim = blockIdx.x;
   if (!LEVEL) {
@@ -312,11 +338,14 @@ __global__ __launch_bounds__(kDenseThreads) void dense_sweep_kernel(
   const double *row = table + d.op_off + (int64_t)dt_idx * d.op_stride;
   const DenseRowLayout L{N, F};
 
-  // load the cell and apply the local block
+  // Stage the coupling blocks G_a in LDS (vector loads, all lanes), load the
+  // cell and apply the local block.
+#pragma unroll
+  for (int a = 0; a < DIM; ++a)
+    for (int e = t; e < N * F; e += kDenseThreads) gl[a][e / F][e % F] = (Rt)row[L.g(a) + e];
   Rt fv[N], y[N];
 #pragma unroll
   for (int q = 0; q < N; ++q) fv[q] = active ? (Rt)ld_state(f + fm.f_base + d.plane_off[q] + cell) : (Rt)0;
-  dense_local_solve<PREC, N, F>(row, fv, y);
   const Rt th = (Rt)d.theta;
   const Rt omt = (Rt)1 - th;
 
@@ -332,10 +361,10 @@ __global__ __launch_bounds__(kDenseThreads) void dense_sweep_kernel(
   // upwind tile of an earlier launch.  Both are fetched before the diagonal
   // loop, so that the loop issues no global load it would have to wait for.
   Rt uin[DIM][F];
-  uint64_t *rsrc[DIM];
+  int64_t rsrc[DIM];  // offset of the upwind tile's trace slots, -1 if none
 #pragma unroll
   for (int a = 0; a < DIM; ++a) {
-    rsrc[a] = nullptr;
+    rsrc[a] = -1;
 #pragma unroll
     for (int tt = 0; tt < F; ++tt) uin[a][tt] = (Rt)0;
     if (!active || d.sgn[a] == 0 || cl[a] > 0) continue;
@@ -348,10 +377,10 @@ __global__ __launch_bounds__(kDenseThreads) void dense_sweep_kernel(
           fc += cl[b] * fs;
           fs *= d.T[b];
         }
-      rsrc[a] = traces + tl.trace_off + (int64_t)a * tl.slot + fc * F;
+      rsrc[a] = tl.trace_off + (int64_t)a * tl.slot + fc * F;
       if (LEVEL)
 #pragma unroll
-        for (int tt = 0; tt < F; ++tt) uin[a][tt] = (Rt)__longlong_as_double((long long)rsrc[a][tt]);
+        for (int tt = 0; tt < F; ++tt) uin[a][tt] = (Rt)__longlong_as_double((long long)traces[rsrc[a] + tt]);
     } else {
       // domain inflow face: transverse cell index over the other axes
       int64_t tau = 0, ts = 1;
@@ -370,65 +399,93 @@ __global__ __launch_bounds__(kDenseThreads) void dense_sweep_kernel(
     }
   }
 
+  // The local block, once the loads above are all in flight.
+  dense_local_solve<PREC, N, F>(row, fv, y);
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+
+  // Loop-invariant data of the diagonal loop, read once: the axis signs, the
+  // downwind trace slots and, when they fit in registers, the rows of G_a
+  // that the outflow nodes need.
+  bool on[DIM];
+  int64_t dst[DIM];  // offset of the downwind tile's trace slots, -1 if none
+#pragma unroll
+  for (int b = 0; b < DIM; ++b) {
+    on[b] = d.sgn[b] != 0;
+    dst[b] = -1;
+    if (!on[b] || !active || cl[b] != d.T[b] - 1 || tl.down[b] < 0) continue;
+    int fc = 0, fs = 1;
+#pragma unroll
+    for (int a2 = 0; a2 < DIM; ++a2)
+      if (a2 != b && d.sgn[a2] != 0) {
+        fc += cl[a2] * fs;
+        fs *= d.T[a2];
+      }
+    const DenseTile &dn = tiles[tl.down[b]];
+    dst[b] = dn.trace_off + (int64_t)b * dn.slot + fc * F;
+  }
+  int up_lds[DIM];
+#pragma unroll
+  for (int a = 0; a < DIM; ++a) up_lds[a] = t - tstride[a];
+  constexpr bool kRegG = dense_out_nodes<NP, DIM>() * DIM * F * (int)sizeof(Rt) <= 512;  // <= 128 VGPRs
+  Rt gr[DIM][N][F];
+  if constexpr (kRegG) {
+#pragma unroll
+    for (int a = 0; a < DIM; ++a)
+#pragma unroll
+      for (int q = 0; q < N; ++q)
+        if (on_out_face<NP, DIM>(q))
+#pragma unroll
+          for (int tt = 0; tt < F; ++tt) gr[a][q][tt] = gl[a][q][tt];
+  }
+
+  // Diagonal by diagonal, a cell needs only its outflow traces on the
+  // critical path: the nodes on its downwind faces.  The inflow traces it
+  // used are kept (uin) for the update of the other nodes after the loop.
   for (int s = 0; s < ndiag; ++s) {
     if (active && diag == s) {
       if (!LEVEL) {
         uint64_t rb[DIM][F];
-        dense_take_faces<DIM, F>(rsrc, rb, err_flag);
+        dense_take_faces<DIM, F>(traces, rsrc, rb, err_flag);
 #pragma unroll
         for (int a = 0; a < DIM; ++a)
-          if (rsrc[a])
+          if (rsrc[a] >= 0)
 #pragma unroll
             for (int tt = 0; tt < F; ++tt) uin[a][tt] = (Rt)__longlong_as_double((long long)rb[a][tt]);
       }
 #pragma unroll
+      for (int a = 0; a < DIM; ++a)
+        if (on[a] && cl[a] > 0)
+#pragma unroll
+          for (int tt = 0; tt < F; ++tt) uin[a][tt] = otr[a][up_lds[a]][tt];
+      Rt yo[N];
+#pragma unroll
+      for (int q = 0; q < N; ++q) yo[q] = y[q];
+#pragma unroll
       for (int a = 0; a < DIM; ++a) {
-        if (d.sgn[a] == 0) continue;
-        Rt u[F];
-        if (cl[a] > 0) {
+        if (!on[a]) continue;
 #pragma unroll
-          for (int tt = 0; tt < F; ++tt) u[tt] = otr[a][t - tstride[a]][tt];
-        } else {
+        for (int q = 0; q < N; ++q) {
+          if (!on_out_face<NP, DIM>(q)) continue;
 #pragma unroll
-          for (int tt = 0; tt < F; ++tt) u[tt] = uin[a][tt];
-        }
-#pragma unroll
-        for (int i = 0; i < N; ++i) {
-          Rt acc = y[i];
-#pragma unroll
-          for (int tt = 0; tt < F; ++tt) acc = fma((Rt)row[L.g(a) + i * F + tt], u[tt], acc);
-          y[i] = acc;
+          for (int tt = 0; tt < F; ++tt) yo[q] = fma(kRegG ? gr[a][q][tt] : gl[a][q][tt], uin[a][tt], yo[q]);
         }
       }
-#pragma unroll
-      for (int q = 0; q < N; ++q) st_state(f + fm.f_base + d.plane_off[q] + cell, (St)y[q]);
       // outflow traces: theta x + (1 - theta) f^n on each downwind face
 #pragma unroll
       for (int b = 0; b < DIM; ++b) {
-        if (d.sgn[b] == 0) continue;
-        int fc = 0, fs = 1;
-#pragma unroll
-        for (int a2 = 0; a2 < DIM; ++a2)
-          if (a2 != b && d.sgn[a2] != 0) {
-            fc += cl[a2] * fs;
-            fs *= d.T[a2];
-          }
-        const bool to_next = cl[b] == d.T[b] - 1 && tl.down[b] >= 0;
-        uint64_t *dst = nullptr;
-        if (to_next) {
-          const DenseTile &dn = tiles[tl.down[b]];
-          dst = traces + dn.trace_off + (int64_t)b * dn.slot + fc * F;
-        }
+        if (!on[b]) continue;
 #pragma unroll
         for (int tt = 0; tt < F; ++tt) {
           const int q = face_node<NP, DIM>(b, tt, NP - 1);
-          const Rt o = th * y[q] + omt * fv[q];
+          const Rt o = th * yo[q] + omt * fv[q];
           otr[b][t][tt] = o;
-          if (to_next) {
+          if (dst[b] >= 0) {
             if (LEVEL)
-              dst[tt] = (uint64_t)__double_as_longlong((double)o);
+              traces[dst[b] + tt] = (uint64_t)__double_as_longlong((double)o);
             else
-              dense_put_trace(dst + tt, (double)o);
+              dense_put_trace(traces + dst[b] + tt, (double)o);
           }
         }
       }
@@ -441,6 +498,19 @@ __global__ __launch_bounds__(kDenseThreads) void dense_sweep_kernel(
     __builtin_amdgcn_wave_barrier();
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
   }
+  if (!active) return;
+  // every node: x = y + sum_a G_a u_a (the face nodes again, in the same
+  // order, so they equal the values the traces were taken from)
+#pragma unroll
+  for (int a = 0; a < DIM; ++a) {
+    if (!on[a]) continue;
+#pragma unroll
+    for (int q = 0; q < N; ++q)
+#pragma unroll
+      for (int tt = 0; tt < F; ++tt) y[q] = fma(gl[a][q][tt], uin[a][tt], y[q]);
+  }
+#pragma unroll
+  for (int q = 0; q < N; ++q) st_state(f + fm.f_base + d.plane_off[q] + cell, (St)y[q]);
 }
 
 }  // namespace
