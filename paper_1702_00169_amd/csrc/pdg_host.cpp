@@ -67,6 +67,7 @@ struct DenseGroup {
   int64_t first, count;  // tile range (tiles and claim order)
   int64_t sync_off;      // index of the group's tile-claim counter
   std::vector<int64_t> level;  // claim-order offsets where each tile diagonal starts (+ count)
+  bool claim = false;          // one launch of claimed tiles (else one launch per tile diagonal)
 };
 
 // One (instance, velocity) family of chains and its launch class.
@@ -142,7 +143,7 @@ struct pdg_ctx {
   DevBuf<double> dtable;
   DevBuf<uint64_t> dtraces;  // inflow-trace slots of the dense tiles (binary64 bits)
   DevBuf<int32_t> dsync;     // per group: tile-claim counter
-  bool dense_level = true;    // dense tiles: one launch per tile diagonal (else one claimed launch)
+  bool dense_claim = false;   // some dense group uses claimed tiles (their slots are reset per sweep)
   DevBuf<int32_t> derr;      // 1: a trace wait timed out, 2: claim counter overrun
   DevBuf<RelaxDesc> rdesc;
   DevBuf<RelaxItem> ritems;
@@ -1302,10 +1303,21 @@ pdg_status pdg_prepare(pdg_ctx *c, double dt, double theta, double omega, pdg_sc
   c->tau = tau;
   c->scheme = scheme;
   c->prec = prec;
-  // dense-path schedule: per-diagonal launches unless PDG_DENSE_SCHEDULE=claim
+  // Dense-tile schedule per kernel shape: claimed tiles (one launch, traces
+  // handed over between running tiles) for cells of 9 or more nodes, one
+  // launch per tile diagonal for the lighter cells of degree 1, whose tiles
+  // finish faster than a hand-over through the device-scope atomics
+  // (measured on 2D and 3D meshes).  PDG_DENSE_SCHEDULE=level or claim forces
+  // one schedule for every shape.
   {
     const char *ds = std::getenv("PDG_DENSE_SCHEDULE");
-    c->dense_level = !(ds && std::strcmp(ds, "claim") == 0);
+    const bool force_level = ds && std::strcmp(ds, "level") == 0;
+    const bool force_claim = ds && std::strcmp(ds, "claim") == 0;
+    c->dense_claim = false;
+    for (DenseGroup &g : c->dgroups) {
+      g.claim = force_claim || (!force_level && g.np >= 3);
+      c->dense_claim = c->dense_claim || g.claim;
+    }
   }
   c->prepared = true;
   return PDG_OK;
@@ -1326,7 +1338,7 @@ pdg_status do_sweep(pdg_ctx *c, void *f, const double *fb_old, const double *fb_
       return from_hip_at(e, what);
     }
   }
-  if (!c->dgroups.empty() && !c->dense_level) {
+  if (c->dense_claim) {
     // every trace slot empty, every claim counter at zero (fill kernels, so
     // that the sequence can be captured into a graph)
     hipError_t e = launch_fill_u64(c->dtraces.p, c->dtraces.n, kDenseTraceEmpty, st);
@@ -1334,7 +1346,7 @@ pdg_status do_sweep(pdg_ctx *c, void *f, const double *fb_old, const double *fb_
     if (e != hipSuccess) return from_hip_at(e, "dense sweep reset");
   }
   for (const DenseGroup &g : c->dgroups) {
-    if (c->dense_level) {
+    if (!g.claim) {
       // one launch per tile diagonal: no tile ever waits
       for (size_t k = 0; k + 1 < g.level.size(); ++k) {
         hipError_t e = launch_dense_sweep(c->prec, true, g.np, g.dim, c->dtiles.p + g.first,
