@@ -53,6 +53,7 @@ struct Group {
   int np;                // node count of every item in the launch
   int64_t first, count;  // range in the item array
   bool graded;           // chains on graded axes (their own kernel)
+  bool wpos = false;     // graded, and every tile width C a multiple of 64
 };
 
 struct RelaxGroup {
@@ -431,9 +432,10 @@ void build_items(pdg_ctx *c, std::vector<SweepItem> &items) {
     const std::pair<int, bool> key{k.np, k.x_kind == 2};
     if (!group_of.count(key)) {
       group_of[key] = (int)groups.size();
-      groups.push_back(Group{k.np, 0, 0, key.second});
+      groups.push_back(Group{k.np, 0, 0, key.second, key.second});
     }
     k.group = group_of[key];
+    if (k.C % 64 != 0) groups[k.group].wpos = false;
   }
   for (size_t g = 0; g < groups.size(); ++g) {
     groups[g].first = (int64_t)items.size();
@@ -1330,7 +1332,7 @@ namespace {
 pdg_status do_sweep(pdg_ctx *c, void *f, const double *fb_old, const double *fb_new, int dt_idx,
                     hipStream_t st) {
   for (const Group &g : c->groups) {
-    hipError_t e = launch_sweep(c->prec, g.np, g.graded, c->sitems.p + g.first, (int)g.count, c->sdesc.p, c->ops.p, dt_idx, f,
+    hipError_t e = launch_sweep(c->prec, g.np, g.graded, g.wpos, c->sitems.p + g.first, (int)g.count, c->sdesc.p, c->ops.p, dt_idx, f,
                                 fb_old, fb_new, c->stats.p + 2 * g.first, st);
     if (e != hipSuccess) {
       char what[96];
@@ -1610,7 +1612,7 @@ pdg_status pdg_autotune(pdg_ctx *c, void *f, const double *fb, int32_t reps, voi
       for (int r = 0; r <= reps && e == hipSuccess; ++r) {
         if (r == 1) e = hipEventRecord(e0, st);
         if (e == hipSuccess)
-          e = launch_sweep(c->prec, g.np, g.graded, c->sitems.p + k.first, (int)k.count, c->sdesc.p, c->ops.p, 0, f, fb, fb,
+          e = launch_sweep(c->prec, g.np, g.graded, g.wpos, c->sitems.p + k.first, (int)k.count, c->sdesc.p, c->ops.p, 0, f, fb, fb,
                            c->stats.p + 2 * k.first, st);
       }
       if (e == hipSuccess) e = hipEventRecord(e1, st);

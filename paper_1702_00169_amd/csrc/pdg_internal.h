@@ -156,8 +156,9 @@ enum Prec { kF64 = 0, kF32 = 1, kRefine = 2 };
 hipError_t launch_invert(OpEntry *ops, int n_ops, hipStream_t st);
 
 // Launch one sweep over items that share the node count np (any chain kind,
-// tile shape or instance).
-hipError_t launch_sweep(int prec, int np, bool graded, const SweepItem *items, int n_items,
+// tile shape or instance).  graded: chains on graded axes; wpos: their tile
+// width C is a multiple of 64 (each wave at one chain position).
+hipError_t launch_sweep(int prec, int np, bool graded, bool wpos, const SweepItem *items, int n_items,
                         const SweepDesc *descs, const OpEntry *ops, int dt_idx, void *f, const double *fb_old,
                         const double *fb_new, double *stats, hipStream_t st);
 

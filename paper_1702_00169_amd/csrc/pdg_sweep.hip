@@ -362,8 +362,11 @@ __global__ __launch_bounds__(kBlock) void sweep_kernel(const SweepItem *__restri
 // (c, p) owns segment p of chain c, the segment maps are composed through
 // LDS -- with each cell's own M, g and a: the segment map is
 // u_out = (prod a_l) u_in + beta with beta_{l+1} = a_l beta_l + theta (M_l
-// f_l)_out + (1 - theta) f_l,out.  Used for chains along any axis.
-template <int PREC, int NP, int SMAX>
+// f_l)_out + (1 - theta) f_l,out.  Used for chains along any axis.  WPOS:
+// C is a multiple of 64, so every wave sits at one chain position and reads
+// the cell operators through scalar loads (they then take no vector
+// registers, and more waves fit on a SIMD).
+template <int PREC, int NP, int SMAX, bool WPOS>
 __global__ __launch_bounds__(kBlock) void sweep_graded_kernel(const SweepItem *__restrict__ items,
                                                              const SweepDesc *__restrict__ descs,
                                                              const OpEntry *__restrict__ ops, int dt_idx,
@@ -398,6 +401,10 @@ __global__ __launch_bounds__(kBlock) void sweep_graded_kernel(const SweepItem *_
   for (int w0 = 0; w0 < n; w0 += window, wpar ^= 1) {
     const int lb = w0 + p * S;
     const int cnt = active ? max(0, min(S, n - lb)) : 0;
+    // operator rows of the window's cells (the same for every lane of a wave
+    // when WPOS)
+    const int lbo = WPOS ? __builtin_amdgcn_readfirstlane(lb) : lb;
+    const int cnto = max(0, min(S, n - lbo));
     Rt y[SMAX][NP], gs[SMAX][NP];
     Rt fo[SMAX], as[SMAX];
 #pragma unroll
@@ -412,7 +419,7 @@ __global__ __launch_bounds__(kBlock) void sweep_graded_kernel(const SweepItem *_
       }
       fo[s] = fv[NP - 1];
       CellOp<PREC, NP> op;
-      op.load(row[s < cnt ? lb + s : 0]);
+      op.load(row[s < cnto ? lbo + s : 0]);
       op.solve(fv, y[s], cmax, ymax);
 #pragma unroll
       for (int q = 0; q < NP; ++q) gs[s][q] = op.g[q];
@@ -542,15 +549,18 @@ __global__ void invert_kernel(OpEntry *ops, int n_ops) {
 // dispatch
 // ---------------------------------------------------------------------------
 template <int PREC, int NP>
-hipError_t go_sweep(bool graded, const SweepItem *items, int n_items, const SweepDesc *descs, const OpEntry *ops,
-                    int dt_idx, void *f, const double *fb_old, const double *fb_new, double *stats,
-                    hipStream_t st) {
+hipError_t go_sweep(bool graded, bool wpos, const SweepItem *items, int n_items, const SweepDesc *descs,
+                    const OpEntry *ops, int dt_idx, void *f, const double *fb_old, const double *fb_new,
+                    double *stats, hipStream_t st) {
   using St = typename Pol<PREC>::St;
   constexpr int SMAX = sweep_smax(NP);
   constexpr int SMAXG = sweep_smax_graded(NP);
-  if (graded)
-    hipLaunchKernelGGL((sweep_graded_kernel<PREC, NP, SMAXG>), dim3(n_items), dim3(kBlock), 0, st, items, descs, ops,
-                       dt_idx, static_cast<St *>(f), fb_old, fb_new, stats);
+  if (graded && wpos)
+    hipLaunchKernelGGL((sweep_graded_kernel<PREC, NP, SMAXG, true>), dim3(n_items), dim3(kBlock), 0, st, items, descs,
+                       ops, dt_idx, static_cast<St *>(f), fb_old, fb_new, stats);
+  else if (graded)
+    hipLaunchKernelGGL((sweep_graded_kernel<PREC, NP, SMAXG, false>), dim3(n_items), dim3(kBlock), 0, st, items,
+                       descs, ops, dt_idx, static_cast<St *>(f), fb_old, fb_new, stats);
   else
     hipLaunchKernelGGL((sweep_kernel<PREC, NP, SMAX>), dim3(n_items), dim3(kBlock), 0, st, items, descs, ops,
                        dt_idx, static_cast<St *>(f), fb_old, fb_new, stats);
@@ -558,14 +568,14 @@ hipError_t go_sweep(bool graded, const SweepItem *items, int n_items, const Swee
 }
 
 template <int PREC>
-hipError_t go_sweep_np(bool graded, int np, const SweepItem *items, int n_items, const SweepDesc *descs,
+hipError_t go_sweep_np(bool graded, bool wpos, int np, const SweepItem *items, int n_items, const SweepDesc *descs,
                        const OpEntry *ops, int dt_idx, void *f, const double *fb_old, const double *fb_new,
                        double *stats, hipStream_t st) {
   switch (np) {
-    case 2: return go_sweep<PREC, 2>(graded, items, n_items, descs, ops, dt_idx, f, fb_old, fb_new, stats, st);
-    case 3: return go_sweep<PREC, 3>(graded, items, n_items, descs, ops, dt_idx, f, fb_old, fb_new, stats, st);
-    case 4: return go_sweep<PREC, 4>(graded, items, n_items, descs, ops, dt_idx, f, fb_old, fb_new, stats, st);
-    case 5: return go_sweep<PREC, 5>(graded, items, n_items, descs, ops, dt_idx, f, fb_old, fb_new, stats, st);
+    case 2: return go_sweep<PREC, 2>(graded, wpos, items, n_items, descs, ops, dt_idx, f, fb_old, fb_new, stats, st);
+    case 3: return go_sweep<PREC, 3>(graded, wpos, items, n_items, descs, ops, dt_idx, f, fb_old, fb_new, stats, st);
+    case 4: return go_sweep<PREC, 4>(graded, wpos, items, n_items, descs, ops, dt_idx, f, fb_old, fb_new, stats, st);
+    case 5: return go_sweep<PREC, 5>(graded, wpos, items, n_items, descs, ops, dt_idx, f, fb_old, fb_new, stats, st);
     default: return hipErrorInvalidValue;
   }
 }
@@ -578,14 +588,14 @@ hipError_t launch_invert(OpEntry *ops, int n_ops, hipStream_t st) {
   return hipGetLastError();
 }
 
-hipError_t launch_sweep(int prec, int np, bool graded, const SweepItem *items, int n_items,
+hipError_t launch_sweep(int prec, int np, bool graded, bool wpos, const SweepItem *items, int n_items,
                         const SweepDesc *descs, const OpEntry *ops, int dt_idx, void *f, const double *fb_old,
                         const double *fb_new, double *stats, hipStream_t st) {
   if (n_items <= 0) return hipSuccess;
   switch (prec) {
-    case kF64: return go_sweep_np<kF64>(graded, np, items, n_items, descs, ops, dt_idx, f, fb_old, fb_new, stats, st);
-    case kF32: return go_sweep_np<kF32>(graded, np, items, n_items, descs, ops, dt_idx, f, fb_old, fb_new, stats, st);
-    case kRefine: return go_sweep_np<kRefine>(graded, np, items, n_items, descs, ops, dt_idx, f, fb_old, fb_new, stats, st);
+    case kF64: return go_sweep_np<kF64>(graded, wpos, np, items, n_items, descs, ops, dt_idx, f, fb_old, fb_new, stats, st);
+    case kF32: return go_sweep_np<kF32>(graded, wpos, np, items, n_items, descs, ops, dt_idx, f, fb_old, fb_new, stats, st);
+    case kRefine: return go_sweep_np<kRefine>(graded, wpos, np, items, n_items, descs, ops, dt_idx, f, fb_old, fb_new, stats, st);
     default: return hipErrorInvalidValue;
   }
 }
