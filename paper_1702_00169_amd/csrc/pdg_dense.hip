@@ -1,6 +1,9 @@
 // gfx950 kernels of the transport sweep for velocities with two or three
 // non-zero components: dense cell blocks in a tiled wavefront.
 
+#include <type_traits>
+#include <utility>
+
 #include "pdg_device.h"
 
 namespace pdg {
@@ -190,6 +193,21 @@ __device__ __forceinline__ void dense_local_solve(const double *row, const typen
       y[i] = acc;
     }
   }
+}
+
+// Register slots of the claimed schedule's trace requests: up to 4 (three
+// diagonals ahead), as many as fit in 64 VGPRs.
+template <int DIM, int F>
+__device__ constexpr int dense_peek_ring() {
+  const int r = 64 / (2 * DIM * F);
+  return r < 1 ? 1 : (r > 4 ? 4 : r);
+}
+
+// One turn of the request ring: step(s0 + k, k) for k = 0 .. RING - 1 while
+// s0 + k < n, with k a constant.
+template <class Step, int... K>
+__device__ __forceinline__ void dense_ring_turn(int s0, int n, Step &step, std::integer_sequence<int, K...>) {
+  ((s0 + K < n ? step(s0 + K, std::integral_constant<int, K>{}) : void()), ...);
 }
 
 // Cross-tile hand-off.  A tile's inflow traces are written by its upwind
@@ -440,12 +458,70 @@ __global__ __launch_bounds__(kDenseThreads) void dense_sweep_kernel(
           for (int tt = 0; tt < F; ++tt) gr[a][q][tt] = gl[a][q][tt];
   }
 
+  // Claimed schedule: a cell's traces from upwind tiles are requested AHEAD
+  // diagonals before the cell's own (compare-and-swap reads that do not
+  // wait), so the round trip overlaps the diagonals in between; only a value
+  // still empty when it is needed is polled again, waiting.  The requests
+  // land in a ring of AHEAD + 1 register slots (lanes of different
+  // diagonals write different registers: a register with a request in
+  // flight cannot be read by any lane); the diagonal loop is unrolled by the
+  // ring length, so the slot indices are constants.  The ring is kept within
+  // 64 VGPRs; without one (large faces) a cell requests and waits at its own
+  // diagonal.
+  constexpr int RING = dense_peek_ring<DIM, F>();
+  constexpr int AHEAD = RING - 1;
+  // (no ring: a one-slot placeholder, unused)
+  uint64_t pk[AHEAD > 0 ? RING : 1][AHEAD > 0 ? DIM : 1][AHEAD > 0 ? F : 1];
+  if constexpr (AHEAD > 0) {
+#pragma unroll
+    for (int k = 0; k < RING; ++k)
+#pragma unroll
+      for (int a = 0; a < DIM; ++a)
+#pragma unroll
+        for (int tt = 0; tt < F; ++tt) pk[k][a][tt] = kDenseTraceEmpty;
+  }
+  auto peek = [&](auto &slot) {
+#pragma unroll
+    for (int a = 0; a < DIM; ++a)
+      if (rsrc[a] >= 0)
+#pragma unroll
+        for (int tt = 0; tt < F; ++tt) slot[a][tt] = dense_peek_trace(traces + rsrc[a] + tt);
+  };
+  if constexpr (!LEVEL && AHEAD > 0) {
+    if (active && diag < AHEAD) {
+#pragma unroll
+      for (int k = 0; k < AHEAD; ++k)
+        if (diag == k) peek(pk[k]);
+    }
+  }
+
   // Diagonal by diagonal, a cell needs only its outflow traces on the
   // critical path: the nodes on its downwind faces.  The inflow traces it
   // used are kept (uin) for the update of the other nodes after the loop.
-  for (int s = 0; s < ndiag; ++s) {
+  // diagonal s; k = s mod RING, a constant (the slot of diagonal s)
+  auto step = [&](int s, auto kc) {
+    constexpr int k = decltype(kc)::value;
+    if constexpr (!LEVEL && AHEAD > 0) {
+      if (active && diag == s + AHEAD) peek(pk[(k + AHEAD) % RING]);
+    }
     if (active && diag == s) {
-      if (!LEVEL) {
+      if constexpr (!LEVEL && AHEAD > 0) {
+        // the request made AHEAD diagonals ago; poll again only if empty
+        uint64_t(&cur)[DIM][F] = pk[k];
+        bool ready = true;
+#pragma unroll
+        for (int a = 0; a < DIM; ++a)
+          if (rsrc[a] >= 0)
+#pragma unroll
+            for (int tt = 0; tt < F; ++tt) ready = ready && cur[a][tt] != kDenseTraceEmpty;
+        if (!ready) dense_take_faces<DIM, F>(traces, rsrc, cur, err_flag);
+#pragma unroll
+        for (int a = 0; a < DIM; ++a)
+          if (rsrc[a] >= 0)
+#pragma unroll
+            for (int tt = 0; tt < F; ++tt) uin[a][tt] = (Rt)__longlong_as_double((long long)cur[a][tt]);
+      } else if constexpr (!LEVEL) {
+        // no ring: request and wait now
         uint64_t rb[DIM][F];
         dense_take_faces<DIM, F>(traces, rsrc, rb, err_flag);
 #pragma unroll
@@ -497,6 +573,11 @@ __global__ __launch_bounds__(kDenseThreads) void dense_sweep_kernel(
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
     __builtin_amdgcn_wave_barrier();
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+  };
+  if constexpr (LEVEL) {
+    for (int s = 0; s < ndiag; ++s) step(s, std::integral_constant<int, 0>{});
+  } else {
+    for (int s0 = 0; s0 < ndiag; s0 += RING) dense_ring_turn(s0, ndiag, step, std::make_integer_sequence<int, RING>{});
   }
   if (!active) return;
   // every node: x = y + sum_a G_a u_a (the face nodes again, in the same

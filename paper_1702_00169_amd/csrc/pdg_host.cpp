@@ -1306,18 +1306,18 @@ pdg_status pdg_prepare(pdg_ctx *c, double dt, double theta, double omega, pdg_sc
   c->scheme = scheme;
   c->prec = prec;
   // Dense-tile schedule per kernel shape: claimed tiles (one launch, traces
-  // handed over between running tiles) for cells of 9 or more nodes, one
-  // launch per tile diagonal for the lighter cells of degree 1, whose tiles
-  // finish faster than a hand-over through the device-scope atomics
-  // (measured on 2D and 3D meshes).  PDG_DENSE_SCHEDULE=level or claim forces
-  // one schedule for every shape.
+  // handed over between running tiles) except for the 8-node cells of 3D
+  // degree 1, whose 4 x 4 x 4 tiles finish faster than a hand-over through
+  // the device-scope atomics (measured on 2D and 3D meshes), so one launch
+  // per tile diagonal serves them better.  PDG_DENSE_SCHEDULE=level or claim
+  // forces one schedule for every shape.
   {
     const char *ds = std::getenv("PDG_DENSE_SCHEDULE");
     const bool force_level = ds && std::strcmp(ds, "level") == 0;
     const bool force_claim = ds && std::strcmp(ds, "claim") == 0;
     c->dense_claim = false;
     for (DenseGroup &g : c->dgroups) {
-      g.claim = force_claim || (!force_level && g.np >= 3);
+      g.claim = force_claim || (!force_level && !(g.dim == 3 && g.np == 2));
       c->dense_claim = c->dense_claim || g.claim;
     }
   }
