@@ -33,12 +33,20 @@ the compositions becomes S(a) C(h) S(b) with source step S of Sec. 3.2:
 * STRANG:            T(dt/2) S(dt/2) C(dt) S(dt/2) T(dt/2), the paper's M_2^s;
 * STRANG_COLLAPSED:  M_2^s with the inner transports fused, as in Sec. 5.1;
 * KIN, KIN4:         each C(h/2) of M_2^kin(h) becomes S(h/4) C(h/2) S(h/4).
-                     The paper does not give M_2^kin with a source; this
-                     symmetric placement keeps the composition palindromic.
+                     The paper does not give M_2^kin with a source.  S moves
+                     only the equilibrium part and C relaxes only the
+                     non-equilibrium part, so S and C commute and the split
+                     of a collision's source around it is immaterial; what
+                     this reading fixes is that each collision carries the
+                     source over h/2, which keeps the composition palindromic
+                     (time symmetric) and integrates the source over h.
 
 Pins: a constant equilibrium state is preserved over several steps (scalar
 and Euler), second-order convergence in dt of the collapsed scheme for scalar
-advection, and the involution C(C(f)) = f at omega = 2.
+advection, and the involution C(C(f)) = f at omega = 2.  With the source:
+S C = C S, time symmetry of M_2^kin and of the triple jump at tau > 0,
+hydrostatic convergence at order 2 for M_2^kin, time order 4 for the triple
+jump, and two planted source mistakes that these pins reject.
 """
 
 import numpy as np

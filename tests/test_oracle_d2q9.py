@@ -164,3 +164,124 @@ def test_wrong_source_sign_breaks_hydrostatic_balance():
     right = _hydro_error(4, 3, ost.STRANG, 0.5, 2.0, 10)
     wrong = _hydro_error(4, 3, ost.STRANG, 0.5, 2.0, 10, g_source=-G)
     assert wrong > 20 * right, (right, wrong)
+
+
+# ---- M_2^kin and its triple jump with the gravity source (Sec. 3.2 + Sec. 5.1) ----
+# The paper gives M_2^kin without a source.  The oracle's reading: each
+# collision C(h/2) of M_2^kin(h) carries the source over h/2, as
+# S(h/4) C(h/2) S(h/4).  The pins below fix what that reading determines:
+# the source commutes with the collision (so its split around one collision
+# is immaterial), the composition stays time symmetric, it approaches the
+# hydrostatic state at order 2, and the triple jump raises the time order to
+# 4.  Planted mistakes (all the source at the first collision; half the
+# total source) must fail them.
+
+
+def _kin_variant(prob, f0, fb, dt, theta, omega, nsteps, pre=(0.25, 0.25), post=(0.25, 0.25)):
+    """M_2^kin(dt) steps with source fractions (pre, post) x dt around the
+    two collisions; (1/4, 1/4) each is the oracle's reading."""
+    f = np.array(f0, dtype=float, copy=True)
+    for _ in range(nsteps):
+        wh = ost.omega_for(dt / 2, dt, omega)
+        f = prob.transport(f, fb, fb, dt / 4, theta)
+        f = prob.local(f, pre[0] * dt, wh, post[0] * dt)
+        f = prob.transport(f, fb, fb, dt / 2, theta)
+        f = prob.local(f, pre[1] * dt, wh, post[1] * dt)
+        f = prob.transport(f, fb, fb, dt / 4, theta)
+    return f
+
+
+ALL_AT_FIRST = dict(pre=(0.5, 0.0), post=(0.5, 0.0))     # planted: total right, placement asymmetric
+HALF_SOURCE = dict(pre=(0.125, 0.125), post=(0.125, 0.125))  # planted: half the total source
+
+
+def _kin_setup():
+    prob = _problem(g=1.3, n=(3, 2), degree=2)
+    f = _random_f(prob, 4)
+    fb = [prob.feq(_state(prob.entries(v)["coords"].shape[0], 10 + v))[v] for v in range(9)]
+    return prob, f, fb
+
+
+def _omega_backwards(dt, omega):
+    """Collision factor over -dt for the relaxation time that omega fixes over dt."""
+    tau = dt * (2.0 - omega) / (2.0 * omega)
+    return -2.0 * dt / (2.0 * tau - dt)
+
+
+@pytest.mark.parametrize("h", [0.3, -0.2])
+@pytest.mark.parametrize("omega", [1.6, 2.0])
+def test_source_commutes_with_collision(h, omega):
+    # S moves only the equilibrium part, C relaxes only the non-equilibrium part
+    prob, f, _ = _kin_setup()
+    a = prob.source(prob.collide(f, omega), h)
+    b = prob.collide(prob.source(f, h), omega)
+    assert np.linalg.norm(a - b) <= 1e-14 * np.linalg.norm(a)
+
+
+@pytest.mark.parametrize("scheme", [ost.KIN, ost.KIN4], ids=["kin", "kin4"])
+def test_kin_compositions_with_source_are_time_symmetric(scheme):
+    # tau > 0 (omega = 1.6) and g != 0: M(-dt) M(dt) = Id (Sec. 3.2)
+    prob, f, fb = _kin_setup()
+    dt, omega = 0.05, 1.6
+    g = ost.run(prob, f, fb, dt, 0.5, omega, scheme, 1)
+    back = ost.run(prob, g, fb, -dt, 0.5, _omega_backwards(dt, omega), scheme, 1)
+    assert np.linalg.norm(g - f) > 1e-3 * np.linalg.norm(f)
+    assert np.linalg.norm(back - f) <= 1e-13 * np.linalg.norm(f)
+
+
+def test_planted_asymmetric_source_breaks_time_symmetry():
+    prob, f, fb = _kin_setup()
+    dt, omega = 0.05, 1.6
+    ob = _omega_backwards(dt, omega)
+    ok = _kin_variant(prob, _kin_variant(prob, f, fb, dt, 0.5, omega, 1), fb, -dt, 0.5, ob, 1)
+    bad = _kin_variant(prob, _kin_variant(prob, f, fb, dt, 0.5, omega, 1, **ALL_AT_FIRST), fb, -dt, 0.5, ob, 1,
+                       **ALL_AT_FIRST)
+    assert np.linalg.norm(ok - f) <= 1e-13 * np.linalg.norm(f)
+    assert np.linalg.norm(bad - f) > 1e-3 * np.linalg.norm(f)
+    # and the oracle's KIN is the symmetric variant
+    np.testing.assert_allclose(ost.run(prob, f, fb, dt, 0.5, omega, ost.KIN, 2),
+                               _kin_variant(prob, f, fb, dt, 0.5, omega, 2), rtol=0, atol=1e-14)
+
+
+def _hydro_variant_error(n, degree, omega, nsteps, **kw):
+    prob = ost.Problem((n, n), (0.0, 0.0), (1.0, 1.0), degree, D2Q9 * LAM, 1, "d2q9", {"g": G})
+    x = prob.mesh.node_coords().reshape(-1, 2)
+    w0 = _w_hydro(x).reshape(3, prob.mesh.nc, prob.mesh.nd)
+    fb = prob.inflow_from_w(_w_hydro)
+    f = _kin_variant(prob, prob.feq(w0), fb, T_END / nsteps, 0.5, omega, nsteps, **kw)
+    return np.linalg.norm(prob.moments(f) - w0) / np.linalg.norm(w0)
+
+
+@pytest.mark.slow
+@pytest.mark.parametrize("omega", [2.0, 1.6])
+def test_kin_hydrostatic_state_second_order(omega):
+    errs = [_hydro_error(4, 4, ost.KIN, 0.5, omega, N) for N in (5, 10)]
+    rate = np.log2(errs[0] / errs[1])
+    print(f"M2kin omega={omega}: errors {errs}, rate {rate:.2f}")
+    assert 1.8 <= rate <= 2.3 and errs[1] < 2e-4, (errs, rate)
+
+
+@pytest.mark.slow
+def test_planted_source_mistakes_fail_the_hydrostatic_test():
+    # all the source at the first collision: first order
+    errs = [_hydro_variant_error(4, 4, 2.0, N, **ALL_AT_FIRST) for N in (5, 10)]
+    assert np.log2(errs[0] / errs[1]) < 1.3, errs
+    # half the source: the hydrostatic balance is lost, no convergence
+    errs = [_hydro_variant_error(4, 4, 2.0, N, **HALF_SOURCE) for N in (5, 10)]
+    assert min(errs) > 0.04, errs
+
+
+@pytest.mark.slow
+@pytest.mark.parametrize("scheme,lo,hi", [(ost.KIN, 1.8, 2.2), (ost.KIN4, 3.6, 4.4)], ids=["kin", "kin4"])
+def test_kin_time_order_with_source(scheme, lo, hi):
+    # time self-convergence on one spatial discretisation (the hydrostatic
+    # error of the triple jump is dominated by the spatial error): differences
+    # of successive halvings of dt shrink at the time order
+    prob = ost.Problem((4, 4), (0.0, 0.0), (1.0, 1.0), 2, D2Q9 * LAM, 1, "d2q9", {"g": G})
+    x = prob.mesh.node_coords().reshape(-1, 2)
+    w0 = _w_hydro(x).reshape(3, prob.mesh.nc, prob.mesh.nd)
+    fb = prob.inflow_from_w(_w_hydro)
+    ws = {N: prob.moments(ost.run(prob, prob.feq(w0), fb, T_END / N, 0.5, 2.0, scheme, N)) for N in (6, 12, 24)}
+    rate = np.log2(np.linalg.norm(ws[6] - ws[12]) / np.linalg.norm(ws[12] - ws[24]))
+    print(f"scheme {scheme}: time order {rate:.2f}")
+    assert lo <= rate <= hi, rate
