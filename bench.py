@@ -11,10 +11,12 @@ Prints one JSON line (rank 0 of a single process):
   value      = N_DoF * K / wall time      [DoF-updates/s], N_DoF = nv m Nc (d+1)^D
   roofline   = the sweep kernel (the dominant launch) against the 8 TB/s HBM
                peak: algorithmic bytes per launch = read + write of the state,
-               2 s N_DoF (s = 8 B for binary64 and binary32+refine state,
-               4 B for binary32), over its HIP-event launch duration
+               2 s N_DoF (s = 8 B for the binary64 state, 6 B for the 48-bit
+               state of binary32 + refinement, 4 B for binary32), over its
+               HIP-event launch duration
   precisions = the same measurement for binary64, binary32 + binary64
-               refinement and plain binary32, each with its error
+               refinement on the 48-bit state and on a binary64 state, and
+               plain binary32, each with its error against binary64
   cpu_baseline = the CPU oracle timed on a bounded sample of the workload
 """
 import argparse
@@ -33,8 +35,10 @@ import workloads as W  # noqa: E402
 
 METRIC = "DoF-updates/s per transport+relax step, FP32+refine vs FP64 at stated error"
 HBM_PEAK_GBS = 8000.0
-PREC_NAMES = {0: "fp64", 2: "fp32refine", 1: "fp32"}
-DTYPE_NAMES = {0: "f64", 2: "f64", 1: "f32"}
+PREC_NAMES = {0: "fp64", 3: "fp32refine48", 2: "fp32refine", 1: "fp32"}
+# arithmetic of the path: binary32 cell solves + binary64 residual for the refined ones
+DTYPE_NAMES = {0: "f64", 3: "f32+f64", 2: "f32+f64", 1: "f32"}
+STATE_BYTES = {0: 8, 3: 6, 2: 8, 1: 4}
 DEFAULT_WORKLOAD = "euler3d_128"
 
 
@@ -46,7 +50,7 @@ def inst_dict(inst):
                 edges=getattr(inst, "edges", None))
 
 
-def initial_state(pdg, prob, insts, torch, dtype):
+def initial_state(pdg, prob, insts, torch):
     """f = f^eq(w0) and fb = f^eq(w0 at the inflow points), built on the device.
     w_inflow holds, per instance and velocity, the moments of w0 at the
     velocity's inflow points (m moments, or 3 for the D2Q9 model)."""
@@ -69,7 +73,7 @@ def initial_state(pdg, prob, insts, torch, dtype):
             if blocks:
                 fbw_blocks.append(np.concatenate(blocks, axis=1).ravel())   # [k][face][t][tau]
     fbw = np.concatenate(fbw_blocks) if fbw_blocks else np.zeros(1)
-    f = torch.empty(prob.layout["f_elems"], dtype=dtype, device="cuda")
+    f = prob.new_state()   # the prepared precision's storage
     fb = torch.empty(prob.layout["fb_elems"], dtype=torch.float64, device="cuda")
     w_t = torch.from_numpy(w).cuda()
     prob.equilibrium(w_t, f)
@@ -131,7 +135,7 @@ def record_traffic(workload, prec_name, fetch_csv, write_csv):
     fetch_factor = copy_bytes / (sum(cf) / len(cf) * 1024)
     write_factor = copy_bytes / (sum(cw) / len(cw) * 1024)
     wl = W.make(workload)
-    state_b = 4 if prec_name == "fp32" else 8
+    state_b = {"fp32": 4, "fp32refine48": 6}.get(prec_name, 8)
     alg_write_kib = wl.n_dof * state_b / 1024
     sf, sw = values(f, "sweep_kernel"), values(w, "sweep_kernel")
     # the full sweep launches (steps and timing loop) write the whole state;
@@ -162,8 +166,7 @@ def measure(pdg, torch, wl, prec, steps, warmup, reps, keep_state=False, autotun
     insts = wl.instances
     prob = pdg.Problem([inst_dict(i) for i in insts])
     prob.prepare(wl.dt, theta=wl.theta, omega=wl.omega, scheme=pdg.PDG_STRANG_COLLAPSED, precision=prec)
-    dtype = torch.float32 if prec == pdg.PDG_FP32 else torch.float64
-    f, fb, w_t = initial_state(pdg, prob, insts, torch, dtype)
+    f, fb, w_t = initial_state(pdg, prob, insts, torch)
     if tiles:
         prob.set_tiles(tiles)
     elif autotune:
@@ -184,7 +187,7 @@ def measure(pdg, torch, wl, prec, steps, warmup, reps, keep_state=False, autotun
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     prob.sync_status()   # raises (PDG_EDEVICE) if a dense-path wait gave up: the timed run would be invalid
-    refine_corr = prob.last_refine_correction() if prec == pdg.PDG_FP32_REFINE else None
+    refine_corr = prob.last_refine_correction() if prec in (pdg.PDG_FP32_REFINE, pdg.PDG_FP32_REFINE_P48) else None
     # per-launch durations on the stream the kernels run on
     stream = torch.cuda.current_stream()
     ev = [torch.cuda.Event(enable_timing=True) for _ in range(4)]
@@ -199,7 +202,7 @@ def measure(pdg, torch, wl, prec, steps, warmup, reps, keep_state=False, autotun
     prob.sync_status()
     t_sweep = ev[0].elapsed_time(ev[1]) / reps * 1e-3
     t_relax = ev[1].elapsed_time(ev[2]) / reps * 1e-3
-    state_bytes = 4 if prec == pdg.PDG_FP32 else 8
+    state_bytes = STATE_BYTES[prec]
     out = dict(
         value=n_dof * steps / wall, ms_per_step=wall / steps * 1e3, wall_s=wall,
         sweep_us=t_sweep * 1e6, relax_us=t_relax * 1e6,
@@ -217,7 +220,7 @@ def measure(pdg, torch, wl, prec, steps, warmup, reps, keep_state=False, autotun
         prob.step(g, fb, steps)
         torch.cuda.synchronize()
         prob.sync_status()
-        result = g if g.dtype == torch.float64 else g.double()   # stays on the device
+        result = prob.state_to_f64(g)   # binary64 values, on the device
         del g
     del f, fb
     prob.close()
@@ -273,7 +276,7 @@ def main():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default=DEFAULT_WORKLOAD, choices=W.WORKLOADS)
-    ap.add_argument("--precision", default="fp64", choices=["fp64", "fp32refine", "fp32"])
+    ap.add_argument("--precision", default="fp64", choices=list(PREC_NAMES.values()))
     ap.add_argument("--reps", type=int, default=20, help="launches per kernel-timing loop")
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--no-compare", action="store_true", help="skip the other precisions")
@@ -301,10 +304,10 @@ def main():
     import paper_1702_00169_amd as pdg
     torch.cuda.set_device(0)
 
-    prec_main = {"fp64": pdg.PDG_FP64, "fp32refine": pdg.PDG_FP32_REFINE, "fp32": pdg.PDG_FP32}[args.precision]
+    prec_main = {v: k for k, v in PREC_NAMES.items()}[args.precision]
     wl = W.make(args.workload, seed=args.seed)
     compare = not args.no_compare
-    precs = [prec_main] + ([p for p in (0, 2, 1) if p != prec_main] if compare else [])
+    precs = [prec_main] + ([p for p in (0, 3, 2, 1) if p != prec_main] if compare else [])
     results, states = {}, {}
     for p in precs:
         print(f"[bench] {args.workload} {PREC_NAMES[p]}: {args.warmup} warm-up + {args.steps} timed steps",
@@ -360,7 +363,8 @@ def main():
             "kernel": "transport sweep (sweep_kernel" + (" + dense_sweep_kernel)" if dense else ")"), "algorithmic_bytes_per_launch": main_res["bytes_per_sweep"],
             "launch_us": main_res["sweep_us"], "device_copy_gbs": copy_gbs,
             "traffic_over_algorithmic": (traffic / main_res["bytes_per_sweep"]) if traffic else None,
-            "step_gbs_at_32B_per_dof": main_res["value"] * 4 * (4 if prec_main == pdg.PDG_FP32 else 8) / 1e9}
+            "step_bytes_per_dof": 4 * STATE_BYTES[prec_main],
+            "step_gbs": main_res["value"] * 4 * STATE_BYTES[prec_main] / 1e9}
     inst0 = wl.instances[0]
     config = {"workload": f"{args.workload}: {wl.description}", "n_dof": wl.n_dof,
               "instances": len(wl.instances), "cells": list(inst0.n) if len(wl.instances) == 1 else "per instance",

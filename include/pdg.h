@@ -77,8 +77,19 @@ typedef enum {
 typedef enum {
   PDG_FP64 = 0,        /* state and arithmetic in binary64 */
   PDG_FP32 = 1,        /* state and arithmetic in binary32 (moments in binary64) */
-  PDG_FP32_REFINE = 2  /* binary64 state; binary32 cell solves with one binary64
+  PDG_FP32_REFINE = 2, /* binary64 state; binary32 cell solves with one binary64
                           residual correction per cell */
+  PDG_FP32_REFINE_P48 = 3 /* the arithmetic of PDG_FP32_REFINE with the state kept in
+                          48 bits per value (6 bytes instead of 8, so a transport +
+                          relax step moves 24 instead of 32 bytes per unknown).  The
+                          f buffer holds 6 * f_elems bytes: f_elems binary32 values h
+                          (each value rounded to nearest), then f_elems int16 values l;
+                          the value is h + l * 2^(e - 39), e the binary exponent of h
+                          (e = -126 for h = 0 or subnormal), l = round((value - h) /
+                          2^(e - 39)) clamped to +-32767: a 40-bit significand, relative
+                          rounding <= 2^-39, for |value| < 2^128.  Each
+                          kernel rounds the values it writes to this format; use
+                          pdg_state_from_f64 / pdg_state_to_f64 to convert. */
 } pdg_precision;
 
 typedef enum {
@@ -199,6 +210,15 @@ pdg_status pdg_prepare(pdg_ctx *c, double dt, double theta, double omega, pdg_sc
  * f in the state precision).  Sets an initial state (Sec. 2). */
 pdg_status pdg_equilibrium(pdg_ctx *c, const double *w, void *f, void *stream);
 
+/* Conversion between the state (f in the prepared precision, layout as
+ * above; for PDG_FP32_REFINE_P48 the two planes described there) and binary64
+ * values x[v][k][j][c] (device, f_elems values): pdg_state_to_f64 reads f into
+ * x, pdg_state_from_f64 writes x into f (rounded to the state precision).
+ * Element-wise, stream ordered; x and f must not overlap.  Used to set or
+ * inspect a state whose storage is not binary64. */
+pdg_status pdg_state_to_f64(pdg_ctx *c, const void *f, double *x, void *stream);
+pdg_status pdg_state_from_f64(pdg_ctx *c, const double *x, void *f, void *stream);
+
 /* fb = f^eq_{v}(w) at the inflow points of every velocity (device, binary64):
  * w_inflow holds, per instance and velocity v (in that order), nw blocks
  * (one per moment) of the macroscopic field at v's inflow points, in the
@@ -260,7 +280,7 @@ pdg_status pdg_get_tiles(const pdg_ctx *c, int32_t *n_classes, int32_t *tiles);
  * invalid tile; nothing is changed then. */
 pdg_status pdg_set_tiles(pdg_ctx *c, int32_t n_classes, const int32_t *tiles);
 
-/* For PDG_FP32_REFINE: max over nodes of |correction| / max |solution| seen by
+/* For PDG_FP32_REFINE and PDG_FP32_REFINE_P48: max over nodes of |correction| / max |solution| seen by
  * the most recent sweep (synchronises the stream of that sweep). */
 pdg_status pdg_last_refine_correction(const pdg_ctx *c, double *max_rel_correction);
 

@@ -16,12 +16,14 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "_lib", "libpdg.so")
 
 PDG_OK, PDG_EINVAL, PDG_EUNSUPPORTED, PDG_ENOTDAG, PDG_ESINGULAR, PDG_ENOMEM, PDG_EDEVICE, PDG_ESTATE = range(8)
-PDG_FP64, PDG_FP32, PDG_FP32_REFINE = 0, 1, 2
+PDG_FP64, PDG_FP32, PDG_FP32_REFINE, PDG_FP32_REFINE_P48 = 0, 1, 2, 3
+# bytes of one state value per precision (the 48-bit state: a binary32 plane, then an int16 plane)
+STATE_BYTES = {PDG_FP64: 8, PDG_FP32: 4, PDG_FP32_REFINE: 8, PDG_FP32_REFINE_P48: 6}
 PDG_FEQ_ADVECTION, PDG_FEQ_EULER, PDG_FEQ_D2Q9 = 0, 1, 2
 PDG_LIE, PDG_STRANG, PDG_STRANG_COLLAPSED, PDG_KIN, PDG_KIN4 = 0, 1, 2, 3, 4
 
 EXPORTED = ("pdg_setup_mesh", "pdg_layout", "pdg_node_coords", "pdg_levels", "pdg_topo_levels", "pdg_line_operator", "pdg_cell_operator",
-            "pdg_prepare", "pdg_equilibrium", "pdg_inflow_equilibrium", "pdg_transport_sweep",
+            "pdg_prepare", "pdg_equilibrium", "pdg_state_to_f64", "pdg_state_from_f64", "pdg_inflow_equilibrium", "pdg_transport_sweep",
             "pdg_relax", "pdg_source", "pdg_step", "pdg_autotune", "pdg_get_tiles", "pdg_set_tiles", "pdg_last_refine_correction", "pdg_sync_status", "pdg_status_string", "pdg_error_detail", "pdg_destroy")
 
 
@@ -61,6 +63,8 @@ def _load():
         "pdg_cell_operator": (i32, [p, i32, i32, p, p]),
         "pdg_prepare": (i32, [p, d, d, d, i32, i32, p]),
         "pdg_equilibrium": (i32, [p, p, p, p]),
+        "pdg_state_to_f64": (i32, [p, p, p, p]),
+        "pdg_state_from_f64": (i32, [p, p, p, p]),
         "pdg_inflow_equilibrium": (i32, [p, p, p, p]),
         "pdg_transport_sweep": (i32, [p, p, p, p, d, p]),
         "pdg_relax": (i32, [p, p, p, p]),
@@ -195,6 +199,14 @@ def pdg_equilibrium(ctx, w, f, stream=None):
     _check(_lib.pdg_equilibrium(ctx, _ptr(w), _ptr(f), _stream(stream)), "pdg_equilibrium")
 
 
+def pdg_state_to_f64(ctx, f, x, stream=None):
+    _check(_lib.pdg_state_to_f64(ctx, _ptr(f), _ptr(x), _stream(stream)), "pdg_state_to_f64")
+
+
+def pdg_state_from_f64(ctx, x, f, stream=None):
+    _check(_lib.pdg_state_from_f64(ctx, _ptr(x), _ptr(f), _stream(stream)), "pdg_state_from_f64")
+
+
 def pdg_inflow_equilibrium(ctx, w_inflow, fb, stream=None):
     _check(_lib.pdg_inflow_equilibrium(ctx, _ptr(w_inflow), _ptr(fb), _stream(stream)), "pdg_inflow_equilibrium")
 
@@ -292,6 +304,27 @@ class Problem:
 
     def equilibrium(self, w, f, stream=None):
         pdg_equilibrium(self.ctx, w, f, stream)
+
+    def new_state(self):
+        """An uninitialised device buffer for f in the prepared precision
+        (binary64 / binary32 elements; for the 48-bit state, 6 bytes per value
+        as int16 triples holding the binary32 plane and then the int16 plane)."""
+        import torch
+        n = self.layout["f_elems"]
+        if self.precision == PDG_FP32_REFINE_P48:
+            return torch.empty(3 * n, dtype=torch.int16, device="cuda")
+        return torch.empty(n, dtype=torch.float32 if self.precision == PDG_FP32 else torch.float64, device="cuda")
+
+    def state_to_f64(self, f, x=None, stream=None):
+        """Binary64 copy of the state (x: optional device float64 tensor)."""
+        import torch
+        if x is None:
+            x = torch.empty(self.layout["f_elems"], dtype=torch.float64, device="cuda")
+        pdg_state_to_f64(self.ctx, f, x, stream)
+        return x
+
+    def state_from_f64(self, x, f, stream=None):
+        pdg_state_from_f64(self.ctx, x, f, stream)
 
     def inflow_equilibrium(self, w_inflow, fb, stream=None):
         pdg_inflow_equilibrium(self.ctx, w_inflow, fb, stream)

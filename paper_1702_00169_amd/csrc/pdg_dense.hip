@@ -54,7 +54,7 @@ __global__ __launch_bounds__(kDenseThreads) void dense_invert_kernel(double *tab
       for (int i = col + 1; i < n; ++i)
         if (fabs(a[i][col]) > fabs(a[pv][col])) pv = i;
       piv = pv;
-      if (!(fabs(a[pv][col]) > 1e-300 * norm)) sing = 1;
+      if (!(fabs(a[pv][col]) > kSingularPivot * norm)) sing = 1;
     }
     __syncthreads();
     if (sing) break;
@@ -152,7 +152,7 @@ __device__ __forceinline__ void dense_local_solve(const double *row, const typen
                                                   typename Pol<PREC>::Rt (&y)[N]) {
   using Rt = typename Pol<PREC>::Rt;
   const DenseRowLayout L{N, F};
-  if (PREC == kRefine) {
+  if (refine_prec(PREC)) {
     double r[N];
     float r32[N], y1[N];
 #pragma unroll
@@ -228,16 +228,25 @@ __device__ inline uint64_t dense_peek_trace(uint64_t *p) {
   return cur;
 }
 
+// Report a failure of the dense sweep (code 1: a wait gave up, 2: a claim
+// past the last tile) on the device flag and, if there is one, on the
+// host-visible flag.
+__device__ inline void dense_fail(const DenseErr &err, int code) {
+  __hip_atomic_fetch_or(err.dev, code, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  if (err.host) __hip_atomic_fetch_or(err.host, code, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+}
+
 // The inflow traces a cell needs from upwind tiles (up to one face per axis,
 // at traces + src[a]; src[a] < 0 where the face is not fed by a tile).
 // Every slot is requested at once, so a ready face costs one round trip; the
 // slots still empty are polled again after a short sleep.  The producer was
 // claimed earlier and is resident, so the wait ends; the wall-clock bound
-// (1 s at the 100 MHz constant clock) and the shared error flag turn a logic
-// error into one reported failure instead of a hang.
+// (err.wait_ticks of the 100 MHz constant clock, 1 s by default) and the
+// shared error flag turn a logic error into one reported failure instead of
+// a hang.
 template <int DIM, int F>
 __device__ inline void dense_take_faces(uint64_t *traces, const int64_t (&src)[DIM], uint64_t (&b)[DIM][F],
-                                        int32_t *err_flag) {
+                                        const DenseErr &err) {
   bool ready = true;
 #pragma unroll
   for (int a = 0; a < DIM; ++a)
@@ -268,9 +277,9 @@ __device__ inline void dense_take_faces(uint64_t *traces, const int64_t (&src)[D
 #pragma unroll
         for (int tt = 0; tt < F; ++tt) ready = ready && b[a][tt] != kDenseTraceEmpty;
     if (ready) return;
-    if (wall_clock64() - t_start > 100000000ull ||
-        __hip_atomic_load(err_flag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0) {
-      __hip_atomic_fetch_or(err_flag, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    if (wall_clock64() - t_start > err.wait_ticks ||
+        __hip_atomic_load(err.dev, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0) {
+      dense_fail(err, 1);
 #pragma unroll
       for (int a = 0; a < DIM; ++a)
 #pragma unroll
@@ -304,10 +313,9 @@ template <int PREC, int NP, int DIM, bool LEVEL>
 __global__ __launch_bounds__(kDenseThreads) void dense_sweep_kernel(
     const DenseTile *__restrict__ tiles, const int32_t *__restrict__ order, const DenseFam *__restrict__ fams,
     const DenseDesc *__restrict__ descs, const double *__restrict__ table, int dt_idx,
-    typename Pol<PREC>::St *__restrict__ f, const double *__restrict__ fb_old, const double *__restrict__ fb_new,
-    uint64_t *traces, int32_t *counter, int32_t *err_flag, int n_tiles) {
+    const State<PREC> f, const double *__restrict__ fb_old, const double *__restrict__ fb_new,
+    uint64_t *traces, int32_t *counter, const DenseErr err, int n_tiles) {
   static_assert(kDenseThreads == 64, "one workgroup is one wave");
-  using St = typename Pol<PREC>::St;
   using Rt = typename Pol<PREC>::Rt;
   constexpr int N = DIM == 2 ? NP * NP : NP * NP * NP;
   constexpr int F = DIM == 2 ? NP : NP * NP;
@@ -319,7 +327,7 @@ __global__ __launch_bounds__(kDenseThreads) void dense_sweep_kernel(
     if (t == 0) claim = atomicAdd(counter, 1);
     claim = __builtin_amdgcn_readfirstlane(claim);
     if (claim >= n_tiles) {  // the counter was not reset: report, do nothing
-      if (t == 0) __hip_atomic_fetch_or(err_flag, 2, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      if (t == 0) dense_fail(err, 2);
       return;
     }
   }
@@ -363,7 +371,7 @@ __global__ __launch_bounds__(kDenseThreads) void dense_sweep_kernel(
     for (int e = t; e < N * F; e += kDenseThreads) gl[a][e / F][e % F] = (Rt)row[L.g(a) + e];
   Rt fv[N], y[N];
 #pragma unroll
-  for (int q = 0; q < N; ++q) fv[q] = active ? (Rt)ld_state(f + fm.f_base + d.plane_off[q] + cell) : (Rt)0;
+  for (int q = 0; q < N; ++q) fv[q] = active ? f.ld(fm.f_base + d.plane_off[q] + cell) : (Rt)0;
   const Rt th = (Rt)d.theta;
   const Rt omt = (Rt)1 - th;
 
@@ -514,7 +522,7 @@ __global__ __launch_bounds__(kDenseThreads) void dense_sweep_kernel(
           if (rsrc[a] >= 0)
 #pragma unroll
             for (int tt = 0; tt < F; ++tt) ready = ready && cur[a][tt] != kDenseTraceEmpty;
-        if (!ready) dense_take_faces<DIM, F>(traces, rsrc, cur, err_flag);
+        if (!ready) dense_take_faces<DIM, F>(traces, rsrc, cur, err);
 #pragma unroll
         for (int a = 0; a < DIM; ++a)
           if (rsrc[a] >= 0)
@@ -523,7 +531,7 @@ __global__ __launch_bounds__(kDenseThreads) void dense_sweep_kernel(
       } else if constexpr (!LEVEL) {
         // no ring: request and wait now
         uint64_t rb[DIM][F];
-        dense_take_faces<DIM, F>(traces, rsrc, rb, err_flag);
+        dense_take_faces<DIM, F>(traces, rsrc, rb, err);
 #pragma unroll
         for (int a = 0; a < DIM; ++a)
           if (rsrc[a] >= 0)
@@ -591,7 +599,7 @@ __global__ __launch_bounds__(kDenseThreads) void dense_sweep_kernel(
       for (int tt = 0; tt < F; ++tt) y[q] = fma(gl[a][q][tt], uin[a][tt], y[q]);
   }
 #pragma unroll
-  for (int q = 0; q < N; ++q) st_state(f + fm.f_base + d.plane_off[q] + cell, (St)y[q]);
+  for (int q = 0; q < N; ++q) f.st(fm.f_base + d.plane_off[q] + cell, y[q]);
 }
 
 }  // namespace
@@ -608,25 +616,24 @@ hipError_t launch_dense_invert(double *table, const int64_t *row_off, const Dens
 
 template <int PREC, int NP, int DIM>
 hipError_t go_dense(bool level, const DenseTile *tiles, const int32_t *order, int n_tiles, const DenseFam *fams,
-                    const DenseDesc *descs, const double *table, int dt_idx, void *f, const double *fb_old,
-                    const double *fb_new, uint64_t *traces, int32_t *counter, int32_t *err, hipStream_t st) {
-  using St = typename Pol<PREC>::St;
+                    const DenseDesc *descs, const double *table, int dt_idx, StateBuf f, const double *fb_old,
+                    const double *fb_new, uint64_t *traces, int32_t *counter, DenseErr err, hipStream_t st) {
   if (level)
     hipLaunchKernelGGL((dense_sweep_kernel<PREC, NP, DIM, true>), dim3(n_tiles), dim3(kDenseThreads), 0, st, tiles,
-                       order, fams, descs, table, dt_idx, static_cast<St *>(f), fb_old, fb_new, traces, counter, err,
+                       order, fams, descs, table, dt_idx, State<PREC>::make(f), fb_old, fb_new, traces, counter, err,
                        n_tiles);
   else
     hipLaunchKernelGGL((dense_sweep_kernel<PREC, NP, DIM, false>), dim3(n_tiles), dim3(kDenseThreads), 0, st, tiles,
-                       order, fams, descs, table, dt_idx, static_cast<St *>(f), fb_old, fb_new, traces, counter, err,
+                       order, fams, descs, table, dt_idx, State<PREC>::make(f), fb_old, fb_new, traces, counter, err,
                        n_tiles);
   return hipGetLastError();
 }
 
 template <int PREC>
 hipError_t go_dense_shape(bool level, int np, int dim, const DenseTile *tiles, const int32_t *order, int n_tiles,
-                          const DenseFam *fams, const DenseDesc *descs, const double *table, int dt_idx, void *f,
+                          const DenseFam *fams, const DenseDesc *descs, const double *table, int dt_idx, StateBuf f,
                           const double *fb_old, const double *fb_new, uint64_t *traces, int32_t *counter,
-                          int32_t *err, hipStream_t st) {
+                          DenseErr err, hipStream_t st) {
 #define PDG_DENSE_CASE(NPV, DIMV)                                                                             \
   if (np == NPV && dim == DIMV)                                                                               \
     return go_dense<PREC, NPV, DIMV>(level, tiles, order, n_tiles, fams, descs, table, dt_idx, f, fb_old, fb_new,   \
@@ -643,13 +650,14 @@ hipError_t go_dense_shape(bool level, int np, int dim, const DenseTile *tiles, c
 
 hipError_t launch_dense_sweep(int prec, bool level, int np, int dim, const DenseTile *tiles, const int32_t *order,
                               int n_tiles, const DenseFam *fams, const DenseDesc *descs, const double *table,
-                              int dt_idx, void *f, const double *fb_old, const double *fb_new, uint64_t *traces,
-                              int32_t *counter, int32_t *err_flag, hipStream_t st) {
+                              int dt_idx, StateBuf f, const double *fb_old, const double *fb_new, uint64_t *traces,
+                              int32_t *counter, DenseErr err_flag, hipStream_t st) {
   if (n_tiles <= 0) return hipSuccess;
   switch (prec) {
     case kF64: return go_dense_shape<kF64>(level, np, dim, tiles, order, n_tiles, fams, descs, table, dt_idx, f, fb_old, fb_new, traces, counter, err_flag, st);
     case kF32: return go_dense_shape<kF32>(level, np, dim, tiles, order, n_tiles, fams, descs, table, dt_idx, f, fb_old, fb_new, traces, counter, err_flag, st);
     case kRefine: return go_dense_shape<kRefine>(level, np, dim, tiles, order, n_tiles, fams, descs, table, dt_idx, f, fb_old, fb_new, traces, counter, err_flag, st);
+    case kP48: return go_dense_shape<kP48>(level, np, dim, tiles, order, n_tiles, fams, descs, table, dt_idx, f, fb_old, fb_new, traces, counter, err_flag, st);
     default: return hipErrorInvalidValue;
   }
 }

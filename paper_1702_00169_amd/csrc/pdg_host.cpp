@@ -19,6 +19,7 @@
 #include <cstdlib>
 #include <cstring>
 #include <map>
+#include <memory>
 #include <new>
 #include <string>
 #include <vector>
@@ -29,6 +30,7 @@
 using namespace pdg;
 
 namespace {
+
 
 struct Instance {
   pdg_instance_desc d;
@@ -146,12 +148,16 @@ struct pdg_ctx {
   DevBuf<int32_t> dsync;     // per group: tile-claim counter
   bool dense_claim = false;   // some dense group uses claimed tiles (their slots are reset per sweep)
   DevBuf<int32_t> derr;      // 1: a trace wait timed out, 2: claim counter overrun
+  int32_t *herr = nullptr;   // host-visible copy of derr's codes (pinned, mapped)
+  int32_t *herr_dev = nullptr;
+  uint64_t wait_ticks = 100000000ull;  // dense trace wait bound (100 MHz ticks)
   DevBuf<RelaxDesc> rdesc;
   DevBuf<RelaxItem> ritems;
   std::vector<RelaxGroup> rgroups;
   DevBuf<InflowDesc> idesc;
   std::vector<RelaxGroup> igroups;  // (nv, m, first, count) over idesc
   DevBuf<double> stats;             // 2 doubles per sweep workgroup
+  const double *last_stats = nullptr;  // statistics written by the most recent sweep
   hipStream_t cap_stream = nullptr;
   // graph cache of the interior step
   hipGraphExec_t gexec = nullptr;
@@ -179,6 +185,9 @@ struct pdg_ctx {
     dtraces.release();
     dsync.release();
     derr.release();
+    if (herr) (void)hipHostFree(herr);
+    herr = nullptr;
+    herr_dev = nullptr;
     dgroups.clear();
     stats.release();
     if (cap_stream) (void)hipStreamDestroy(cap_stream);
@@ -502,7 +511,7 @@ const char *pdg_status_string(pdg_status s) {
   return "PDG_UNKNOWN";
 }
 
-pdg_status pdg_topo_levels(int32_t n_nodes, int64_t n_edges, const int32_t *src, const int32_t *dst,
+static pdg_status topo_levels_impl(int32_t n_nodes, int64_t n_edges, const int32_t *src, const int32_t *dst,
                            int32_t *level) {
   if (n_nodes < 0 || n_edges < 0 || !level || (n_edges > 0 && (!src || !dst))) return PDG_EINVAL;
   std::vector<int32_t> indeg(n_nodes, 0);
@@ -536,10 +545,10 @@ pdg_status pdg_topo_levels(int32_t n_nodes, int64_t n_edges, const int32_t *src,
   return done == n_nodes ? PDG_OK : PDG_ENOTDAG;
 }
 
-pdg_status pdg_setup_mesh(const pdg_instance_desc *descs, int32_t n_inst, pdg_ctx **out) {
+static pdg_status setup_mesh_impl(const pdg_instance_desc *descs, int32_t n_inst, pdg_ctx **out) {
   if (!descs || n_inst <= 0 || !out) return PDG_EINVAL;
-  pdg_ctx *c = new (std::nothrow) pdg_ctx();
-  if (!c) return PDG_ENOMEM;
+  // owned here until handed to the caller (also on a std::bad_alloc)
+  std::unique_ptr<pdg_ctx> c(new pdg_ctx());
   int64_t f_off = 0, w_off = 0, fb_off = 0;
   for (int32_t i = 0; i < n_inst; ++i) {
     const pdg_instance_desc &d = descs[i];
@@ -563,8 +572,7 @@ pdg_status pdg_setup_mesh(const pdg_instance_desc *descs, int32_t n_inst, pdg_ct
       }
     }
     if (err != PDG_OK) {
-      delete c;
-      return err;
+            return err;
     }
     in.d.v = nullptr;
     for (int k = 0; k < 3; ++k) {
@@ -579,8 +587,7 @@ pdg_status pdg_setup_mesh(const pdg_instance_desc *descs, int32_t n_inst, pdg_ct
     in.v.assign(d.v, d.v + (size_t)d.nv * d.dim);
     for (double x : in.v)
       if (!is_finite(x)) {
-        delete c;
-        return PDG_EINVAL;
+                return PDG_EINVAL;
       }
     in.nw = d.m;
     if (d.feq == PDG_FEQ_D2Q9) {
@@ -604,8 +611,7 @@ pdg_status pdg_setup_mesh(const pdg_instance_desc *descs, int32_t n_inst, pdg_ct
         for (int b = 0; b < 3; ++b)
           if (seen[a][b] != 1) ok = false;
       if (!ok || !(lam > 0.0) || !is_finite(d.feq_param[0])) {
-        delete c;
-        return PDG_EINVAL;
+                return PDG_EINVAL;
       }
       in.lat_lambda = lam;
       in.nw = 3;
@@ -622,8 +628,7 @@ pdg_status pdg_setup_mesh(const pdg_instance_desc *descs, int32_t n_inst, pdg_ct
       in.nc *= in.n[k];
     }
     if (in.nc > (int64_t)1 << 31) {
-      delete c;
-      return PDG_EUNSUPPORTED;
+            return PDG_EUNSUPPORTED;
     }
     in.axis.assign(d.nv, -1);
     in.sign.assign(d.nv, 0);
@@ -656,8 +661,7 @@ pdg_status pdg_setup_mesh(const pdg_instance_desc *descs, int32_t n_inst, pdg_ct
       std::vector<int32_t> lev;
       pdg_status s = mesh_levels(in, v, lev);
       if (s != PDG_OK) {
-        delete c;
-        return s;
+                return s;
       }
       if (nz == 1) {
         // chains: the level of a cell is its downwind position along the axis
@@ -666,8 +670,7 @@ pdg_status pdg_setup_mesh(const pdg_instance_desc *descs, int32_t n_inst, pdg_ct
           int64_t pos = (cc / stride) % in.n[ax];
           int64_t want = in.sign[v] > 0 ? pos : in.n[ax] - 1 - pos;
           if (lev[cc] != want) {
-            delete c;
-            return PDG_EDEVICE;  // internal inconsistency
+                        return PDG_EDEVICE;  // internal inconsistency
           }
         }
       }
@@ -684,7 +687,7 @@ pdg_status pdg_setup_mesh(const pdg_instance_desc *descs, int32_t n_inst, pdg_ct
   c->f_elems = f_off;
   c->w_elems = w_off;
   c->fb_elems = fb_off;
-  *out = c;
+  *out = c.release();
   return PDG_OK;
 }
 
@@ -703,7 +706,7 @@ pdg_status pdg_layout(const pdg_ctx *c, int64_t *f_elems, int64_t *w_elems, int6
   return PDG_OK;
 }
 
-pdg_status pdg_node_coords(const pdg_ctx *c, int32_t inst, double *vol_xyz, double *inflow_xyz) {
+static pdg_status node_coords_impl(const pdg_ctx *c, int32_t inst, double *vol_xyz, double *inflow_xyz) {
   if (!c || inst < 0 || inst >= (int32_t)c->inst.size()) return PDG_EINVAL;
   const Instance &in = c->inst[inst];
   const int dim = in.d.dim;
@@ -759,7 +762,7 @@ pdg_status pdg_node_coords(const pdg_ctx *c, int32_t inst, double *vol_xyz, doub
   return PDG_OK;
 }
 
-pdg_status pdg_levels(const pdg_ctx *c, int32_t inst, int32_t vel, int32_t *level) {
+static pdg_status levels_impl(const pdg_ctx *c, int32_t inst, int32_t vel, int32_t *level) {
   if (!c || !level || inst < 0 || inst >= (int32_t)c->inst.size()) return PDG_EINVAL;
   const Instance &in = c->inst[inst];
   if (vel < 0 || vel >= in.d.nv) return PDG_EINVAL;
@@ -798,13 +801,13 @@ pdg_status pdg_cell_operator(const pdg_ctx *c, int32_t inst, int32_t vel, double
   return PDG_OK;
 }
 
-pdg_status pdg_prepare(pdg_ctx *c, double dt, double theta, double omega, pdg_scheme scheme, pdg_precision prec,
+static pdg_status prepare_impl(pdg_ctx *c, double dt, double theta, double omega, pdg_scheme scheme, pdg_precision prec,
                        void *stream) {
   if (!c) return PDG_EINVAL;
   if (!is_finite(dt) || dt == 0.0 || !is_finite(theta) || !(theta > 0.0) || theta > 1.0 || !is_finite(omega))
     return PDG_EINVAL;
   if (scheme < PDG_LIE || scheme > PDG_KIN4) return PDG_EINVAL;
-  if (prec < PDG_FP64 || prec > PDG_FP32_REFINE) return PDG_EINVAL;
+  if (prec < PDG_FP64 || prec > PDG_FP32_REFINE_P48) return PDG_EINVAL;
   for (const Instance &in : c->inst)
     for (int v = 0; v < in.d.nv; ++v) {
       if (in.ndep[v] >= 2 && in.nd > kDenseMaxN) return PDG_EUNSUPPORTED;
@@ -1254,6 +1257,15 @@ pdg_status pdg_prepare(pdg_ctx *c, double dt, double theta, double omega, pdg_sc
   PREP_TRY(c->dtraces.upload(std::vector<uint64_t>((size_t)trace_total, kDenseTraceEmpty)))
   PREP_TRY(c->dsync.upload(std::vector<int32_t>((size_t)sync_total, 0)))
   PREP_TRY(c->derr.upload(std::vector<int32_t>(1, 0)))
+  PREP_TRY(hipHostMalloc(reinterpret_cast<void **>(&c->herr), sizeof(int32_t), hipHostMallocMapped))
+  *c->herr = 0;
+  PREP_TRY(hipHostGetDevicePointer(reinterpret_cast<void **>(&c->herr_dev), c->herr, 0))
+  {
+    // the dense trace wait bound; PDG_DENSE_WAIT_TICKS overrides it (tests of
+    // the failure report use a bound of zero ticks)
+    const char *wt = std::getenv("PDG_DENSE_WAIT_TICKS");
+    c->wait_ticks = wt ? std::strtoull(wt, nullptr, 10) : 100000000ull;
+  }
   if (!drow_off.empty()) {
     std::map<std::pair<int, int>, std::vector<size_t>> rows_by_shape;
     for (size_t r = 0; r < drow_off.size(); ++r) {
@@ -1329,11 +1341,33 @@ pdg_status pdg_prepare(pdg_ctx *c, double dt, double theta, double omega, pdg_sc
 
 namespace {
 
+DenseErr dense_err(const pdg_ctx *c) { return DenseErr{c->derr.p, c->herr_dev, c->wait_ticks}; }
+
+// A dense-sweep failure already reported by a finished kernel (host-visible
+// flag, read without synchronising): the state is invalid until the caller
+// has seen it through pdg_sync_status, so the entry points refuse to go on.
+bool dense_failed(const pdg_ctx *c) {
+  if (!c->herr || *static_cast<volatile const int32_t *>(c->herr) == 0) return false;
+  std::snprintf(g_detail, sizeof(g_detail), "%s",
+                "dense sweep: an earlier sweep reported a failed trace wait; call pdg_sync_status");
+  return true;
+}
+
+// Device scratch of one sweep: per-workgroup refinement statistics (2 doubles
+// per work item), the dense inflow-trace slots and the tile-claim counters.
+struct SweepScratch {
+  double *stats;
+  uint64_t *traces;
+  int32_t *sync;
+};
+
+SweepScratch ctx_scratch(pdg_ctx *c) { return SweepScratch{c->stats.p, c->dtraces.p, c->dsync.p}; }
+
 pdg_status do_sweep(pdg_ctx *c, void *f, const double *fb_old, const double *fb_new, int dt_idx,
-                    hipStream_t st) {
+                    hipStream_t st, const SweepScratch &sc) {
   for (const Group &g : c->groups) {
-    hipError_t e = launch_sweep(c->prec, g.np, g.graded, g.wpos, c->sitems.p + g.first, (int)g.count, c->sdesc.p, c->ops.p, dt_idx, f,
-                                fb_old, fb_new, c->stats.p + 2 * g.first, st);
+    hipError_t e = launch_sweep(c->prec, g.np, g.graded, g.wpos, c->sitems.p + g.first, (int)g.count, c->sdesc.p, c->ops.p, dt_idx, StateBuf{f, c->f_elems},
+                                fb_old, fb_new, sc.stats + 2 * g.first, st);
     if (e != hipSuccess) {
       char what[96];
       std::snprintf(what, sizeof(what), "launch_sweep(np=%d,items=%lld)", g.np, (long long)g.count);
@@ -1343,8 +1377,8 @@ pdg_status do_sweep(pdg_ctx *c, void *f, const double *fb_old, const double *fb_
   if (c->dense_claim) {
     // every trace slot empty, every claim counter at zero (fill kernels, so
     // that the sequence can be captured into a graph)
-    hipError_t e = launch_fill_u64(c->dtraces.p, c->dtraces.n, kDenseTraceEmpty, st);
-    if (e == hipSuccess) e = launch_fill_int(c->dsync.p, (int64_t)c->dgroups.size(), 0, st);
+    hipError_t e = launch_fill_u64(sc.traces, c->dtraces.n, kDenseTraceEmpty, st);
+    if (e == hipSuccess) e = launch_fill_int(sc.sync, (int64_t)c->dgroups.size(), 0, st);
     if (e != hipSuccess) return from_hip_at(e, "dense sweep reset");
   }
   for (const DenseGroup &g : c->dgroups) {
@@ -1353,18 +1387,19 @@ pdg_status do_sweep(pdg_ctx *c, void *f, const double *fb_old, const double *fb_
       for (size_t k = 0; k + 1 < g.level.size(); ++k) {
         hipError_t e = launch_dense_sweep(c->prec, true, g.np, g.dim, c->dtiles.p + g.first,
                                           c->dorder.p + g.first + g.level[k], (int)(g.level[k + 1] - g.level[k]),
-                                          c->dfams.p, c->ddesc.p, c->dtable.p, dt_idx, f, fb_old, fb_new,
-                                          c->dtraces.p, c->dsync.p + g.sync_off, c->derr.p, st);
+                                          c->dfams.p, c->ddesc.p, c->dtable.p, dt_idx, StateBuf{f, c->f_elems}, fb_old, fb_new,
+                                          sc.traces, sc.sync + g.sync_off, dense_err(c), st);
         if (e != hipSuccess) return from_hip_at(e, "launch_dense_sweep(level)");
       }
       continue;
     }
     hipError_t e = launch_dense_sweep(c->prec, false, g.np, g.dim, c->dtiles.p + g.first, c->dorder.p + g.first,
-                                      (int)g.count, c->dfams.p, c->ddesc.p, c->dtable.p, dt_idx, f, fb_old, fb_new,
-                                      c->dtraces.p, c->dsync.p + g.sync_off, c->derr.p, st);
+                                      (int)g.count, c->dfams.p, c->ddesc.p, c->dtable.p, dt_idx, StateBuf{f, c->f_elems}, fb_old, fb_new,
+                                      sc.traces, sc.sync + g.sync_off, dense_err(c), st);
     if (e != hipSuccess) return from_hip_at(e, "launch_dense_sweep");
   }
-  c->stats_valid = c->prec == PDG_FP32_REFINE;
+  c->stats_valid = c->prec == PDG_FP32_REFINE || c->prec == PDG_FP32_REFINE_P48;
+  c->last_stats = sc.stats;
   c->last_stream = st;
   return PDG_OK;
 }
@@ -1378,12 +1413,12 @@ pdg_status do_local(pdg_ctx *c, void *f, double *w_out, double omega, double h_p
   for (const RelaxGroup &g : c->rgroups) {
     hipError_t e;
     if (g.lattice)
-      e = launch_lattice(c->prec, c->ritems.p + g.first, (int)g.count, c->rdesc.p, f, w_out, nullptr, omega, h_pre,
+      e = launch_lattice(c->prec, c->ritems.p + g.first, (int)g.count, c->rdesc.p, StateBuf{f, c->f_elems}, w_out, nullptr, omega, h_pre,
                          h_post, 0, st);
     else if (source_only)
       e = hipSuccess;
     else
-      e = launch_relax(c->prec, g.nv, g.m, c->ritems.p + g.first, (int)g.count, c->rdesc.p, f, w_out, nullptr,
+      e = launch_relax(c->prec, g.nv, g.m, c->ritems.p + g.first, (int)g.count, c->rdesc.p, StateBuf{f, c->f_elems}, w_out, nullptr,
                        omega, 0, st);
     if (e != hipSuccess) return from_hip(e);
   }
@@ -1400,7 +1435,7 @@ struct StepOp {
 
 pdg_status run_ops(pdg_ctx *c, const std::vector<StepOp> &ops, void *f, const double *fb, hipStream_t st) {
   for (const StepOp &o : ops) {
-    const pdg_status s = o.kind == 0 ? do_sweep(c, f, fb, fb, o.dt_idx, st)
+    const pdg_status s = o.kind == 0 ? do_sweep(c, f, fb, fb, o.dt_idx, st, ctx_scratch(c))
                                      : do_local(c, f, nullptr, o.omega, o.h_pre, o.h_post, false, st);
     if (s != PDG_OK) return s;
   }
@@ -1415,6 +1450,7 @@ pdg_status pdg_transport_sweep(pdg_ctx *c, void *f, const double *fb_old, const 
                                void *stream) {
   if (!c || !f || (c->fb_elems > 0 && (!fb_old || !fb_new))) return PDG_EINVAL;
   if (!c->prepared) return PDG_ESTATE;
+  if (dense_failed(c)) return PDG_EDEVICE;
   int dt_idx = -1;
   for (size_t i = 0; i < c->dts.size(); ++i)
     if (dt_sub == c->dts[i]) {
@@ -1422,18 +1458,20 @@ pdg_status pdg_transport_sweep(pdg_ctx *c, void *f, const double *fb_old, const 
       break;
     }
   if (dt_idx < 0) return PDG_ESTATE;
-  return do_sweep(c, f, fb_old, fb_new, dt_idx, static_cast<hipStream_t>(stream));
+  return do_sweep(c, f, fb_old, fb_new, dt_idx, static_cast<hipStream_t>(stream), ctx_scratch(c));
 }
 
 pdg_status pdg_relax(pdg_ctx *c, void *f, double *w_out, void *stream) {
   if (!c || !f) return PDG_EINVAL;
   if (!c->prepared) return PDG_ESTATE;
+  if (dense_failed(c)) return PDG_EDEVICE;
   return do_local(c, f, w_out, c->omega, 0.0, 0.0, false, static_cast<hipStream_t>(stream));
 }
 
 pdg_status pdg_source(pdg_ctx *c, void *f, double h, void *stream) {
   if (!c || !f || !is_finite(h)) return PDG_EINVAL;
   if (!c->prepared) return PDG_ESTATE;
+  if (dense_failed(c)) return PDG_EDEVICE;
   if (h == 0.0) return PDG_OK;
   return do_local(c, f, nullptr, 0.0, h, 0.0, true, static_cast<hipStream_t>(stream));
 }
@@ -1443,13 +1481,29 @@ pdg_status pdg_equilibrium(pdg_ctx *c, const double *w, void *f, void *stream) {
   if (!c->prepared) return PDG_ESTATE;
   if (c->rgroups.empty()) return PDG_EUNSUPPORTED;
   for (const RelaxGroup &g : c->rgroups) {
-    hipError_t e = g.lattice ? launch_lattice(c->prec, c->ritems.p + g.first, (int)g.count, c->rdesc.p, f, nullptr,
+    hipError_t e = g.lattice ? launch_lattice(c->prec, c->ritems.p + g.first, (int)g.count, c->rdesc.p, StateBuf{f, c->f_elems}, nullptr,
                                               w, 1.0, 0.0, 0.0, 1, static_cast<hipStream_t>(stream))
-                             : launch_relax(c->prec, g.nv, g.m, c->ritems.p + g.first, (int)g.count, c->rdesc.p, f,
+                             : launch_relax(c->prec, g.nv, g.m, c->ritems.p + g.first, (int)g.count, c->rdesc.p, StateBuf{f, c->f_elems},
                                             nullptr, w, 1.0, 1, static_cast<hipStream_t>(stream));
     if (e != hipSuccess) return from_hip(e);
   }
   return PDG_OK;
+}
+
+pdg_status pdg_state_to_f64(pdg_ctx *c, const void *f, double *x, void *stream) {
+  if (!c || !f || !x) return PDG_EINVAL;
+  if (!c->prepared) return PDG_ESTATE;
+  const hipError_t e = launch_convert(c->prec, StateBuf{const_cast<void *>(f), c->f_elems}, x, true,
+                                      static_cast<hipStream_t>(stream));
+  return e == hipSuccess ? PDG_OK : from_hip_at(e, "launch_convert");
+}
+
+pdg_status pdg_state_from_f64(pdg_ctx *c, const double *x, void *f, void *stream) {
+  if (!c || !f || !x) return PDG_EINVAL;
+  if (!c->prepared) return PDG_ESTATE;
+  const hipError_t e = launch_convert(c->prec, StateBuf{f, c->f_elems}, const_cast<double *>(x), false,
+                                      static_cast<hipStream_t>(stream));
+  return e == hipSuccess ? PDG_OK : from_hip_at(e, "launch_convert");
 }
 
 pdg_status pdg_inflow_equilibrium(pdg_ctx *c, const double *w_inflow, double *fb, void *stream) {
@@ -1466,10 +1520,11 @@ pdg_status pdg_inflow_equilibrium(pdg_ctx *c, const double *w_inflow, double *fb
   return PDG_OK;
 }
 
-pdg_status pdg_step(pdg_ctx *c, void *f, const double *fb, int32_t n_steps, void *stream) {
+static pdg_status step_impl(pdg_ctx *c, void *f, const double *fb, int32_t n_steps, void *stream) {
   if (!c || !f || n_steps < 0 || (c->fb_elems > 0 && !fb)) return PDG_EINVAL;
   if (!c->prepared) return PDG_ESTATE;
   if (c->rgroups.empty()) return PDG_EUNSUPPORTED;
+  if (dense_failed(c)) return PDG_EDEVICE;
   if (n_steps == 0) return PDG_OK;
   hipStream_t st = static_cast<hipStream_t>(stream);
   // prologue, interior (repeated), epilogue: sweeps by sub-step index, relaxations by omega
@@ -1548,7 +1603,8 @@ pdg_status pdg_step(pdg_ctx *c, void *f, const double *fb, int32_t n_steps, void
         return s;
       }
     }
-    c->stats_valid = c->prec == PDG_FP32_REFINE;
+    c->stats_valid = c->prec == PDG_FP32_REFINE || c->prec == PDG_FP32_REFINE_P48;
+    c->last_stats = c->stats.p;
     c->last_stream = st;
   }
   return run_ops(c, epi, f, fb, st);
@@ -1581,9 +1637,10 @@ bool tile_valid(const LaunchClass &k, int C, int S) {
 
 }  // namespace
 
-pdg_status pdg_autotune(pdg_ctx *c, void *f, const double *fb, int32_t reps, void *stream) {
+static pdg_status autotune_impl(pdg_ctx *c, void *f, const double *fb, int32_t reps, void *stream) {
   if (!c || !f || (c->fb_elems > 0 && !fb) || reps < 1) return PDG_EINVAL;
   if (!c->prepared) return PDG_ESTATE;
+  c->stats_valid = false;  // the work items change below
   hipStream_t st = static_cast<hipStream_t>(stream);
   hipEvent_t e0 = nullptr, e1 = nullptr;
   HIP_TRY(hipEventCreate(&e0));
@@ -1612,7 +1669,7 @@ pdg_status pdg_autotune(pdg_ctx *c, void *f, const double *fb, int32_t reps, voi
       for (int r = 0; r <= reps && e == hipSuccess; ++r) {
         if (r == 1) e = hipEventRecord(e0, st);
         if (e == hipSuccess)
-          e = launch_sweep(c->prec, g.np, g.graded, g.wpos, c->sitems.p + k.first, (int)k.count, c->sdesc.p, c->ops.p, 0, f, fb, fb,
+          e = launch_sweep(c->prec, g.np, g.graded, g.wpos, c->sitems.p + k.first, (int)k.count, c->sdesc.p, c->ops.p, 0, StateBuf{f, c->f_elems}, fb, fb,
                            c->stats.p + 2 * k.first, st);
       }
       if (e == hipSuccess) e = hipEventRecord(e1, st);
@@ -1654,7 +1711,7 @@ pdg_status pdg_get_tiles(const pdg_ctx *c, int32_t *n_classes, int32_t *tiles) {
   return PDG_OK;
 }
 
-pdg_status pdg_set_tiles(pdg_ctx *c, int32_t n_classes, const int32_t *tiles) {
+static pdg_status set_tiles_impl(pdg_ctx *c, int32_t n_classes, const int32_t *tiles) {
   if (!c || (n_classes > 0 && !tiles) || n_classes < 0) return PDG_EINVAL;
   if (!c->prepared) return PDG_ESTATE;
   for (int32_t i = 0; i < n_classes; ++i) {
@@ -1677,13 +1734,13 @@ pdg_status pdg_set_tiles(pdg_ctx *c, int32_t n_classes, const int32_t *tiles) {
   return upload_items(c, items);
 }
 
-pdg_status pdg_last_refine_correction(const pdg_ctx *c, double *max_rel_correction) {
+static pdg_status last_refine_correction_impl(const pdg_ctx *c, double *max_rel_correction) {
   if (!c || !max_rel_correction) return PDG_EINVAL;
   if (!c->prepared || !c->stats_valid) return PDG_ESTATE;
   hipError_t e = hipStreamSynchronize(c->last_stream);
   if (e != hipSuccess) return from_hip(e);
-  std::vector<double> h(c->stats.n);
-  e = hipMemcpy(h.data(), c->stats.p, h.size() * sizeof(double), hipMemcpyDeviceToHost);
+  std::vector<double> h(2 * c->sitems.n);
+  e = hipMemcpy(h.data(), c->last_stats, h.size() * sizeof(double), hipMemcpyDeviceToHost);
   if (e != hipSuccess) return from_hip(e);
   double cm = 0.0, ym = 0.0;
   for (size_t i = 0; i + 1 < h.size(); i += 2) {
@@ -1701,6 +1758,7 @@ pdg_status pdg_sync_status(pdg_ctx *c) {
   HIP_TRY(hipGetLastError());
   int32_t err = 0;
   HIP_TRY(hipMemcpy(&err, c->derr.p, sizeof(err), hipMemcpyDeviceToHost));
+  if (c->herr) *c->herr = 0;
   if (err) {
     const int32_t zero = 0;
     HIP_TRY(hipMemcpy(c->derr.p, &zero, sizeof(zero), hipMemcpyHostToDevice));
@@ -1710,6 +1768,82 @@ pdg_status pdg_sync_status(pdg_ctx *c) {
     return PDG_EDEVICE;
   }
   return PDG_OK;
+}
+
+// Host allocation failures (std::bad_alloc) are reported as PDG_ENOMEM; no
+// exception crosses the C ABI.
+pdg_status pdg_topo_levels(int32_t n_nodes, int64_t n_edges, const int32_t *src, const int32_t *dst,
+                           int32_t *level) {
+  try {
+    return topo_levels_impl(n_nodes, n_edges, src, dst, level);
+  } catch (const std::bad_alloc &) {
+    return PDG_ENOMEM;
+  }
+}
+
+pdg_status pdg_setup_mesh(const pdg_instance_desc *descs, int32_t n_inst, pdg_ctx **out) {
+  try {
+    return setup_mesh_impl(descs, n_inst, out);
+  } catch (const std::bad_alloc &) {
+    return PDG_ENOMEM;
+  }
+}
+
+pdg_status pdg_node_coords(const pdg_ctx *c, int32_t inst, double *vol_xyz, double *inflow_xyz) {
+  try {
+    return node_coords_impl(c, inst, vol_xyz, inflow_xyz);
+  } catch (const std::bad_alloc &) {
+    return PDG_ENOMEM;
+  }
+}
+
+pdg_status pdg_levels(const pdg_ctx *c, int32_t inst, int32_t vel, int32_t *level) {
+  try {
+    return levels_impl(c, inst, vel, level);
+  } catch (const std::bad_alloc &) {
+    return PDG_ENOMEM;
+  }
+}
+
+pdg_status pdg_prepare(pdg_ctx *c, double dt, double theta, double omega, pdg_scheme scheme, pdg_precision prec,
+                       void *stream) {
+  try {
+    return prepare_impl(c, dt, theta, omega, scheme, prec, stream);
+  } catch (const std::bad_alloc &) { if (c) c->release_device();
+    return PDG_ENOMEM;
+  }
+}
+
+pdg_status pdg_step(pdg_ctx *c, void *f, const double *fb, int32_t n_steps, void *stream) {
+  try {
+    return step_impl(c, f, fb, n_steps, stream);
+  } catch (const std::bad_alloc &) {
+    return PDG_ENOMEM;
+  }
+}
+
+pdg_status pdg_autotune(pdg_ctx *c, void *f, const double *fb, int32_t reps, void *stream) {
+  try {
+    return autotune_impl(c, f, fb, reps, stream);
+  } catch (const std::bad_alloc &) {
+    return PDG_ENOMEM;
+  }
+}
+
+pdg_status pdg_set_tiles(pdg_ctx *c, int32_t n_classes, const int32_t *tiles) {
+  try {
+    return set_tiles_impl(c, n_classes, tiles);
+  } catch (const std::bad_alloc &) {
+    return PDG_ENOMEM;
+  }
+}
+
+pdg_status pdg_last_refine_correction(const pdg_ctx *c, double *max_rel_correction) {
+  try {
+    return last_refine_correction_impl(c, max_rel_correction);
+  } catch (const std::bad_alloc &) {
+    return PDG_ENOMEM;
+  }
 }
 
 void pdg_destroy(pdg_ctx *c) {

@@ -14,6 +14,11 @@ constexpr int kMaxNP = 5;       // d + 1 for degree <= 4
 constexpr int kBlock = 256;     // threads per workgroup of every kernel
 constexpr int kMaxNV = 27;
 constexpr int kMaxM = 8;
+// A cell block is taken as singular when a Gauss-Jordan pivot (partial
+// pivoting) is at most this fraction of its largest entry: an exactly singular
+// block leaves a pivot of rounding size, and the blocks I + theta dt Gamma
+// of a forward step keep every pivot above 0.2 of the largest entry (d <= 4).
+constexpr double kSingularPivot = 1e-12;
 
 // One (instance, velocity) line family: how a chain (a line of cells along
 // the velocity axis, ordered downwind) is addressed in the state array.
@@ -44,7 +49,10 @@ struct SweepItem {
 };
 
 // Largest segment length compiled for a node count (register budget).
-constexpr int sweep_smax(int np) { return np <= 3 ? 8 : 4; }
+#ifndef PDG_SMAX_LOW
+#define PDG_SMAX_LOW 8   // d + 1 <= 3
+#endif
+constexpr int sweep_smax(int np) { return np <= 3 ? PDG_SMAX_LOW : 4; }
 // Same for chains on graded axes, which also hold each cell's g and a.
 constexpr int sweep_smax_graded(int np) { return np <= 3 ? 4 : 2; }
 // Largest segment length of a launch class (chain kind 2: graded axis).
@@ -151,7 +159,16 @@ struct DenseTile {
 };
 
 // ---- kernel launchers ------------------------------------------------------
-enum Prec { kF64 = 0, kF32 = 1, kRefine = 2 };
+// The state buffer of a launch: its base address and its element count n (the
+// packed kP48 state holds n binary32 values followed by n int16 values).
+struct StateBuf {
+  void *p;
+  int64_t n;
+};
+// kP48: the arithmetic of kRefine with the state stored in 48 bits per value
+// (a binary32 plane, then an int16 plane with the next 16 bits; see State<kP48>).
+enum Prec { kF64 = 0, kF32 = 1, kRefine = 2, kP48 = 3 };
+constexpr bool refine_prec(int p) { return p == kRefine || p == kP48; }
 
 hipError_t launch_invert(OpEntry *ops, int n_ops, hipStream_t st);
 
@@ -159,12 +176,12 @@ hipError_t launch_invert(OpEntry *ops, int n_ops, hipStream_t st);
 // tile shape or instance).  graded: chains on graded axes; wpos: their tile
 // width C is a multiple of 64 (each wave at one chain position).
 hipError_t launch_sweep(int prec, int np, bool graded, bool wpos, const SweepItem *items, int n_items,
-                        const SweepDesc *descs, const OpEntry *ops, int dt_idx, void *f, const double *fb_old,
+                        const SweepDesc *descs, const OpEntry *ops, int dt_idx, StateBuf f, const double *fb_old,
                         const double *fb_new, double *stats, hipStream_t st);
 
 // Relax / equilibrium launch for items whose instances share (nv, m).
 hipError_t launch_relax(int prec, int nv, int m, const RelaxItem *items, int n_items, const RelaxDesc *descs,
-                        void *f, double *w_out, const double *w_in, double omega, int mode, hipStream_t st);
+                        StateBuf f, double *w_out, const double *w_in, double omega, int mode, hipStream_t st);
 
 hipError_t launch_inflow_eq(int nv, int m, const InflowDesc *items, int n_items, const RelaxDesc *descs,
                             const double *w_inflow, double *fb, hipStream_t st);
@@ -172,12 +189,15 @@ hipError_t launch_inflow_eq(int nv, int m, const InflowDesc *items, int n_items,
 // D2Q9 lattice instances (Sec. 5.1): mode 0 applies S(h_pre) C(omega)
 // S(h_post) at every node (the source terms only where the instance has
 // gravity), mode 1 sets f = f^eq(w_in).
-hipError_t launch_lattice(int prec, const RelaxItem *items, int n_items, const RelaxDesc *descs, void *f,
+hipError_t launch_lattice(int prec, const RelaxItem *items, int n_items, const RelaxDesc *descs, StateBuf f,
                           double *w_out, const double *w_in, double omega, double h_pre, double h_post, int mode,
                           hipStream_t st);
 hipError_t launch_lattice_inflow(const InflowDesc *items, int n_items, const RelaxDesc *descs, const double *w_in,
                                  double *fb, hipStream_t st);
 hipError_t launch_fill(double *p, int64_t n, double value, hipStream_t st);
+// Conversion between the state of precision prec and binary64 values:
+// to_f64 = true reads the state into x, false writes x into the state.
+hipError_t launch_convert(int prec, StateBuf f, double *x, bool to_f64, hipStream_t st);
 hipError_t launch_fill_int(int32_t *p, int64_t n, int32_t value, hipStream_t st);
 hipError_t launch_fill_u64(uint64_t *p, int64_t n, uint64_t value, hipStream_t st);
 
@@ -189,12 +209,23 @@ hipError_t launch_dense_invert(double *table, const int64_t *row_off, const Dens
                                const int32_t *row_desc, const double *c0, int32_t *flags, int n_rows, int n,
                                int F, hipStream_t st);
 
+// Failure reporting of the dense sweep: a wait for an upwind trace that has
+// lasted wait_ticks of the 100 MHz constant clock gives up; it (or a claim
+// past the last tile) sets *dev (1: wait, 2: claim) and, if host is not
+// NULL, *host (host-visible memory, read by the entry points without a
+// synchronisation).
+struct DenseErr {
+  int32_t *dev;
+  int32_t *host;
+  uint64_t wait_ticks;
+};
+
 // Dense sweep of n_tiles tiles (claim order `order`); counter and flags must be
-// zero on entry; err_flag is set if a wait times out.
+// zero on entry.
 hipError_t launch_dense_sweep(int prec, bool level, int np, int dim, const DenseTile *tiles, const int32_t *order,
                               int n_tiles, const DenseFam *fams, const DenseDesc *descs, const double *table,
-                              int dt_idx, void *f, const double *fb_old, const double *fb_new, uint64_t *traces,
-                              int32_t *counter, int32_t *err_flag, hipStream_t st);
+                              int dt_idx, StateBuf f, const double *fb_old, const double *fb_new, uint64_t *traces,
+                              int32_t *counter, DenseErr err, hipStream_t st);
 
 
 }  // namespace pdg

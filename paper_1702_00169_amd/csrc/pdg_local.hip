@@ -69,14 +69,13 @@ __device__ inline void equilibrium(const RelaxDesc &d, const double (&w)[M], dou
 template <int PREC, int NV, int M>
 __global__ __launch_bounds__(kBlock) void relax_kernel(const RelaxItem *__restrict__ items,
                                                       const RelaxDesc *__restrict__ descs,
-                                                      typename Pol<PREC>::St *__restrict__ f,
+                                                      const State<PREC> f,
                                                       double *__restrict__ w_out,
                                                       const double *__restrict__ w_in, double omega, int mode) {
-  using St = typename Pol<PREC>::St;
   const RelaxItem it = items[blockIdx.x];
   const RelaxDesc d = descs[it.desc];
   const int64_t nodes = d.nodes;
-  St *fi = f + d.f_base;
+  const int64_t fi = d.f_base;
   const double inv_nv = 1.0 / NV;
   const double h2l = 0.5 / d.lambda;
   for (int64_t node = it.node0 + threadIdx.x; node < it.node0 + it.count; node += kBlock) {
@@ -86,7 +85,7 @@ __global__ __launch_bounds__(kBlock) void relax_kernel(const RelaxItem *__restri
 #pragma unroll
       for (int i = 0; i < NV; ++i)
 #pragma unroll
-        for (int k = 0; k < M; ++k) fv[i][k] = (double)ld_state(fi + (int64_t)(i * M + k) * nodes + node);
+        for (int k = 0; k < M; ++k) fv[i][k] = (double)f.ld(fi + (int64_t)(i * M + k) * nodes + node);
 #pragma unroll
       for (int k = 0; k < M; ++k) {
         // Neumaier compensated sum over velocities, fixed order
@@ -121,7 +120,7 @@ __global__ __launch_bounds__(kBlock) void relax_kernel(const RelaxItem *__restri
         for (int k = 0; k < M; ++k) {
           const double fe = fma(sg, q[k], w[k] * inv_nv);
           const double nv = (mode == 0) ? fma(omega, fe - fv[i][k], fv[i][k]) : fe;
-          st_state(fi + (int64_t)(i * M + k) * nodes + node, (St)nv);
+          f.st(fi + (int64_t)(i * M + k) * nodes + node, nv);
         }
       }
     }
@@ -189,14 +188,13 @@ __device__ inline void lattice_source(const RelaxDesc &d, double (&fv)[9], const
 template <int PREC>
 __global__ __launch_bounds__(kBlock) void lattice_kernel(const RelaxItem *__restrict__ items,
                                                         const RelaxDesc *__restrict__ descs,
-                                                        typename Pol<PREC>::St *__restrict__ f,
+                                                        const State<PREC> f,
                                                         double *__restrict__ w_out, const double *__restrict__ w_in,
                                                         double omega, double h_pre, double h_post, int mode) {
-  using St = typename Pol<PREC>::St;
   const RelaxItem it = items[blockIdx.x];
   const RelaxDesc d = descs[it.desc];
   const int64_t nodes = d.nodes;
-  St *fi = f + d.f_base;
+  const int64_t fi = d.f_base;
   const double lam = d.lambda;
   const double inv_l = 1.0 / lam;
   const bool source = d.param[0] != 0.0;
@@ -208,7 +206,7 @@ __global__ __launch_bounds__(kBlock) void lattice_kernel(const RelaxItem *__rest
     double rho, jx, jy;
     if (mode == 0) {
 #pragma unroll
-      for (int i = 0; i < 9; ++i) fv[i] = (double)ld_state(fi + (int64_t)i * nodes + node);
+      for (int i = 0; i < 9; ++i) fv[i] = (double)f.ld(fi + (int64_t)i * nodes + node);
       // moments: Neumaier compensated sums in a fixed order
       double acc[3] = {fv[0], fv[0] * d.cx[0], fv[0] * d.cy[0]};
       double comp[3] = {0.0, 0.0, 0.0};
@@ -235,7 +233,7 @@ __global__ __launch_bounds__(kBlock) void lattice_kernel(const RelaxItem *__rest
     if (mode == 1) {
 #pragma unroll
       for (int i = 0; i < 9; ++i)
-        st_state(fi + (int64_t)i * nodes + node, (St)lattice_feq(wt[i], d.cx[i], d.cy[i], rho, jx, jy, inv_l));
+        f.st(fi + (int64_t)i * nodes + node, lattice_feq(wt[i], d.cx[i], d.cy[i], rho, jx, jy, inv_l));
       continue;
     }
     if (source && h_pre != 0.0) lattice_source(d, fv, wt, rho, jx, jy, h_pre, inv_l);
@@ -244,7 +242,7 @@ __global__ __launch_bounds__(kBlock) void lattice_kernel(const RelaxItem *__rest
       fv[i] = fma(omega, lattice_feq(wt[i], d.cx[i], d.cy[i], rho, jx, jy, inv_l) - fv[i], fv[i]);
     if (source && h_post != 0.0) lattice_source(d, fv, wt, rho, jx, jy, h_post, inv_l);
 #pragma unroll
-    for (int i = 0; i < 9; ++i) st_state(fi + (int64_t)i * nodes + node, (St)fv[i]);
+    for (int i = 0; i < 9; ++i) f.st(fi + (int64_t)i * nodes + node, fv[i]);
     if (w_out != nullptr) {
       w_out[d.w_base + node] = rho;
       w_out[d.w_base + nodes + node] = jx;
@@ -285,11 +283,22 @@ __global__ void fill_u64_kernel(uint64_t *p, int64_t n, uint64_t value) {
     p[i] = value;
 }
 
+// state <-> binary64 (to_f64: x = state; else state = x), grid-stride
+template <int PREC>
+__global__ __launch_bounds__(kBlock) void convert_kernel(const State<PREC> f, double *__restrict__ x, int64_t n,
+                                                        int to_f64) {
+  for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < n; i += (int64_t)gridDim.x * kBlock) {
+    if (to_f64)
+      x[i] = (double)f.ld(i);
+    else
+      f.st(i, (typename Pol<PREC>::Rt)x[i]);
+  }
+}
+
 template <int PREC, int NV>
-hipError_t go_relax_m(int m, const RelaxItem *items, int n_items, const RelaxDesc *descs, void *f, double *w_out,
+hipError_t go_relax_m(int m, const RelaxItem *items, int n_items, const RelaxDesc *descs, StateBuf f, double *w_out,
                       const double *w_in, double omega, int mode, hipStream_t st) {
-  using St = typename Pol<PREC>::St;
-  St *fp = static_cast<St *>(f);
+  const State<PREC> fp = State<PREC>::make(f);
   switch (m) {
 #define PDG_RELAX_CASE(MM)                                                                                   \
   case MM:                                                                                                   \
@@ -334,7 +343,7 @@ hipError_t go_inflow_m(int m, const InflowDesc *items, int n_items, const RelaxD
 }  // namespace
 
 hipError_t launch_relax(int prec, int nv, int m, const RelaxItem *items, int n_items, const RelaxDesc *descs,
-                        void *f, double *w_out, const double *w_in, double omega, int mode, hipStream_t st) {
+                        StateBuf f, double *w_out, const double *w_in, double omega, int mode, hipStream_t st) {
   if (n_items <= 0) return hipSuccess;
 #define PDG_RELAX_NV(PR)                                                                            \
   switch (nv) {                                                                                     \
@@ -346,6 +355,7 @@ hipError_t launch_relax(int prec, int nv, int m, const RelaxItem *items, int n_i
     case kF64: PDG_RELAX_NV(kF64)
     case kF32: PDG_RELAX_NV(kF32)
     case kRefine: PDG_RELAX_NV(kRefine)
+    case kP48: PDG_RELAX_NV(kP48)
     default: return hipErrorInvalidValue;
   }
 #undef PDG_RELAX_NV
@@ -375,25 +385,23 @@ hipError_t launch_fill_u64(uint64_t *p, int64_t n, uint64_t value, hipStream_t s
   return hipGetLastError();
 }
 
-hipError_t launch_lattice(int prec, const RelaxItem *items, int n_items, const RelaxDesc *descs, void *f,
+hipError_t launch_lattice(int prec, const RelaxItem *items, int n_items, const RelaxDesc *descs, StateBuf f,
                           double *w_out, const double *w_in, double omega, double h_pre, double h_post, int mode,
                           hipStream_t st) {
   if (n_items <= 0) return hipSuccess;
+#define PDG_LATTICE_CASE(PR)                                                                                 \
+  case PR:                                                                                                   \
+    hipLaunchKernelGGL(lattice_kernel<PR>, dim3(n_items), dim3(kBlock), 0, st, items, descs,                 \
+                       State<PR>::make(f), w_out, w_in, omega, h_pre, h_post, mode);                         \
+    break;
   switch (prec) {
-    case kF64:
-      hipLaunchKernelGGL(lattice_kernel<kF64>, dim3(n_items), dim3(kBlock), 0, st, items, descs,
-                         static_cast<double *>(f), w_out, w_in, omega, h_pre, h_post, mode);
-      break;
-    case kF32:
-      hipLaunchKernelGGL(lattice_kernel<kF32>, dim3(n_items), dim3(kBlock), 0, st, items, descs,
-                         static_cast<float *>(f), w_out, w_in, omega, h_pre, h_post, mode);
-      break;
-    case kRefine:
-      hipLaunchKernelGGL(lattice_kernel<kRefine>, dim3(n_items), dim3(kBlock), 0, st, items, descs,
-                         static_cast<double *>(f), w_out, w_in, omega, h_pre, h_post, mode);
-      break;
+    PDG_LATTICE_CASE(kF64)
+    PDG_LATTICE_CASE(kF32)
+    PDG_LATTICE_CASE(kRefine)
+    PDG_LATTICE_CASE(kP48)
     default: return hipErrorInvalidValue;
   }
+#undef PDG_LATTICE_CASE
   return hipGetLastError();
 }
 
@@ -401,6 +409,24 @@ hipError_t launch_lattice_inflow(const InflowDesc *items, int n_items, const Rel
                                  double *fb, hipStream_t st) {
   if (n_items <= 0) return hipSuccess;
   hipLaunchKernelGGL(lattice_inflow_kernel, dim3(64, n_items), dim3(kBlock), 0, st, items, descs, w_in, fb);
+  return hipGetLastError();
+}
+
+hipError_t launch_convert(int prec, StateBuf f, double *x, bool to_f64, hipStream_t st) {
+  if (f.n <= 0) return hipSuccess;
+  const dim3 grid((unsigned)std::min<int64_t>(4096, (f.n + kBlock - 1) / kBlock));
+#define PDG_CONVERT_CASE(PR)                                                                                 \
+  case PR:                                                                                                   \
+    hipLaunchKernelGGL(convert_kernel<PR>, grid, dim3(kBlock), 0, st, State<PR>::make(f), x, f.n, to_f64 ? 1 : 0); \
+    break;
+  switch (prec) {
+    PDG_CONVERT_CASE(kF64)
+    PDG_CONVERT_CASE(kF32)
+    PDG_CONVERT_CASE(kRefine)
+    PDG_CONVERT_CASE(kP48)
+    default: return hipErrorInvalidValue;
+  }
+#undef PDG_CONVERT_CASE
   return hipGetLastError();
 }
 

@@ -132,6 +132,10 @@ struct CellOp<kRefine, NP> {
   }
 };
 
+// The 48-bit state keeps the arithmetic of binary32 + refinement.
+template <int NP>
+struct CellOp<kP48, NP> : CellOp<kRefine, NP> {};
+
 // Chains along the contiguous axis: one cell per thread, lanes in downwind
 // order over the item's rows (rows of one family are contiguous in memory,
 // so every load and store is a coalesced row segment).  The inflow values
@@ -142,13 +146,15 @@ struct CellOp<kRefine, NP> {
 // and across 256-cell chunks through a carry.
 template <int PREC, int NP>
 __device__ __forceinline__ void sweep_rows(const SweepItem &it, const SweepDesc &d, const CellOp<PREC, NP> &op,
-                                           typename Pol<PREC>::St *__restrict__ f,
+                                           const State<PREC> f,
                                            const double *__restrict__ fb_old, const double *__restrict__ fb_new,
                                            typename Pol<PREC>::Rt (*wtot)[4], int (*wopen)[4], double &cmax,
                                            double &ymax) {
-  using St = typename Pol<PREC>::St;
   using Rt = typename Pol<PREC>::Rt;
-  constexpr int KCH = 4;  // 256-cell chunks whose loads are issued together
+#ifndef PDG_KCH
+#define PDG_KCH 4
+#endif
+  constexpr int KCH = PDG_KCH;  // 256-cell chunks whose loads are issued together
   const Rt theta = op.theta;
   const Rt omt = (Rt)1 - theta;
   const Rt a = op.a;
@@ -189,7 +195,7 @@ __device__ __forceinline__ void sweep_rows(const SweepItem &it, const SweepDesc 
       row[k] = r;
       pos[k] = rev ? n - 1 - x : x;  // downwind position in the chain
 #pragma unroll
-      for (int q = 0; q < NP; ++q) fv[k][q] = valid ? (Rt)ld_state(f + rowbase + q * d.plane_step + pi) : (Rt)0;
+      for (int q = 0; q < NP; ++q) fv[k][q] = valid ? f.ld(rowbase + q * d.plane_step + pi) : (Rt)0;
     }
 #pragma unroll
     for (int k = 0; k < KCH; ++k, par ^= 1) {
@@ -233,7 +239,7 @@ __device__ __forceinline__ void sweep_rows(const SweepItem &it, const SweepDesc 
       const Rt u = (l == 0) ? ub : (lane > 0 ? prev : cin);
       if (valid) {
 #pragma unroll
-        for (int q = 0; q < NP; ++q) st_state(f + rowbase + q * d.plane_step + pidx[k], (St)fma(op.g[q], u, y[q]));
+        for (int q = 0; q < NP; ++q) f.st(rowbase + q * d.plane_step + pidx[k], fma(op.g[q], u, y[q]));
       }
       carry = cw;
     }
@@ -244,11 +250,10 @@ template <int PREC, int NP, int SMAX>
 __global__ __launch_bounds__(kBlock) void sweep_kernel(const SweepItem *__restrict__ items,
                                                       const SweepDesc *__restrict__ descs,
                                                       const OpEntry *__restrict__ ops, int dt_idx,
-                                                      typename Pol<PREC>::St *__restrict__ f,
+                                                      const State<PREC> f,
                                                       const double *__restrict__ fb_old,
                                                       const double *__restrict__ fb_new,
                                                       double *__restrict__ stats) {
-  using St = typename Pol<PREC>::St;
   using Rt = typename Pol<PREC>::Rt;
   __shared__ Rt xa[2][kBlock];
   __shared__ Rt xb[2][kBlock];
@@ -291,7 +296,7 @@ __global__ __launch_bounds__(kBlock) void sweep_kernel(const SweepItem *__restri
       Rt fv[NP];
       if (s < cnt) {
 #pragma unroll
-        for (int q = 0; q < NP; ++q) fv[q] = (Rt)ld_state(f + chain + (int64_t)(lb + s) * d.cell_step + q * d.plane_step);
+        for (int q = 0; q < NP; ++q) fv[q] = f.ld(chain + (int64_t)(lb + s) * d.cell_step + q * d.plane_step);
       } else {
 #pragma unroll
         for (int q = 0; q < NP; ++q) fv[q] = 0;
@@ -325,7 +330,7 @@ __global__ __launch_bounds__(kBlock) void sweep_kernel(const SweepItem *__restri
         for (int q = 0; q < NP; ++q) {
           const Rt xv = fma(op.g[q], uu, y[s][q]);
           if (q == NP - 1) xo = xv;
-          st_state(f + chain + (int64_t)(lb + s) * d.cell_step + q * d.plane_step, (St)xv);
+          f.st(chain + (int64_t)(lb + s) * d.cell_step + q * d.plane_step, xv);
         }
         uu = theta * xo + omt * fo[s];
       }
@@ -335,7 +340,7 @@ __global__ __launch_bounds__(kBlock) void sweep_kernel(const SweepItem *__restri
 
   }
 
-  if (PREC == kRefine) {
+  if (refine_prec(PREC)) {
     // block maxima of |correction| and |solution|, one pair per workgroup
     __syncthreads();
     double *red = reinterpret_cast<double *>(&xa[0][0]);
@@ -370,11 +375,10 @@ template <int PREC, int NP, int SMAX, bool WPOS>
 __global__ __launch_bounds__(kBlock) void sweep_graded_kernel(const SweepItem *__restrict__ items,
                                                              const SweepDesc *__restrict__ descs,
                                                              const OpEntry *__restrict__ ops, int dt_idx,
-                                                             typename Pol<PREC>::St *__restrict__ f,
+                                                             const State<PREC> f,
                                                              const double *__restrict__ fb_old,
                                                              const double *__restrict__ fb_new,
                                                              double *__restrict__ stats) {
-  using St = typename Pol<PREC>::St;
   using Rt = typename Pol<PREC>::Rt;
   __shared__ Rt xa[2][kBlock];
   __shared__ Rt xb[2][kBlock];
@@ -412,7 +416,7 @@ __global__ __launch_bounds__(kBlock) void sweep_graded_kernel(const SweepItem *_
       Rt fv[NP];
       if (s < cnt) {
 #pragma unroll
-        for (int q = 0; q < NP; ++q) fv[q] = (Rt)ld_state(f + chain + (int64_t)(lb + s) * d.cell_step + q * d.plane_step);
+        for (int q = 0; q < NP; ++q) fv[q] = f.ld(chain + (int64_t)(lb + s) * d.cell_step + q * d.plane_step);
       } else {
 #pragma unroll
         for (int q = 0; q < NP; ++q) fv[q] = 0;
@@ -449,14 +453,14 @@ __global__ __launch_bounds__(kBlock) void sweep_graded_kernel(const SweepItem *_
         for (int q = 0; q < NP; ++q) {
           const Rt xv = fma(gs[s][q], uu, y[s][q]);
           if (q == NP - 1) xo = xv;
-          st_state(f + chain + (int64_t)(lb + s) * d.cell_step + q * d.plane_step, (St)xv);
+          f.st(chain + (int64_t)(lb + s) * d.cell_step + q * d.plane_step, xv);
         }
         uu = theta * xo + omt * fo[s];
       }
     }
     u = unext;
   }
-  if (PREC == kRefine) {
+  if (refine_prec(PREC)) {
     __syncthreads();
     double *red = reinterpret_cast<double *>(&xa[0][0]);
     red[t] = cmax;
@@ -497,7 +501,7 @@ __global__ void invert_kernel(OpEntry *ops, int n_ops) {
     int piv = col;
     for (int r = col + 1; r < np; ++r)
       if (fabs(a[r][col]) > fabs(a[piv][col])) piv = r;
-    if (!(fabs(a[piv][col]) > 1e-300 * norm)) {
+    if (!(fabs(a[piv][col]) > kSingularPivot * norm)) {
       singular = 1;
       break;
     }
@@ -550,26 +554,25 @@ __global__ void invert_kernel(OpEntry *ops, int n_ops) {
 // ---------------------------------------------------------------------------
 template <int PREC, int NP>
 hipError_t go_sweep(bool graded, bool wpos, const SweepItem *items, int n_items, const SweepDesc *descs,
-                    const OpEntry *ops, int dt_idx, void *f, const double *fb_old, const double *fb_new,
+                    const OpEntry *ops, int dt_idx, StateBuf f, const double *fb_old, const double *fb_new,
                     double *stats, hipStream_t st) {
-  using St = typename Pol<PREC>::St;
   constexpr int SMAX = sweep_smax(NP);
   constexpr int SMAXG = sweep_smax_graded(NP);
   if (graded && wpos)
     hipLaunchKernelGGL((sweep_graded_kernel<PREC, NP, SMAXG, true>), dim3(n_items), dim3(kBlock), 0, st, items, descs,
-                       ops, dt_idx, static_cast<St *>(f), fb_old, fb_new, stats);
+                       ops, dt_idx, State<PREC>::make(f), fb_old, fb_new, stats);
   else if (graded)
     hipLaunchKernelGGL((sweep_graded_kernel<PREC, NP, SMAXG, false>), dim3(n_items), dim3(kBlock), 0, st, items,
-                       descs, ops, dt_idx, static_cast<St *>(f), fb_old, fb_new, stats);
+                       descs, ops, dt_idx, State<PREC>::make(f), fb_old, fb_new, stats);
   else
     hipLaunchKernelGGL((sweep_kernel<PREC, NP, SMAX>), dim3(n_items), dim3(kBlock), 0, st, items, descs, ops,
-                       dt_idx, static_cast<St *>(f), fb_old, fb_new, stats);
+                       dt_idx, State<PREC>::make(f), fb_old, fb_new, stats);
   return hipGetLastError();
 }
 
 template <int PREC>
 hipError_t go_sweep_np(bool graded, bool wpos, int np, const SweepItem *items, int n_items, const SweepDesc *descs,
-                       const OpEntry *ops, int dt_idx, void *f, const double *fb_old, const double *fb_new,
+                       const OpEntry *ops, int dt_idx, StateBuf f, const double *fb_old, const double *fb_new,
                        double *stats, hipStream_t st) {
   switch (np) {
     case 2: return go_sweep<PREC, 2>(graded, wpos, items, n_items, descs, ops, dt_idx, f, fb_old, fb_new, stats, st);
@@ -589,13 +592,14 @@ hipError_t launch_invert(OpEntry *ops, int n_ops, hipStream_t st) {
 }
 
 hipError_t launch_sweep(int prec, int np, bool graded, bool wpos, const SweepItem *items, int n_items,
-                        const SweepDesc *descs, const OpEntry *ops, int dt_idx, void *f, const double *fb_old,
+                        const SweepDesc *descs, const OpEntry *ops, int dt_idx, StateBuf f, const double *fb_old,
                         const double *fb_new, double *stats, hipStream_t st) {
   if (n_items <= 0) return hipSuccess;
   switch (prec) {
     case kF64: return go_sweep_np<kF64>(graded, wpos, np, items, n_items, descs, ops, dt_idx, f, fb_old, fb_new, stats, st);
     case kF32: return go_sweep_np<kF32>(graded, wpos, np, items, n_items, descs, ops, dt_idx, f, fb_old, fb_new, stats, st);
     case kRefine: return go_sweep_np<kRefine>(graded, wpos, np, items, n_items, descs, ops, dt_idx, f, fb_old, fb_new, stats, st);
+    case kP48: return go_sweep_np<kP48>(graded, wpos, np, items, n_items, descs, ops, dt_idx, f, fb_old, fb_new, stats, st);
     default: return hipErrorInvalidValue;
   }
 }

@@ -125,7 +125,8 @@ def gpu_initial_state(prob, insts, torch, dtype):
     dev = "cuda"
     w_t = torch.tensor(w, device=dev)
     fbw_t = torch.tensor(fbw, device=dev)
-    f = torch.empty(prob.layout["f_elems"], dtype=dtype, device=dev)
+    # dtype None: the prepared precision's own storage (e.g. the 48-bit state)
+    f = prob.new_state() if dtype is None else torch.empty(prob.layout["f_elems"], dtype=dtype, device=dev)
     fb = torch.empty(prob.layout["fb_elems"], dtype=torch.float64, device=dev)
     prob.equilibrium(w_t, f)
     prob.inflow_equilibrium(fbw_t, fb)
@@ -137,3 +138,16 @@ def oracle_initial_state(oprob, inst):
     x = oprob.mesh.node_coords().reshape(-1, oprob.mesh.dim)
     w = inst.w0(x).reshape(-1, oprob.mesh.nc, oprob.mesh.nd)
     return oprob.feq(w), oprob.inflow_from_w(inst.w0)
+
+
+def gpu_state(prob, torch, x_flat):
+    """Device state in the prepared precision holding the binary64 values
+    x_flat (GPU layout), written by the library's conversion."""
+    f = prob.new_state()
+    prob.state_from_f64(torch.as_tensor(np.asarray(x_flat, np.float64), device="cuda"), f)
+    return f
+
+
+def gpu_state_values(prob, f):
+    """The state's values as binary64 numpy (GPU layout)."""
+    return prob.state_to_f64(f).cpu().numpy()

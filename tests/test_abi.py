@@ -34,7 +34,7 @@ def lib():
 
 def _declared():
     text = open(os.path.join(ROOT, "include", "pdg.h")).read()
-    return sorted(set(re.findall(r"\b(pdg_[a-z_]+)\s*\(", text)))
+    return sorted(set(re.findall(r"\b(pdg_[a-z_0-9]+)\s*\(", text)))
 
 
 def test_every_declared_symbol_is_exported(lib):
@@ -72,6 +72,8 @@ def test_null_arguments_are_rejected(lib):
     assert so.pdg_transport_sweep(None, None, None, None, 0.1, None) == lib.PDG_EINVAL
     assert so.pdg_relax(None, None, None, None) == lib.PDG_EINVAL
     assert so.pdg_step(None, None, None, 1, None) == lib.PDG_EINVAL
+    assert so.pdg_state_to_f64(None, None, None, None) == lib.PDG_EINVAL
+    assert so.pdg_state_from_f64(None, None, None, None) == lib.PDG_EINVAL
 
 
 def test_calls_before_prepare_report_state_error(lib):
@@ -80,6 +82,11 @@ def test_calls_before_prepare_report_state_error(lib):
     assert lib._lib.pdg_transport_sweep(ctx, dummy, dummy, dummy, 0.1, None) == lib.PDG_ESTATE
     assert lib._lib.pdg_relax(ctx, dummy, None, None) == lib.PDG_ESTATE
     assert lib._lib.pdg_step(ctx, dummy, dummy, 2, None) == lib.PDG_ESTATE
+    assert lib._lib.pdg_state_to_f64(ctx, dummy, dummy, None) == lib.PDG_ESTATE
+    assert lib._lib.pdg_state_from_f64(ctx, dummy, dummy, None) == lib.PDG_ESTATE
+    # precisions beyond the 48-bit state are rejected before any device work
+    assert lib._lib.pdg_prepare(ctx, 0.01, 0.5, 2.0, 2, 4, None) == lib.PDG_EINVAL
+    assert lib._lib.pdg_prepare(ctx, 0.01, 0.5, 2.0, 2, -1, None) == lib.PDG_EINVAL
     lib.pdg_destroy(ctx)
 
 

@@ -1,15 +1,12 @@
 """Parity of the D2Q9 Euler-gravity workload (Sec. 5.1) at its full size
 (256^2 cells, degree 3), in the launch configuration bench.py times.
 
-Transport: after one sweep, the values of a cell depend only on the cells of
-its upwind cone (Sec. 4.1): for a velocity with non-negative components the
-cells at or below-left of it.  So a square sub-mesh of S x S cells at the
-inflow corner of a velocity, with the same initial data and the same inflow
-data on its two domain faces, has exactly the full-domain solution on its
-cells.  The oracle solves that sub-mesh for every velocity and the GPU's
-full-domain sweep is compared there (the dense tiled sweep for the four
-diagonal velocities, the chain kernel for the four axis velocities, the
-identity for the rest velocity).
+Transport: one sweep of every velocity on the whole domain is compared with
+the oracle's level sweep of the whole domain, cell by cell: the dense tiled
+sweep of the four diagonal velocities (1024 tiles each, under the claimed
+schedule that hands traces between running tiles, and under the levelled
+one), the chain kernel of the four axis velocities and the identity of the
+rest velocity.
 
 Node-local step: S(dt/2) C S(dt/2) is compared on every node.
 """
@@ -17,13 +14,12 @@ import numpy as np
 import pytest
 
 import workloads as W
-from helpers import gpu_initial_state, gpu_to_oracle, inst_dict, oracle_to_gpu, rel_errors, sizes
+from helpers import (gpu_initial_state, gpu_state_values, gpu_to_oracle, inst_dict, oracle_initial_state,
+                     oracle_problem, oracle_to_gpu, rel_errors, sizes)
 from oracle import step as ost
 from oracle import transport as otr
 
 pytestmark = pytest.mark.gpu
-
-S = 16   # sub-mesh cells per axis at each inflow corner
 
 
 @pytest.fixture(scope="module")
@@ -32,49 +28,40 @@ def lib():
     return P
 
 
-def _corner_block(inst, v):
-    """(first cell index per axis, physical box) of the S x S block at the
-    inflow corner of velocity v."""
-    n = np.array(inst.n)
-    h = (inst.hi - inst.lo) / n
-    first = np.array([0 if inst.vel[v][a] >= 0 else n[a] - S for a in range(inst.dim)])
-    lo = inst.lo + first * h
-    return first, lo, lo + S * h
-
-
-def _oracle_corner(inst, v, dt_sub, theta):
-    first, lo, hi = _corner_block(inst, v)
-    prob = ost.Problem((S, S), lo, hi, inst.degree, inst.vel, inst.m, inst.feq_kind, inst.feq_param)
-    x = prob.mesh.node_coords().reshape(-1, inst.dim)
-    f0 = prob.feq(inst.w0(x).reshape(-1, prob.mesh.nc, prob.mesh.nd))
-    fb = prob.feq(inst.w0(prob.entries(v)["coords"]))[v]
-    return first, otr.theta_step_sweep(prob.mesh, inst.vel[v], f0[v], fb, fb, dt_sub, theta, levels=prob.levels(v))
-
-
-@pytest.mark.parametrize("prec", [0, 2], ids=["fp64", "fp32refine"])
-def test_gravity2d_256_sweep_on_corner_blocks(lib, prec):
-    torch = pytest.importorskip("torch")
+@pytest.fixture(scope="module")
+def oracle_sweep():
+    """The oracle's sweep T(dt/2) of every velocity from f = f^eq(w0) on the
+    whole 256^2 mesh (oracle layout (9, 1, nc, nd))."""
     wl = W.make("gravity2d_256")
     inst = wl.instances[0]
-    print(f"gravity2d_256 full-size sweep prec={prec}", flush=True)
+    oprob = oracle_problem(inst)
+    f0, fb = oracle_initial_state(oprob, inst)
+    out = np.empty_like(f0)
+    for v in range(inst.vel.shape[0]):
+        out[v] = otr.theta_step_sweep(oprob.mesh, inst.vel[v], f0[v], fb[v], fb[v], wl.dt / 2, wl.theta,
+                                      levels=oprob.levels(v))
+    return out
+
+
+@pytest.mark.parametrize("prec,schedule", [(0, "claim"), (2, "claim"), (3, "claim"), (0, "level"), (3, "level")],
+                         ids=["fp64-claim", "fp32refine-claim", "fp32refine48-claim", "fp64-level",
+                              "fp32refine48-level"])
+def test_gravity2d_256_whole_domain_sweep(lib, oracle_sweep, monkeypatch, prec, schedule):
+    torch = pytest.importorskip("torch")
+    monkeypatch.setenv("PDG_DENSE_SCHEDULE", schedule)
+    wl = W.make("gravity2d_256")
+    inst = wl.instances[0]
+    print(f"gravity2d_256 whole-domain sweep prec={prec} schedule={schedule}", flush=True)
     prob = lib.Problem([inst_dict(inst)])
     prob.prepare(wl.dt, theta=wl.theta, omega=wl.omega, scheme=lib.PDG_STRANG_COLLAPSED, precision=prec)
-    f, fb = gpu_initial_state(prob, [inst], torch, torch.float64)
-    dt_sub = wl.dt / 2
-    prob.transport_sweep(f, fb, fb, dt_sub)
+    f, fb = gpu_initial_state(prob, [inst], torch, None)
+    prob.transport_sweep(f, fb, fb, wl.dt / 2)
     prob.sync_status()
-    got = gpu_to_oracle(f.cpu().numpy(), inst)          # (9, 1, nc, nd)
-    n = inst.n[0]
-    worst = 0.0
+    got = gpu_to_oracle(gpu_state_values(prob, f), inst)     # (9, 1, nc, nd)
+    bar = 1e-12 if prec == 0 else 1e-10
     for v in range(inst.vel.shape[0]):
-        first, want = _oracle_corner(inst, v, dt_sub, wl.theta)   # (1, S*S, nd)
-        ix = first[0] + np.arange(S)
-        iy = first[1] + np.arange(S)
-        cells = (ix[None, :] + n * iy[:, None]).ravel()            # sub-mesh order: x fastest
-        l2, mx = rel_errors(got[v][:, cells, :], want)
-        worst = max(worst, l2)
+        l2, mx = rel_errors(got[v], oracle_sweep[v])
         print(f"  velocity {inst.vel[v]}: rel L2 {l2:.3e} max {mx:.3e}")
-        bar = 1e-12 if prec == 0 else 1e-10
         assert l2 <= bar and mx <= 10 * bar, (v, l2, mx)
     prob.close()
 

@@ -41,7 +41,10 @@ def _instance(case):
     return inst
 
 
-def _run_case(lib, torch, case, prec, theta, half, seed=0):
+def _run_case(lib, torch, case, prec, theta, half, seed=0, tiles=None, autotune=False):
+    """One sweep on a random state against the oracle; tiles: apply these
+    tiles before the sweep; autotune: tune on this context first (the tuned
+    tiles are returned with the errors)."""
     inst = _instance(case)
     print(f"sweep case={case[0]} prec={prec} theta={theta} half={half}", flush=True)
     prob = lib.Problem([inst_dict(inst)])
@@ -49,6 +52,8 @@ def _run_case(lib, torch, case, prec, theta, half, seed=0):
     h = np.min((inst.hi - inst.lo) / np.array(inst.n))
     dt = 0.83 * h / inst.lam
     prob.prepare(dt, theta=theta, omega=2.0, precision=prec)
+    if tiles is not None:
+        prob.set_tiles(tiles)
     nv, m = inst.vel.shape[0], inst.m
     f_or = W.random_state(seed, (nv, m, nc, nd))
     if prec == lib.PDG_FP32:
@@ -62,6 +67,9 @@ def _run_case(lib, torch, case, prec, theta, half, seed=0):
     fbo_t = torch.tensor(fbo, device="cuda")
     fbn_t = torch.tensor(fbn, device="cuda")
     dsub = 0.5 * dt if half else dt
+    if autotune:
+        tiles = prob.autotune(torch.zeros_like(f), fbo_t, reps=1)
+    used = prob.tiles()
     prob.transport_sweep(f, fbo_t, fbn_t, dsub)
     torch.cuda.synchronize()
     got = gpu_to_oracle(f.double().cpu().numpy(), inst)
@@ -74,6 +82,8 @@ def _run_case(lib, torch, case, prec, theta, half, seed=0):
                                        levels=oprob.levels(v))
     corr = prob.last_refine_correction() if prec == lib.PDG_FP32_REFINE else None
     prob.close()
+    if autotune or tiles is not None:
+        return rel_errors(got, want), corr, used
     return rel_errors(got, want), corr
 
 
@@ -105,21 +115,22 @@ def test_sweep_tile_shapes_agree(lib, monkeypatch):
         assert l2 <= 1e-12 and mx <= 1e-11, tile
 
 
-def test_autotuned_tiles_solve_the_same_system(lib):
-    """The autotuner only changes the work decomposition."""
+@pytest.mark.parametrize("case", [CASES[4], CASES[1]], ids=[CASES[4][0], CASES[1][0]])
+def test_autotuned_tiles_solve_the_same_system(lib, case):
+    """The autotuner only changes the work decomposition: parity on the
+    context that was tuned, with the tiles it chose; the same tiles applied to
+    a fresh context through pdg_set_tiles give the same result."""
     torch = pytest.importorskip("torch")
-    case = ("3d_9x7x13_d2", 3, (9, 7, 13), 2, 1.0, 1)
+    (l2, mx), _, tuned = _run_case(lib, torch, case, 0, 0.5, False, seed=8, autotune=True)
+    print(f"  tuned tiles {tuned}: rel L2 {l2:.3e} max {mx:.3e}")
+    assert {t["np"] for t in tuned} == {case[3] + 1}
+    assert l2 <= 1e-12 and mx <= 1e-11
+    (l2b, mxb), _, used = _run_case(lib, torch, case, 0, 0.5, False, seed=8, tiles=tuned)
+    assert used == tuned
+    assert l2b <= 1e-12 and mxb <= 1e-11
     inst = _instance(case)
     prob = lib.Problem([inst_dict(inst)])
     prob.prepare(0.05)
-    scratch = torch.zeros(prob.layout["f_elems"], dtype=torch.float64, device="cuda")
-    fb = torch.ones(prob.layout["fb_elems"], dtype=torch.float64, device="cuda")
-    tiles = prob.autotune(scratch, fb, reps=1)
-    assert {(t["np"], t["x_kind"]) for t in tiles} == {(3, 0), (3, 1)}
-    prob.set_tiles(tiles)
     with pytest.raises(lib.PdgError):
-        prob.set_tiles([dict(np=3, x_kind=0, C=7, S=1)])
-    assert prob.tiles() == tiles
+        prob.set_tiles([dict(np=case[3] + 1, x_kind=0, C=7, S=1)])
     prob.close()
-    (l2, mx), _ = _run_case(lib, torch, case, 0, 0.5, False, seed=8)
-    assert l2 <= 1e-12 and mx <= 1e-11

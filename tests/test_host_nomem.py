@@ -1,0 +1,45 @@
+"""Host allocation failures come back as PDG_ENOMEM, not as a crash.
+
+A child process loads the library (host calls only: no device is touched),
+caps its own address space just above what it already uses, and asks for
+the dependency graph of a mesh whose per-cell tables need far more.
+"""
+import os
+import subprocess
+import sys
+
+from conftest import ROOT
+
+CHILD = r"""
+import ctypes, resource, sys
+sys.path.insert(0, sys.argv[1])
+lib = ctypes.CDLL(sys.argv[2])
+
+class Desc(ctypes.Structure):
+    _fields_ = [("dim", ctypes.c_int32), ("n", ctypes.c_int32 * 3), ("degree", ctypes.c_int32),
+                ("nv", ctypes.c_int32), ("m", ctypes.c_int32), ("lo", ctypes.c_double * 3),
+                ("hi", ctypes.c_double * 3), ("v", ctypes.POINTER(ctypes.c_double)),
+                ("feq", ctypes.c_int32), ("feq_param", ctypes.c_double * 4),
+                ("edges", ctypes.POINTER(ctypes.c_double) * 3)]
+
+v = (ctypes.c_double * 2)(1.0, 1.0)
+d = Desc()
+d.dim, d.degree, d.nv, d.m = 2, 1, 1, 1
+d.n[0], d.n[1], d.n[2] = 40000, 40000, 1      # 1.6e9 cells: GBs of per-cell tables
+d.lo[0], d.lo[1], d.hi[0], d.hi[1] = 0.0, 0.0, 1.0, 1.0
+d.v = ctypes.cast(v, ctypes.POINTER(ctypes.c_double))
+with open("/proc/self/status") as fh:
+    vm = [int(l.split()[1]) for l in fh if l.startswith("VmSize:")][0] * 1024
+limit = vm + 256 * 2 ** 20
+resource.setrlimit(resource.RLIMIT_AS, (limit, limit))
+out = ctypes.c_void_p()
+lib.pdg_setup_mesh.restype = ctypes.c_int32
+print(lib.pdg_setup_mesh(ctypes.byref(d), 1, ctypes.byref(out)))
+"""
+
+
+def test_setup_reports_enomem_when_host_memory_runs_out():
+    so = os.path.join(ROOT, "paper_1702_00169_amd", "_lib", "libpdg.so")
+    r = subprocess.run([sys.executable, "-c", CHILD, ROOT, so], capture_output=True, text=True, timeout=120)
+    assert r.returncode == 0, r.stderr
+    assert r.stdout.strip() == "5"   # PDG_ENOMEM
