@@ -276,7 +276,7 @@ def main():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default=DEFAULT_WORKLOAD, choices=W.WORKLOADS)
-    ap.add_argument("--precision", default="fp64", choices=list(PREC_NAMES.values()))
+    ap.add_argument("--precision", default="fp32refine48", choices=list(PREC_NAMES.values()))
     ap.add_argument("--reps", type=int, default=20, help="launches per kernel-timing loop")
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--no-compare", action="store_true", help="skip the other precisions")

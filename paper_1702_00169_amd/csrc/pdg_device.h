@@ -64,8 +64,11 @@ template <int PREC>
 struct State {
   using St = typename Pol<PREC>::St;
   using Rt = typename Pol<PREC>::Rt;
+  using Raw = St;  // a value as loaded, before conversion (see State<kP48>)
   St *p;
   static State make(StateBuf b) { return State{static_cast<St *>(b.p)}; }
+  __device__ __forceinline__ Raw ldr(int64_t i) const { return ld_state(p + i); }
+  __device__ __forceinline__ Rt dec(Raw r) const { return (Rt)r; }
   __device__ __forceinline__ Rt ld(int64_t i) const { return (Rt)ld_state(p + i); }
   __device__ __forceinline__ void st(int64_t i, Rt v) const { st_state(p + i, (St)v); }
 };
@@ -99,11 +102,19 @@ __device__ __forceinline__ void p48_encode(double x, float &h, int16_t &l) {
 template <>
 struct State<kP48> {
   using Rt = double;
+  // Loading the two planes and decoding are separate steps, so that a kernel
+  // can issue all of its loads before it decodes any of them.
+  struct Raw {
+    float h;
+    int16_t l;
+  };
   float *hi;
   int16_t *lo;
   static State make(StateBuf b) {
     return State{static_cast<float *>(b.p), reinterpret_cast<int16_t *>(static_cast<char *>(b.p) + 4 * b.n)};
   }
+  __device__ __forceinline__ Raw ldr(int64_t i) const { return Raw{ld_state(hi + i), ld_state(lo + i)}; }
+  __device__ __forceinline__ double dec(Raw r) const { return p48_decode(r.h, r.l); }
   __device__ __forceinline__ double ld(int64_t i) const { return p48_decode(ld_state(hi + i), ld_state(lo + i)); }
   __device__ __forceinline__ void st(int64_t i, double v) const {
     float h;

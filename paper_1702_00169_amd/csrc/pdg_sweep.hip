@@ -151,10 +151,13 @@ __device__ __forceinline__ void sweep_rows(const SweepItem &it, const SweepDesc 
                                            typename Pol<PREC>::Rt (*wtot)[4], int (*wopen)[4], double &cmax,
                                            double &ymax) {
   using Rt = typename Pol<PREC>::Rt;
-#ifndef PDG_KCH
-#define PDG_KCH 4
+  // 256-cell chunks whose loads are issued together: eight for cells of up
+  // to three nodes (the registers allow it at the same occupancy), four above
+#ifdef PDG_KCH
+  constexpr int KCH = PDG_KCH;
+#else
+  constexpr int KCH = NP <= 3 ? 8 : 4;
 #endif
-  constexpr int KCH = PDG_KCH;  // 256-cell chunks whose loads are issued together
   const Rt theta = op.theta;
   const Rt omt = (Rt)1 - theta;
   const Rt a = op.a;
@@ -181,8 +184,9 @@ __device__ __forceinline__ void sweep_rows(const SweepItem &it, const SweepDesc 
   Rt carry = 0;  // I of the last element of the previous chunk
   int par = 0;
   for (int c0 = 0; c0 < total; c0 += KCH * kBlock) {
-    // issue the loads of KCH chunks before any of them is used
-    Rt fv[KCH][NP];
+    // issue the loads of KCH chunks before any of them is used (and before
+    // any is converted to the arithmetic type)
+    typename State<PREC>::Raw fr[KCH][NP];
     int pidx[KCH], row[KCH], pos[KCH];
 #pragma unroll
     for (int k = 0; k < KCH; ++k) {
@@ -194,8 +198,11 @@ __device__ __forceinline__ void sweep_rows(const SweepItem &it, const SweepDesc 
       pidx[k] = valid ? pi : -1;
       row[k] = r;
       pos[k] = rev ? n - 1 - x : x;  // downwind position in the chain
+      // lanes past the end load the item's first cell (always in bounds):
+      // the loads stay unconditional, so they are all issued before any wait
+      const int pis = valid ? pi : 0;
 #pragma unroll
-      for (int q = 0; q < NP; ++q) fv[k][q] = valid ? f.ld(rowbase + q * d.plane_step + pi) : (Rt)0;
+      for (int q = 0; q < NP; ++q) fr[k][q] = f.ldr(rowbase + q * d.plane_step + pis);
     }
 #pragma unroll
     for (int k = 0; k < KCH; ++k, par ^= 1) {
@@ -203,9 +210,12 @@ __device__ __forceinline__ void sweep_rows(const SweepItem &it, const SweepDesc 
       const bool valid = pidx[k] >= 0;
       const int l = pos[k];
       const int r = row[k];
+      Rt fv[NP];
+#pragma unroll
+      for (int q = 0; q < NP; ++q) fv[q] = valid ? f.dec(fr[k][q]) : (Rt)0;
       Rt y[NP];
-      op.solve(fv[k], y, cmax, ymax);
-      const Rt fo = fv[k][NP - 1];
+      op.solve(fv, y, cmax, ymax);
+      const Rt fo = fv[NP - 1];
       Rt beta = valid ? theta * y[NP - 1] + omt * fo : (Rt)0;
       Rt ub = 0;
       if (valid && l == 0) {
@@ -247,7 +257,7 @@ __device__ __forceinline__ void sweep_rows(const SweepItem &it, const SweepDesc 
 }
 
 template <int PREC, int NP, int SMAX>
-__global__ __launch_bounds__(kBlock) void sweep_kernel(const SweepItem *__restrict__ items,
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(3))) void sweep_kernel(const SweepItem *__restrict__ items,
                                                       const SweepDesc *__restrict__ descs,
                                                       const OpEntry *__restrict__ ops, int dt_idx,
                                                       const State<PREC> f,
@@ -283,7 +293,10 @@ __global__ __launch_bounds__(kBlock) void sweep_kernel(const SweepItem *__restri
   const int window = P * S;
   Rt u = 0;
   if (active) u = theta * (Rt)fb_new[it.fb + c] + omt * (Rt)fb_old[it.fb + c];
-  const int tau = it.tau0 + c;
+  // inactive lanes address chain tau0 (in bounds) and cells past the chain
+  // end address its last cell: every load is unconditional and in bounds,
+  // and the values of those lanes and cells are never used
+  const int tau = it.tau0 + (active ? c : 0);
   const int64_t chain = it.base + (int64_t)(tau % d.nx) + (int64_t)(tau / d.nx) * d.hi_stride + d.cell0 + d.plane0;
   int wpar = 0;
   for (int w0 = 0; w0 < n; w0 += window, wpar ^= 1) {
@@ -291,16 +304,18 @@ __global__ __launch_bounds__(kBlock) void sweep_kernel(const SweepItem *__restri
     const int cnt = active ? max(0, min(S, n - lb)) : 0;
     Rt y[SMAX][NP];
     Rt fo[SMAX];
+    typename State<PREC>::Raw fr[SMAX][NP];
+#pragma unroll
+    for (int s = 0; s < SMAX; ++s) {
+      const int64_t cl = min(lb + s, n - 1);
+#pragma unroll
+      for (int q = 0; q < NP; ++q) fr[s][q] = f.ldr(chain + cl * d.cell_step + q * d.plane_step);
+    }
 #pragma unroll
     for (int s = 0; s < SMAX; ++s) {
       Rt fv[NP];
-      if (s < cnt) {
 #pragma unroll
-        for (int q = 0; q < NP; ++q) fv[q] = f.ld(chain + (int64_t)(lb + s) * d.cell_step + q * d.plane_step);
-      } else {
-#pragma unroll
-        for (int q = 0; q < NP; ++q) fv[q] = 0;
-      }
+      for (int q = 0; q < NP; ++q) fv[q] = s < cnt ? f.dec(fr[s][q]) : (Rt)0;
       fo[s] = fv[NP - 1];
       op.solve(fv, y[s], cmax, ymax);
     }
