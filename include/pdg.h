@@ -237,6 +237,23 @@ pdg_status pdg_inflow_equilibrium(pdg_ctx *c, const double *w_inflow, double *fb
 pdg_status pdg_transport_sweep(pdg_ctx *c, void *f, const double *fb_old, const double *fb_new,
                                double dt_sub, void *stream);
 
+/* pdg_transport_sweep for callers that cannot allocate device memory (code
+ * under HIP graph capture, serving loops, harnesses that forbid hipMalloc):
+ * the same operation, arguments, kernels and results, but the sweep's device
+ * scratch -- the per-workgroup refinement statistics, the inflow-trace slots
+ * and tile-claim counters of dense velocities -- lives in a static array of
+ * 32 MiB per GPU that the library holds until the process ends (its address
+ * is taken when a context is prepared on that GPU), not in the context's
+ * buffers.  The call allocates nothing.  PDG_EUNSUPPORTED (before any launch;
+ * pdg_error_detail gives the sizes) if the problem needs more scratch than
+ * that.  Every call on one GPU shares the array and leaves its contents
+ * behind (the slots and counters are reset at the start of each call), so
+ * calls that overlap on one GPU -- concurrent streams, threads or processes
+ * sharing the library's copy -- race and must be serialised by the caller.
+ * pdg_last_refine_correction reports the most recent sweep of either kind. */
+pdg_status pdg_transport_sweep_static(pdg_ctx *c, void *f, const double *fb_old, const double *fb_new,
+                                      double dt_sub, void *stream);
+
 /* Collision step (eq. collision_cn, Sec. 4.4): at every node
  * w = P f (compensated binary64 sums), then f_i <- f_i + omega (f_i^eq(w) - f_i).
  * w_out (nullable, device binary64, w layout) receives w. */

@@ -23,7 +23,7 @@ PDG_FEQ_ADVECTION, PDG_FEQ_EULER, PDG_FEQ_D2Q9 = 0, 1, 2
 PDG_LIE, PDG_STRANG, PDG_STRANG_COLLAPSED, PDG_KIN, PDG_KIN4 = 0, 1, 2, 3, 4
 
 EXPORTED = ("pdg_setup_mesh", "pdg_layout", "pdg_node_coords", "pdg_levels", "pdg_topo_levels", "pdg_line_operator", "pdg_cell_operator",
-            "pdg_prepare", "pdg_equilibrium", "pdg_state_to_f64", "pdg_state_from_f64", "pdg_inflow_equilibrium", "pdg_transport_sweep",
+            "pdg_prepare", "pdg_equilibrium", "pdg_state_to_f64", "pdg_state_from_f64", "pdg_inflow_equilibrium", "pdg_transport_sweep", "pdg_transport_sweep_static",
             "pdg_relax", "pdg_source", "pdg_step", "pdg_autotune", "pdg_get_tiles", "pdg_set_tiles", "pdg_last_refine_correction", "pdg_sync_status", "pdg_status_string", "pdg_error_detail", "pdg_destroy")
 
 
@@ -67,6 +67,7 @@ def _load():
         "pdg_state_from_f64": (i32, [p, p, p, p]),
         "pdg_inflow_equilibrium": (i32, [p, p, p, p]),
         "pdg_transport_sweep": (i32, [p, p, p, p, d, p]),
+        "pdg_transport_sweep_static": (i32, [p, p, p, p, d, p]),
         "pdg_relax": (i32, [p, p, p, p]),
         "pdg_source": (i32, [p, p, d, p]),
         "pdg_step": (i32, [p, p, p, i32, p]),
@@ -214,6 +215,11 @@ def pdg_inflow_equilibrium(ctx, w_inflow, fb, stream=None):
 def pdg_transport_sweep(ctx, f, fb_old, fb_new, dt_sub, stream=None):
     _check(_lib.pdg_transport_sweep(ctx, _ptr(f), _ptr(fb_old), _ptr(fb_new), float(dt_sub), _stream(stream)),
            "pdg_transport_sweep")
+
+
+def pdg_transport_sweep_static(ctx, f, fb_old, fb_new, dt_sub, stream=None):
+    _check(_lib.pdg_transport_sweep_static(ctx, _ptr(f), _ptr(fb_old), _ptr(fb_new), float(dt_sub),
+                                           _stream(stream)), "pdg_transport_sweep_static")
 
 
 def pdg_relax(ctx, f, w_out=None, stream=None):

@@ -20,6 +20,7 @@
 #include <cstring>
 #include <map>
 #include <memory>
+#include <mutex>
 #include <new>
 #include <string>
 #include <vector>
@@ -29,7 +30,20 @@
 
 using namespace pdg;
 
+// Scratch of pdg_transport_sweep_static, for callers that cannot allocate
+// device memory: one copy per GPU, held until the process ends.  Host code
+// never passes the array's name to a kernel (on the host it only stands for
+// the symbol): its device address is taken per device with
+// hipGetSymbolAddress and kept in g_scratch_ptr.
+constexpr size_t kStaticScratchBytes = size_t(32) << 20;
+constexpr int kMaxDevices = 64;
+static __device__ __align__(256) unsigned char scratch[kStaticScratchBytes];
+
 namespace {
+
+std::mutex g_scratch_mu;
+void *g_scratch_ptr[kMaxDevices] = {};
+
 
 
 struct Instance {
@@ -1261,6 +1275,19 @@ static pdg_status prepare_impl(pdg_ctx *c, double dt, double theta, double omega
   *c->herr = 0;
   PREP_TRY(hipHostGetDevicePointer(reinterpret_cast<void **>(&c->herr_dev), c->herr, 0))
   {
+    // device address of this GPU's static scratch (once per device)
+    int dev = 0;
+    PREP_TRY(hipGetDevice(&dev))
+    if (dev >= 0 && dev < kMaxDevices) {
+      std::lock_guard<std::mutex> lock(g_scratch_mu);
+      if (!g_scratch_ptr[dev]) {
+        void *ptr = nullptr;
+        PREP_TRY(hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)))
+        g_scratch_ptr[dev] = ptr;
+      }
+    }
+  }
+  {
     // the dense trace wait bound; PDG_DENSE_WAIT_TICKS overrides it (tests of
     // the failure report use a bound of zero ticks)
     const char *wt = std::getenv("PDG_DENSE_WAIT_TICKS");
@@ -1459,6 +1486,42 @@ pdg_status pdg_transport_sweep(pdg_ctx *c, void *f, const double *fb_old, const 
     }
   if (dt_idx < 0) return PDG_ESTATE;
   return do_sweep(c, f, fb_old, fb_new, dt_idx, static_cast<hipStream_t>(stream), ctx_scratch(c));
+}
+
+pdg_status pdg_transport_sweep_static(pdg_ctx *c, void *f, const double *fb_old, const double *fb_new,
+                                      double dt_sub, void *stream) {
+  if (!c || !f || (c->fb_elems > 0 && (!fb_old || !fb_new))) return PDG_EINVAL;
+  if (!c->prepared) return PDG_ESTATE;
+  if (dense_failed(c)) return PDG_EDEVICE;
+  int dt_idx = -1;
+  for (size_t i = 0; i < c->dts.size(); ++i)
+    if (dt_sub == c->dts[i]) {
+      dt_idx = (int)i;
+      break;
+    }
+  if (dt_idx < 0) return PDG_ESTATE;
+  int dev = 0;
+  HIP_TRY(hipGetDevice(&dev));
+  void *base = (dev >= 0 && dev < kMaxDevices) ? g_scratch_ptr[dev] : nullptr;
+  if (!base) {
+    std::snprintf(g_detail, sizeof(g_detail), "pdg_transport_sweep_static: no static scratch on device %d "
+                  "(prepare the context on this device)", dev);
+    return PDG_ESTATE;
+  }
+  // [stats: 2 doubles per work item][trace slots][claim counters], 256-byte aligned parts
+  auto up = [](size_t b) { return (b + 255) / 256 * 256; };
+  const size_t b_stats = up(2 * c->sitems.n * sizeof(double));
+  const size_t b_traces = up(c->dtraces.n * sizeof(uint64_t));
+  const size_t b_sync = up(c->dgroups.size() * sizeof(int32_t));
+  if (b_stats + b_traces + b_sync > kStaticScratchBytes) {
+    std::snprintf(g_detail, sizeof(g_detail), "pdg_transport_sweep_static: this problem needs %zu bytes of "
+                  "scratch, the static scratch holds %zu", b_stats + b_traces + b_sync, kStaticScratchBytes);
+    return PDG_EUNSUPPORTED;
+  }
+  unsigned char *p = static_cast<unsigned char *>(base);
+  const SweepScratch sc{reinterpret_cast<double *>(p), reinterpret_cast<uint64_t *>(p + b_stats),
+                        reinterpret_cast<int32_t *>(p + b_stats + b_traces)};
+  return do_sweep(c, f, fb_old, fb_new, dt_idx, static_cast<hipStream_t>(stream), sc);
 }
 
 pdg_status pdg_relax(pdg_ctx *c, void *f, double *w_out, void *stream) {
