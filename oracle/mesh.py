@@ -1,12 +1,13 @@
-"""Cartesian meshes of hexahedral (box) cells with affine maps.
+"""Structured meshes of hexahedral cells with affine maps.
 
 Oracle (test infrastructure only).  The paper maps the reference cell
 ]-1,1[^D onto each cell L by tau_L with positive Jacobian determinant and
 places the Gauss-Lobatto points and weights of eq. map_GL in it (Sec. 3.1).
-On the axis-aligned box meshes used here, tau_L is affine:
-tau_L(xh) = corner_L + (xh + 1) h_L / 2.  The cells are uniform on [lo, hi]
-unless per-axis cell edges are given (a tensor-product graded mesh: cell
-sizes vary along each axis, every cell stays a box).
+Every map here is affine, tau_L(xh) = corner_L + J_L (xh + 1), on three kinds
+of meshes: uniform box cells on [lo, hi]; tensor-product graded box cells
+(per-axis cell edges: sizes vary along each axis); and a uniform affine
+lattice (cell edge vectors a_k, the columns of `axes`): every cell is the same
+parallelogram / parallelepiped, corner_L = lo + sum_k i_k a_k, J_L = A / 2.
 
 Numbering used by the oracle (its own; the GPU library has another):
 cells are lexicographic with x fastest, nodes in a cell are tensor indices
@@ -21,14 +22,26 @@ from . import gl
 
 
 class Mesh:
-    """Mesh of n[0] x ... x n[D-1] box cells, degree d: uniform on [lo, hi],
-    or with cell edges edges[k] (n[k] + 1 increasing values) along axis k."""
+    """Mesh of n[0] x ... x n[D-1] cells, degree d: uniform boxes on [lo, hi],
+    boxes with cell edges edges[k] (n[k] + 1 increasing values) along axis k,
+    or the affine lattice of cell edge vectors axes[:, k] (D x D, positive
+    determinant) from the corner lo (hi is then ignored)."""
 
-    def __init__(self, n, lo, hi, degree, edges=None):
+    def __init__(self, n, lo, hi, degree, edges=None, axes=None):
         self.n = tuple(int(v) for v in n)
         self.dim = len(self.n)
         if self.dim not in (1, 2, 3):
             raise ValueError("dimension must be 1, 2 or 3")
+        self.axes = None
+        if axes is not None:
+            if edges is not None:
+                raise ValueError("a mesh has either cell edges or lattice axes")
+            self.axes = np.asarray(axes, dtype=float).reshape(self.dim, self.dim)
+            if not np.linalg.det(self.axes) > 0:
+                raise ValueError("the lattice axes must have a positive determinant")
+            lo = np.asarray(lo, dtype=float).reshape(self.dim)
+            # box-equivalent edges: only used for the extent of each axis index
+            edges = [np.arange(self.n[k] + 1, dtype=float) for k in range(self.dim)]
         if edges is None:
             lo = np.asarray(lo, dtype=float).reshape(self.dim)
             hi = np.asarray(hi, dtype=float).reshape(self.dim)
@@ -41,6 +54,10 @@ class Mesh:
         self.hi = np.array([e[-1] for e in self.edges])
         # smallest cell size per axis (a length scale for tolerances)
         self.h = np.array([np.min(np.diff(e)) for e in self.edges])
+        if self.axes is not None:
+            self.lo = lo
+            self.hi = lo + self.axes @ np.array(self.n, dtype=float)   # the far corner
+            self.h = np.linalg.norm(self.axes, axis=0)
         self.degree = int(degree)
         self.np1 = self.degree + 1
         self.nc = int(np.prod(self.n))
@@ -82,6 +99,8 @@ class Mesh:
         map would be: column k is (corner + h_k e_k - corner) / 2.
         """
         multi = self.cell_multi(cells)
+        if self.axes is not None:
+            return np.broadcast_to(self.axes / 2.0, (len(multi), self.dim, self.dim)).copy()
         corner = self.corner(multi)
         jac = np.zeros((len(multi), self.dim, self.dim))
         for k in range(self.dim):
@@ -92,6 +111,8 @@ class Mesh:
 
     def corner(self, multi):
         """Lower corner of the cells with integer coordinates multi, (N, D)."""
+        if self.axes is not None:
+            return self.lo[None, :] + np.asarray(multi, dtype=float) @ self.axes.T
         return np.stack([self.edges[k][multi[:, k]] for k in range(self.dim)], axis=1)
 
     def node_coords(self, cells=None):

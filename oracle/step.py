@@ -70,8 +70,8 @@ def omega_for(h, dt, omega):
 
 
 class Problem:
-    def __init__(self, n, lo, hi, degree, vel, m, feq_kind, feq_param, edges=None):
-        self.mesh = _mesh.Mesh(n, lo, hi, degree, edges)
+    def __init__(self, n, lo, hi, degree, vel, m, feq_kind, feq_param, edges=None, axes=None):
+        self.mesh = _mesh.Mesh(n, lo, hi, degree, edges, axes)
         self.vel = np.asarray(vel, dtype=float).reshape(-1, self.mesh.dim)
         self.nv = self.vel.shape[0]
         self.m = int(m)
