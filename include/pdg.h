@@ -140,6 +140,18 @@ typedef struct {
                              Velocities with two or three non-zero components along a graded
                              axis are PDG_EUNSUPPORTED at prepare (their dense cell blocks would
                              differ from cell to cell). */
+  double axes[9];       /* optional uniform affine lattice (Sec. 3.1, affine cell maps): axes[3 k + i]
+                           is component i of the edge vector a_k shared by every cell, for k, i < D;
+                           cell (c_0, .., c_{D-1}) is lo + sum_k (c_k + [0, 1]) a_k, every cell the
+                           same parallelogram / parallelepiped (positive determinant, else
+                           PDG_EINVAL; hi and edges must then be unused).  All zero: box cells.
+                           Transport runs in the frame of the cell index axes, where the scheme is
+                           that of unit box cells with velocity A^{-1} v (A = [a_0 .. a_{D-1}]):
+                           chains follow the index axes along which A^{-1} v is non-zero (a
+                           component at most 1e-13 of its largest counts as zero), and a
+                           velocity with several non-zero components of A^{-1} v takes the dense
+                           path.  fb and pdg_node_coords use the same index-frame faces, mapped
+                           to physical points; the relaxation and equilibria use v itself. */
 } pdg_instance_desc;
 
 /* Build a context for n_inst independent instances (Sec. 4.1): validate the
@@ -278,8 +290,10 @@ pdg_status pdg_step(pdg_ctx *c, void *f, const double *fb, int32_t n_steps, void
 /* Autotuner of the sweep's work decomposition.  Work items are grouped in
  * launch classes (same node count d+1 and same chain kind: chains along the
  * contiguous x axis, or along a strided axis).  For every class this times
- * each candidate tile (x chains: rows per workgroup 1..64; strided chains:
- * chains per workgroup 8..64 x cells per thread segment 1..8) with `reps`
+ * each candidate tile (x chains: rows per workgroup 1..64 with one cell per
+ * thread (S = 1), or chains per workgroup 8..64 x cells per thread segment
+ * 2..8; strided chains: chains per workgroup 8..64 x cells per thread
+ * segment 1..8) with `reps`
  * launches of the class alone on `stream`, keeps the fastest, and uses it
  * from then on.  f is used as scratch and overwritten; fb is read.  Every tile
  * solves the same system; only the rounding order of the segment combine

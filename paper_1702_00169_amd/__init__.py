@@ -39,7 +39,7 @@ class pdg_instance_desc(ctypes.Structure):
                 ("nv", ctypes.c_int32), ("m", ctypes.c_int32), ("lo", ctypes.c_double * 3),
                 ("hi", ctypes.c_double * 3), ("v", ctypes.POINTER(ctypes.c_double)),
                 ("feq", ctypes.c_int32), ("feq_param", ctypes.c_double * 4),
-                ("edges", ctypes.POINTER(ctypes.c_double) * 3)]
+                ("edges", ctypes.POINTER(ctypes.c_double) * 3), ("axes", ctypes.c_double * 9)]
 
 
 def _load():
@@ -125,7 +125,9 @@ def _stream(stream):
 def pdg_setup_mesh(instances):
     """instances: list of dicts with dim, n, degree, v (nv x dim), m, lo, hi,
     feq ('advection'|'euler'|'d2q9'), feq_param and optionally edges (per
-    axis None or n[k] + 1 cell edges).  Returns an opaque context handle."""
+    axis None or n[k] + 1 cell edges) or axes (D x D array whose column k is
+    the cell edge vector a_k of a uniform affine lattice).  Returns an opaque
+    context handle."""
     import numpy as np
     arr = (pdg_instance_desc * len(instances))()
     keep = []
@@ -148,10 +150,16 @@ def pdg_setup_mesh(instances):
                 e = np.ascontiguousarray(np.asarray(e, dtype=np.float64))
                 keep.append(e)
                 eptr[k] = e.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+        ax9 = [0.0] * 9
+        if ins.get("axes") is not None:
+            a = np.asarray(ins["axes"], dtype=np.float64).reshape(dim, dim)
+            for k in range(dim):
+                for r in range(dim):
+                    ax9[3 * k + r] = float(a[r, k])
         arr[i] = pdg_instance_desc(dim, (ctypes.c_int32 * 3)(*n), int(ins["degree"]), nv, int(ins["m"]),
                                    (ctypes.c_double * 3)(*lo), (ctypes.c_double * 3)(*hi),
                                    v.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), int(feq),
-                                   (ctypes.c_double * 4)(*par), eptr)
+                                   (ctypes.c_double * 4)(*par), eptr, (ctypes.c_double * 9)(*ax9))
     ctx = ctypes.c_void_p()
     _check(_lib.pdg_setup_mesh(arr, len(instances), ctypes.byref(ctx)), "pdg_setup_mesh")
     return ctx

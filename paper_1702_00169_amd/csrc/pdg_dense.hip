@@ -19,6 +19,8 @@ struct DenseRowLayout {
   __host__ __device__ int64_t a_off() const { return n * n + 3 * n * f; }
   __host__ __device__ int64_t b_off() const { return 2 * n * n + 3 * n * f; }
   __host__ __device__ int64_t ai_off() const { return 3 * n * n + 3 * n * f; }
+  // transfer operator of a full tile (two-dimensional velocities only)
+  __host__ __device__ int64_t r_off() const { return 4 * n * n + 3 * n * f; }
 };
 
 __global__ __launch_bounds__(kDenseThreads) void dense_invert_kernel(double *table, const int64_t *row_off,
@@ -195,6 +197,223 @@ __device__ __forceinline__ void dense_local_solve(const double *row, const typen
   }
 }
 
+// ---------------------------------------------------------------------------
+// transfer schedule (two-dimensional velocities with two non-zero components)
+// ---------------------------------------------------------------------------
+// A full tile of T x T cells is linear in its data: its outflow traces are
+// Z(f, domain inflow) + R u, u its inflow traces from upwind tiles.  Traces
+// of a tile edge are indexed edge cell by edge cell, face node fastest: the
+// west (inflow) and east (outflow) edges by cell row j as j F + tt, the south
+// and north edges by cell column i as T F + i F + tt, so the east/north part
+// of a tile's output is the west/south part of its neighbours' input.  R
+// (2TF x 2TF) is the same for every full tile of a (velocity, sub-step).  It
+// is stored in the order of the A operand of the binary64 16x16x4 MFMA:
+// element (row o, column c) at ((o / 16) (2TF / 4) + c / 4) 64 + o % 16 +
+// 16 (c % 4), so that lane l of a wave reads entry l of each 16 x 4 block.
+constexpr int kTransferT = 8;        // tile edge (cells)
+constexpr int kTransferMaxDiag = 64; // tiles per diagonal held in LDS (edge <= 512 cells)
+
+__host__ __device__ constexpr int64_t transfer_index(int o, int c, int nr) {
+  return ((int64_t)(o / 16) * (nr / 4) + c / 4) * 64 + o % 16 + 16 * (c % 4);
+}
+
+// One thread per column c of R: the tile is solved from f = 0 with the unit
+// inflow e_c, cell by cell in row order (a cell's west and south neighbours
+// come first), keeping only the traces that cross cell faces: with f = 0 the
+// local solve gives y = 0, so x = G_0 u_west + G_1 u_south and an outflow
+// trace is theta x at the outflow face node.
+template <int NP>
+__global__ __launch_bounds__(128) void dense_transfer_operator_kernel(double *table, const int64_t *row_off,
+                                                                      const DenseDesc *descs,
+                                                                      const int32_t *row_desc) {
+  constexpr int N = NP * NP, F = NP, T = kTransferT, TF = T * F, NR = 2 * TF;
+  const int c = threadIdx.x;
+  if (c >= NR) return;
+  double *row = table + row_off[blockIdx.x];
+  const DenseDesc &d = descs[row_desc[blockIdx.x]];
+  const DenseRowLayout L{N, F};
+  const double th = d.theta;
+  const double *g0 = row + L.g(0);
+  const double *g1 = row + L.g(1);
+  double us[T][F];  // inflow from the south of each cell column: the north traces of the row below
+#pragma unroll
+  for (int i = 0; i < T; ++i)
+#pragma unroll
+    for (int tt = 0; tt < F; ++tt) us[i][tt] = (c == TF + i * F + tt) ? 1.0 : 0.0;
+  for (int j = 0; j < T; ++j) {
+    double uw[F];
+#pragma unroll
+    for (int tt = 0; tt < F; ++tt) uw[tt] = (c == j * F + tt) ? 1.0 : 0.0;
+#pragma unroll
+    for (int i = 0; i < T; ++i) {
+      double ue[F], un[F];
+#pragma unroll
+      for (int tt = 0; tt < F; ++tt) {
+        const int qe = face_node<NP, 2>(0, tt, NP - 1);
+        const int qn = face_node<NP, 2>(1, tt, NP - 1);
+        double xe = 0.0, xn = 0.0;
+#pragma unroll
+        for (int s2 = 0; s2 < F; ++s2) {
+          xe = fma(g0[qe * F + s2], uw[s2], fma(g1[qe * F + s2], us[i][s2], xe));
+          xn = fma(g0[qn * F + s2], uw[s2], fma(g1[qn * F + s2], us[i][s2], xn));
+        }
+        ue[tt] = th * xe;
+        un[tt] = th * xn;
+      }
+#pragma unroll
+      for (int tt = 0; tt < F; ++tt) {
+        uw[tt] = ue[tt];
+        us[i][tt] = un[tt];
+      }
+    }
+#pragma unroll
+    for (int tt = 0; tt < F; ++tt) row[L.r_off() + transfer_index(j * F + tt, c, NR)] = uw[tt];
+  }
+#pragma unroll
+  for (int i = 0; i < T; ++i)
+#pragma unroll
+    for (int tt = 0; tt < F; ++tt) row[L.r_off() + transfer_index(TF + i * F + tt, c, NR)] = us[i][tt];
+}
+
+// The trace wavefront of one family (velocity, component) over its tile
+// diagonals, after the zero-inflow tile pass has left each tile's Z in the
+// slots of its downwind tiles.  Tile (I, J) of diagonal s = I + J takes its
+// inflow from the outputs of (I - 1, J) and (I, J - 1) on diagonal s - 1,
+// held in LDS; the outputs of a diagonal are one matrix product
+// OUT = Z + R IN over its tiles (columns), computed as 16 x 16 blocks of
+// binary64 MFMA: wave w owns the row blocks w, w + 4, .. of R, whose A
+// operands stay in registers for the whole sweep.  The outputs replace Z in
+// the slots, where the final tile pass reads them as exact inflow traces.
+typedef double transfer_d4 __attribute__((ext_vector_type(4)));
+
+template <int F>
+__global__ __launch_bounds__(256) void dense_transfer_kernel(const DenseTile *__restrict__ tiles,
+                                                             const DenseFam *__restrict__ fams,
+                                                             const int32_t *__restrict__ fam_list,
+                                                             const DenseDesc *__restrict__ descs,
+                                                             const double *__restrict__ table, int dt_idx,
+                                                             uint64_t *__restrict__ traces) {
+  constexpr int N = F * F, T = kTransferT, TF = T * F, NR = 2 * TF, KS = NR / 4, NRB = NR / 16;
+  constexpr int NPW = (NRB + 3) / 4;               // row blocks per wave
+  constexpr int NCB = (kTransferMaxDiag + 15) / 16;  // column blocks of the longest diagonal
+  constexpr int LS = kTransferMaxDiag + 16;        // LDS row stride (doubles)
+  __shared__ double ob[2][NR][LS];                 // outputs of the previous and current diagonal: [row][column]
+  const DenseFam fm = fams[fam_list[blockIdx.x]];
+  const DenseDesc &d = descs[fm.desc];
+  const DenseRowLayout L{N, F};
+  const double *R = table + d.op_off + (int64_t)dt_idx * d.op_stride + L.r_off();
+  const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
+  const int nt0 = fm.nt[0], nt1 = fm.nt[1];
+  double A[NPW][KS];
+#pragma unroll
+  for (int r = 0; r < NPW; ++r)
+#pragma unroll
+    for (int ks = 0; ks < KS; ++ks) A[r][ks] = (w + 4 * r < NRB) ? R[((w + 4 * r) * KS + ks) * 64 + l] : 0.0;
+  // A family's tiles were given their trace slots in order (t0 fastest), 3
+  // axis slots each: tile (I, J)'s slots start at tbase + (I + nt0 J) 3 slot.
+  const int slot = tiles[fm.tile0].slot;
+  const int64_t tbase = tiles[fm.tile0].trace_off;
+  // B operand: lane l holds row kq = l / 16, column jj = l % 16 of a 4 x 16
+  // block; D: register i of lane l holds row 4 i + kq, column jj
+  const int jj = l & 15, kq = l >> 4;
+  // offset of output row o of tile column j of diagonal s in the slots of the
+  // downwind tile it feeds (east edge: axis-0 slot of (I + 1, J); north edge:
+  // axis-1 slot of (I, J + 1)), or -1 when the tile is on the downwind border
+  auto out_slot = [&](int s, int j, int o) -> int64_t {
+    const int ilo = max(0, s - nt1 + 1), ihi = min(s, nt0 - 1);
+    const int I = ilo + j, J = s - I;
+    if (I > ihi) return -1;
+    if (o < TF) return I + 1 < nt0 ? tbase + ((int64_t)(I + 1) + (int64_t)nt0 * J) * 3 * slot + o : -1;
+    return J + 1 < nt1 ? tbase + ((int64_t)I + (int64_t)nt0 * (J + 1)) * 3 * slot + slot + (o - TF) : -1;
+  };
+  // Z of the next diagonal's tiles is loaded one diagonal ahead, so the loads
+  // are in flight while the current product runs
+  auto load_z = [&](int s, double (&zz)[NPW][NCB][4]) {
+    const int ntl = min(s, nt0 - 1) - max(0, s - nt1 + 1) + 1;
+#pragma unroll
+    for (int r = 0; r < NPW; ++r)
+#pragma unroll
+      for (int cb = 0; cb < NCB; ++cb)
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+          const int64_t src = (w + 4 * r < NRB && cb * 16 < ntl) ? out_slot(s, cb * 16 + jj, (w + 4 * r) * 16 + 4 * i + kq) : -1;
+          zz[r][cb][i] = src >= 0 ? __longlong_as_double((long long)traces[src]) : 0.0;
+        }
+  };
+  const int ndiag = nt0 + nt1 - 1;
+  int cur = 0;
+  // diagonal s with its Z in zc, loading the next diagonal's Z into zn.  The
+  // column blocks run in pairs: every B operand of a pair is read from LDS
+  // (unconditionally, from an in-range column, then masked) before the two
+  // independent MFMA chains are issued interleaved.
+  auto step = [&](int s, double (&zc)[NPW][NCB][4], double (&zn)[NPW][NCB][4]) {
+    if (s + 1 < ndiag) load_z(s + 1, zn);
+    const int ilo = max(0, s - nt1 + 1), ihi = min(s, nt0 - 1);
+    const int plo = max(0, s - nt1);  // first tile column I of diagonal s - 1
+    const int ncb = (ihi - ilo) / 16 + 1;
+#pragma unroll
+    for (int cp = 0; cp < NCB; cp += 2) {
+      if (cp >= ncb) break;  // wave-uniform
+      double b[2][KS];
+      int jcol[2];
+      bool valid[2];
+#pragma unroll
+      for (int h = 0; h < 2; ++h) {
+        const int j = (cp + h) * 16 + jj;
+        jcol[h] = j;
+        valid[h] = cp + h < ncb && ilo + j <= ihi;
+        const int I = ilo + j, J = s - I;
+        // west neighbour (I - 1, J) and south neighbour (I, J - 1) on diagonal s - 1
+        const bool west = valid[h] && I > 0, south = valid[h] && J > 0;
+        const int cw = west ? I - 1 - plo : 0, cs = south ? I - plo : 0;
+#pragma unroll
+        for (int ks = 0; ks < KS; ++ks) {
+          const int k = 4 * ks + kq;  // input index
+          const bool use = k < TF ? west : south;
+          const double x = ob[cur ^ 1][k][k < TF ? cw : cs];
+          b[h][ks] = use ? x : 0.0;
+        }
+      }
+#pragma unroll
+      for (int r = 0; r < NPW; ++r) {
+        const int rb = w + 4 * r;
+        if (rb >= NRB) break;  // wave-uniform
+        transfer_d4 acc0, acc1;
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+          acc0[i] = zc[r][cp][i];
+          acc1[i] = cp + 1 < NCB ? zc[r][cp + 1 < NCB ? cp + 1 : cp][i] : 0.0;
+        }
+#pragma unroll
+        for (int ks = 0; ks < KS; ++ks) {
+          acc0 = __builtin_amdgcn_mfma_f64_16x16x4f64(A[r][ks], b[0][ks], acc0, 0, 0, 0);
+          acc1 = __builtin_amdgcn_mfma_f64_16x16x4f64(A[r][ks], b[1][ks], acc1, 0, 0, 0);
+        }
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+          if (!valid[h]) continue;
+#pragma unroll
+          for (int i = 0; i < 4; ++i) {
+            const int o = rb * 16 + 4 * i + kq;
+            const double y = h == 0 ? acc0[i] : acc1[i];
+            ob[cur][o][jcol[h]] = y;
+            const int64_t dst = out_slot(s, jcol[h], o);
+            if (dst >= 0) traces[dst] = (uint64_t)__double_as_longlong(y);
+          }
+        }
+      }
+    }
+    __syncthreads();
+    cur ^= 1;
+  };
+  double z0[NPW][NCB][4], z1[NPW][NCB][4];
+  load_z(0, z0);
+  for (int s = 0; s < ndiag; s += 2) {
+    step(s, z0, z1);
+    if (s + 1 < ndiag) step(s + 1, z1, z0);
+  }
+}
+
 // Register slots of the claimed schedule's trace requests: up to 4 (three
 // diagonals ahead), as many as fit in 64 VGPRs.
 template <int DIM, int F>
@@ -294,22 +513,28 @@ __device__ inline void dense_put_trace(uint64_t *p, double v) {
   __hip_atomic_exchange(p, (uint64_t)__double_as_longlong(v), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
-// One wave per tile, in one of two schedules:
-// * claimed (LEVEL = false): one launch for all tiles.  The tile index is
+// One wave per tile, in one of these modes (DenseMode):
+// * claimed (kDenseClaim): one launch for all tiles.  The tile index is
 //   claimed by lane 0 from a counter that hands out tiles in dependency order
 //   (upwind tiles first) and broadcast with readfirstlane, so it is
 //   wave-uniform; inflow traces arrive through the atomic slots above, cell by
 //   cell, so a tile starts as soon as its first upwind cells are done.
-// * levelled (LEVEL = true): one launch per tile diagonal; the launch's tiles
+// * levelled (kDenseLevel): one launch per tile diagonal; the launch's tiles
 //   are order[0 .. n_tiles).  Upwind tiles belong to earlier launches, whose
 //   writes the kernel boundary makes visible: plain loads and stores, no
 //   waiting.
+// * the two tile passes of the transfer schedule (all tiles in one launch,
+//   no waiting): kDenseZero solves each tile with the traces of its upwind
+//   tiles taken as zero (domain inflow as given) and stores only its outflow
+//   traces, into the downwind tiles' slots; after the trace wavefront has
+//   replaced them by the exact traces (dense_transfer_kernel), kDenseFinal
+//   solves each tile with them and stores the cells (and no traces).
 // Either way descriptors and operator rows are read through scalar loads and
 // all control flow that depends on the tile is uniform.  Inside the tile the
 // cells are solved diagonal by diagonal; the inflow traces of a cell come from
 // the previous diagonal through LDS, from an upwind tile through the trace
 // slots, or from the domain inflow data.
-template <int PREC, int NP, int DIM, bool LEVEL>
+template <int PREC, int NP, int DIM, int MODE>
 __global__ __launch_bounds__(kDenseThreads) void dense_sweep_kernel(
     const DenseTile *__restrict__ tiles, const int32_t *__restrict__ order, const DenseFam *__restrict__ fams,
     const DenseDesc *__restrict__ descs, const double *__restrict__ table, int dt_idx,
@@ -323,7 +548,7 @@ __global__ __launch_bounds__(kDenseThreads) void dense_sweep_kernel(
   __shared__ Rt gl[DIM][N][F];             // G_a of the tile's operator row
   const int t = threadIdx.x;
   int claim = blockIdx.x;
-  if (!LEVEL) {
+  if (MODE == kDenseClaim) {
     if (t == 0) claim = atomicAdd(counter, 1);
     claim = __builtin_amdgcn_readfirstlane(claim);
     if (claim >= n_tiles) {  // the counter was not reset: report, do nothing
@@ -403,8 +628,9 @@ __global__ __launch_bounds__(kDenseThreads) void dense_sweep_kernel(
           fc += cl[b] * fs;
           fs *= d.T[b];
         }
+      if (MODE == kDenseZero) continue;  // upwind tile's traces taken as zero
       rsrc[a] = tl.trace_off + (int64_t)a * tl.slot + fc * F;
-      if (LEVEL)
+      if (MODE == kDenseLevel || MODE == kDenseFinal)
 #pragma unroll
         for (int tt = 0; tt < F; ++tt) uin[a][tt] = (Rt)__longlong_as_double((long long)traces[rsrc[a] + tt]);
     } else {
@@ -454,7 +680,12 @@ __global__ __launch_bounds__(kDenseThreads) void dense_sweep_kernel(
   int up_lds[DIM];
 #pragma unroll
   for (int a = 0; a < DIM; ++a) up_lds[a] = t - tstride[a];
-  constexpr bool kRegG = dense_out_nodes<NP, DIM>() * DIM * F * (int)sizeof(Rt) <= 512;  // <= 128 VGPRs
+  // G rows in registers (<= 128 VGPRs) shorten each diagonal step, which is on
+  // the critical path of the claimed and levelled schedules; the two passes
+  // of the transfer schedule have no critical path inside a tile and keep
+  // them in LDS, for the occupancy
+  constexpr bool kRegG = (MODE == kDenseClaim || MODE == kDenseLevel) &&
+                         dense_out_nodes<NP, DIM>() * DIM * F * (int)sizeof(Rt) <= 512;
   Rt gr[DIM][N][F];
   if constexpr (kRegG) {
 #pragma unroll
@@ -495,7 +726,7 @@ __global__ __launch_bounds__(kDenseThreads) void dense_sweep_kernel(
 #pragma unroll
         for (int tt = 0; tt < F; ++tt) slot[a][tt] = dense_peek_trace(traces + rsrc[a] + tt);
   };
-  if constexpr (!LEVEL && AHEAD > 0) {
+  if constexpr (MODE == kDenseClaim && AHEAD > 0) {
     if (active && diag < AHEAD) {
 #pragma unroll
       for (int k = 0; k < AHEAD; ++k)
@@ -509,11 +740,11 @@ __global__ __launch_bounds__(kDenseThreads) void dense_sweep_kernel(
   // diagonal s; k = s mod RING, a constant (the slot of diagonal s)
   auto step = [&](int s, auto kc) {
     constexpr int k = decltype(kc)::value;
-    if constexpr (!LEVEL && AHEAD > 0) {
+    if constexpr (MODE == kDenseClaim && AHEAD > 0) {
       if (active && diag == s + AHEAD) peek(pk[(k + AHEAD) % RING]);
     }
     if (active && diag == s) {
-      if constexpr (!LEVEL && AHEAD > 0) {
+      if constexpr (MODE == kDenseClaim && AHEAD > 0) {
         // the request made AHEAD diagonals ago; poll again only if empty
         uint64_t(&cur)[DIM][F] = pk[k];
         bool ready = true;
@@ -528,7 +759,7 @@ __global__ __launch_bounds__(kDenseThreads) void dense_sweep_kernel(
           if (rsrc[a] >= 0)
 #pragma unroll
             for (int tt = 0; tt < F; ++tt) uin[a][tt] = (Rt)__longlong_as_double((long long)cur[a][tt]);
-      } else if constexpr (!LEVEL) {
+      } else if constexpr (MODE == kDenseClaim) {
         // no ring: request and wait now
         uint64_t rb[DIM][F];
         dense_take_faces<DIM, F>(traces, rsrc, rb, err);
@@ -566,9 +797,9 @@ __global__ __launch_bounds__(kDenseThreads) void dense_sweep_kernel(
           const Rt o = th * yo[q] + omt * fv[q];
           otr[b][t][tt] = o;
           if (dst[b] >= 0) {
-            if (LEVEL)
+            if constexpr (MODE == kDenseLevel || MODE == kDenseZero)
               traces[dst[b] + tt] = (uint64_t)__double_as_longlong((double)o);
-            else
+            else if constexpr (MODE == kDenseClaim)
               dense_put_trace(traces + dst[b] + tt, (double)o);
           }
         }
@@ -582,12 +813,12 @@ __global__ __launch_bounds__(kDenseThreads) void dense_sweep_kernel(
     __builtin_amdgcn_wave_barrier();
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
   };
-  if constexpr (LEVEL) {
+  if constexpr (MODE != kDenseClaim) {
     for (int s = 0; s < ndiag; ++s) step(s, std::integral_constant<int, 0>{});
   } else {
     for (int s0 = 0; s0 < ndiag; s0 += RING) dense_ring_turn(s0, ndiag, step, std::make_integer_sequence<int, RING>{});
   }
-  if (!active) return;
+  if (MODE == kDenseZero || !active) return;
   // every node: x = y + sum_a G_a u_a (the face nodes again, in the same
   // order, so they equal the values the traces were taken from)
 #pragma unroll
@@ -614,29 +845,78 @@ hipError_t launch_dense_invert(double *table, const int64_t *row_off, const Dens
   return hipGetLastError();
 }
 
+hipError_t launch_dense_transfer_operator(int np, double *table, const int64_t *row_off, const DenseDesc *descs,
+                                          const int32_t *row_desc, int n_rows, hipStream_t st) {
+  if (n_rows <= 0) return hipSuccess;
+  switch (np) {
+#define PDG_TOP_CASE(NPV)                                                                                    \
+  case NPV:                                                                                                  \
+    hipLaunchKernelGGL(dense_transfer_operator_kernel<NPV>, dim3(n_rows), dim3(128), 0, st, table, row_off, \
+                       descs, row_desc);                                                                     \
+    break;
+    PDG_TOP_CASE(2)
+    PDG_TOP_CASE(3)
+    PDG_TOP_CASE(4)
+    PDG_TOP_CASE(5)
+#undef PDG_TOP_CASE
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_dense_transfer(int np, const DenseTile *tiles, const DenseFam *fams, const int32_t *fam_list,
+                                 int n_fams, const DenseDesc *descs, const double *table, int dt_idx,
+                                 uint64_t *traces, hipStream_t st) {
+  if (n_fams <= 0) return hipSuccess;
+  switch (np) {
+#define PDG_TR_CASE(NPV)                                                                                       \
+  case NPV:                                                                                                    \
+    hipLaunchKernelGGL(dense_transfer_kernel<NPV>, dim3(n_fams), dim3(256), 0, st, tiles, fams, fam_list, descs, \
+                       table, dt_idx, traces);                                                                 \
+    break;
+    PDG_TR_CASE(2)
+    PDG_TR_CASE(3)
+    PDG_TR_CASE(4)
+    PDG_TR_CASE(5)
+#undef PDG_TR_CASE
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
 template <int PREC, int NP, int DIM>
-hipError_t go_dense(bool level, const DenseTile *tiles, const int32_t *order, int n_tiles, const DenseFam *fams,
+hipError_t go_dense(int mode, const DenseTile *tiles, const int32_t *order, int n_tiles, const DenseFam *fams,
                     const DenseDesc *descs, const double *table, int dt_idx, StateBuf f, const double *fb_old,
                     const double *fb_new, uint64_t *traces, int32_t *counter, DenseErr err, hipStream_t st) {
-  if (level)
-    hipLaunchKernelGGL((dense_sweep_kernel<PREC, NP, DIM, true>), dim3(n_tiles), dim3(kDenseThreads), 0, st, tiles,
-                       order, fams, descs, table, dt_idx, State<PREC>::make(f), fb_old, fb_new, traces, counter, err,
-                       n_tiles);
-  else
-    hipLaunchKernelGGL((dense_sweep_kernel<PREC, NP, DIM, false>), dim3(n_tiles), dim3(kDenseThreads), 0, st, tiles,
-                       order, fams, descs, table, dt_idx, State<PREC>::make(f), fb_old, fb_new, traces, counter, err,
-                       n_tiles);
+#define PDG_DENSE_MODE(M)                                                                                      \
+  hipLaunchKernelGGL((dense_sweep_kernel<PREC, NP, DIM, M>), dim3(n_tiles), dim3(kDenseThreads), 0, st, tiles, \
+                     order, fams, descs, table, dt_idx, State<PREC>::make(f), fb_old, fb_new, traces, counter, err, \
+                     n_tiles)
+  switch (mode) {
+    case kDenseClaim: PDG_DENSE_MODE(kDenseClaim); break;
+    case kDenseLevel: PDG_DENSE_MODE(kDenseLevel); break;
+    case kDenseZero:
+      if constexpr (DIM != 2) return hipErrorInvalidValue;  // the transfer schedule is two-dimensional
+      else PDG_DENSE_MODE(kDenseZero);
+      break;
+    case kDenseFinal:
+      if constexpr (DIM != 2) return hipErrorInvalidValue;
+      else PDG_DENSE_MODE(kDenseFinal);
+      break;
+    default: return hipErrorInvalidValue;
+  }
+#undef PDG_DENSE_MODE
   return hipGetLastError();
 }
 
 template <int PREC>
-hipError_t go_dense_shape(bool level, int np, int dim, const DenseTile *tiles, const int32_t *order, int n_tiles,
+hipError_t go_dense_shape(int mode, int np, int dim, const DenseTile *tiles, const int32_t *order, int n_tiles,
                           const DenseFam *fams, const DenseDesc *descs, const double *table, int dt_idx, StateBuf f,
                           const double *fb_old, const double *fb_new, uint64_t *traces, int32_t *counter,
                           DenseErr err, hipStream_t st) {
 #define PDG_DENSE_CASE(NPV, DIMV)                                                                             \
   if (np == NPV && dim == DIMV)                                                                               \
-    return go_dense<PREC, NPV, DIMV>(level, tiles, order, n_tiles, fams, descs, table, dt_idx, f, fb_old, fb_new,   \
+    return go_dense<PREC, NPV, DIMV>(mode, tiles, order, n_tiles, fams, descs, table, dt_idx, f, fb_old, fb_new,    \
                                      traces, counter, err, st);
   PDG_DENSE_CASE(2, 2)
   PDG_DENSE_CASE(3, 2)
@@ -648,16 +928,16 @@ hipError_t go_dense_shape(bool level, int np, int dim, const DenseTile *tiles, c
   return hipErrorInvalidValue;
 }
 
-hipError_t launch_dense_sweep(int prec, bool level, int np, int dim, const DenseTile *tiles, const int32_t *order,
+hipError_t launch_dense_sweep(int prec, int mode, int np, int dim, const DenseTile *tiles, const int32_t *order,
                               int n_tiles, const DenseFam *fams, const DenseDesc *descs, const double *table,
                               int dt_idx, StateBuf f, const double *fb_old, const double *fb_new, uint64_t *traces,
-                              int32_t *counter, DenseErr err_flag, hipStream_t st) {
+                              int32_t *counter, DenseErr err, hipStream_t st) {
   if (n_tiles <= 0) return hipSuccess;
   switch (prec) {
-    case kF64: return go_dense_shape<kF64>(level, np, dim, tiles, order, n_tiles, fams, descs, table, dt_idx, f, fb_old, fb_new, traces, counter, err_flag, st);
-    case kF32: return go_dense_shape<kF32>(level, np, dim, tiles, order, n_tiles, fams, descs, table, dt_idx, f, fb_old, fb_new, traces, counter, err_flag, st);
-    case kRefine: return go_dense_shape<kRefine>(level, np, dim, tiles, order, n_tiles, fams, descs, table, dt_idx, f, fb_old, fb_new, traces, counter, err_flag, st);
-    case kP48: return go_dense_shape<kP48>(level, np, dim, tiles, order, n_tiles, fams, descs, table, dt_idx, f, fb_old, fb_new, traces, counter, err_flag, st);
+    case kF64: return go_dense_shape<kF64>(mode, np, dim, tiles, order, n_tiles, fams, descs, table, dt_idx, f, fb_old, fb_new, traces, counter, err, st);
+    case kF32: return go_dense_shape<kF32>(mode, np, dim, tiles, order, n_tiles, fams, descs, table, dt_idx, f, fb_old, fb_new, traces, counter, err, st);
+    case kRefine: return go_dense_shape<kRefine>(mode, np, dim, tiles, order, n_tiles, fams, descs, table, dt_idx, f, fb_old, fb_new, traces, counter, err, st);
+    case kP48: return go_dense_shape<kP48>(mode, np, dim, tiles, order, n_tiles, fams, descs, table, dt_idx, f, fb_old, fb_new, traces, counter, err, st);
     default: return hipErrorInvalidValue;
   }
 }

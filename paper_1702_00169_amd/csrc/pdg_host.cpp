@@ -48,7 +48,17 @@ void *g_scratch_ptr[kMaxDevices] = {};
 
 struct Instance {
   pdg_instance_desc d;
-  std::vector<double> v;     // nv * dim
+  std::vector<double> v;     // nv * dim, physical velocities (equilibria, relaxation)
+  // Transport works in the frame of the cell index axes: on box meshes that
+  // is physical space (vt = v, ht = cell sizes); on an affine lattice of cell
+  // edge vectors a_k it is the unit box mesh with velocity A^{-1} v and unit
+  // cells (the cofactor of the affine cell map turns v into A^{-1} v in every
+  // volume and face term of eq. DG_reduit).
+  bool affine = false;
+  double A[3][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}};  // A[i][k]: component i of a_k
+  std::vector<double> vt;    // nv * dim, transport-frame velocities
+  double ht[3] = {1, 1, 1};  // transport-frame cell sizes (box meshes: h)
+  std::vector<int> paxis, psign;  // per velocity: physical axis and sign ({+-lambda e_k} sets), -1/0 otherwise
   int64_t nc, nd, np;
   int64_t f_off, w_off, fb_off;
   std::vector<int64_t> fb_vel_off;  // per velocity, offset within the instance's fb block
@@ -85,6 +95,9 @@ struct DenseGroup {
   int64_t sync_off;      // index of the group's tile-claim counter
   std::vector<int64_t> level;  // claim-order offsets where each tile diagonal starts (+ count)
   bool claim = false;          // one launch of claimed tiles (else one launch per tile diagonal)
+  bool transfer_ok = false;    // two-dimensional, full tiles only, diagonals within the LDS limit
+  bool transfer = false;       // transfer schedule: zero-inflow tiles, trace wavefront, final tiles
+  int64_t tfam_first = 0, tfam_count = 0;  // its families in the transfer family list
 };
 
 // One (instance, velocity) family of chains and its launch class.
@@ -160,6 +173,7 @@ struct pdg_ctx {
   DevBuf<double> dtable;
   DevBuf<uint64_t> dtraces;  // inflow-trace slots of the dense tiles (binary64 bits)
   DevBuf<int32_t> dsync;     // per group: tile-claim counter
+  DevBuf<int32_t> dtfams;    // families of the transfer-schedule groups, group by group
   bool dense_claim = false;   // some dense group uses claimed tiles (their slots are reset per sweep)
   DevBuf<int32_t> derr;      // 1: a trace wait timed out, 2: claim counter overrun
   int32_t *herr = nullptr;   // host-visible copy of derr's codes (pinned, mapped)
@@ -170,7 +184,10 @@ struct pdg_ctx {
   std::vector<RelaxGroup> rgroups;
   DevBuf<InflowDesc> idesc;
   std::vector<RelaxGroup> igroups;  // (nv, m, first, count) over idesc
-  DevBuf<double> stats;             // 2 doubles per sweep workgroup
+  DevBuf<double> stats;             // 2 doubles per sweep workgroup (and per mixed-launch workgroup after them)
+  std::vector<int> item_cost;       // per item: its relative running time (longest first within a launch)
+  bool mixed = false;               // one launch for the items of every node count (uniform meshes)
+  DevBuf<SweepItem> smixed;         // those items, longest first
   const double *last_stats = nullptr;  // statistics written by the most recent sweep
   hipStream_t cap_stream = nullptr;
   // graph cache of the interior step
@@ -198,12 +215,16 @@ struct pdg_ctx {
     dtable.release();
     dtraces.release();
     dsync.release();
+    dtfams.release();
     derr.release();
     if (herr) (void)hipHostFree(herr);
     herr = nullptr;
     herr_dev = nullptr;
     dgroups.clear();
     stats.release();
+    smixed.release();
+    item_cost.clear();
+    mixed = false;
     if (cap_stream) (void)hipStreamDestroy(cap_stream);
     cap_stream = nullptr;
     groups.clear();
@@ -362,7 +383,7 @@ pdg_status from_hip_at(hipError_t e, const char *where) {
 pdg_status mesh_levels(const Instance &in, int vel, std::vector<int32_t> &level) {
   const int dim = in.d.dim;
   const int64_t nc = in.nc;
-  const double *v = &in.v[(size_t)vel * dim];
+  const double *v = &in.vt[(size_t)vel * dim];
   std::vector<int32_t> indeg(nc, 0);
   int64_t stride[3] = {1, in.n[0], in.n[0] * in.n[1]};
   auto coord = [&](int64_t c, int k) { return (c / stride[k]) % in.n[k]; };
@@ -435,10 +456,15 @@ void default_tile(LaunchClass &k) {
   }
 }
 
+// Chains along the contiguous axis run in the row kernel (one cell per
+// thread, tile S = 1) or, for tiles with S >= 2, in the segment mapping of the
+// strided chains (thread (c, p) owns S consecutive cells of row c).
+bool rows_mapping(const LaunchClass &k) { return k.x_kind == 1 && k.S == 1; }
+
 // Segment length of a strided family under its class tile: the smallest
 // power of two covering the chain in one window, capped by the class.
 int family_S(const LaunchClass &k, int n_a) {
-  if (k.x_kind == 1) return 1;
+  if (rows_mapping(k)) return 1;
   const int P = kBlock / k.C;
   int S = 1;
   while (S < k.S && P * S < n_a) S <<= 1;
@@ -449,6 +475,7 @@ int family_S(const LaunchClass &k, int n_a) {
 // workgroups first inside each launch, classes contiguous.
 void build_items(pdg_ctx *c, std::vector<SweepItem> &items) {
   items.clear();
+  c->item_cost.clear();
   std::vector<Group> groups;
   std::map<std::pair<int, bool>, int> group_of;
   for (LaunchClass &k : c->classes) {
@@ -469,8 +496,9 @@ void build_items(pdg_ctx *c, std::vector<SweepItem> &items) {
         if (&c->classes[fm.cls] != &k) continue;
         const int C = k.C;
         const int S = family_S(k, fm.n_a);
-        const int cost = fm.x_kind == 1 ? (int)((C * (int64_t)fm.n_a + kBlock - 1) / kBlock)
-                                        : ((fm.n_a + (kBlock / C) * S - 1) / ((kBlock / C) * S)) * S;
+        const bool rows = rows_mapping(k);
+        const int cost = rows ? (int)((C * (int64_t)fm.n_a + kBlock - 1) / kBlock)
+                              : ((fm.n_a + (kBlock / C) * S - 1) / ((kBlock / C) * S)) * S;
         for (int kk = 0; kk < fm.m; ++kk)
           for (int64_t t = 0; t < fm.tnodes; ++t) {
             const int64_t base = fm.f_vel + kk * fm.comp_stride + fm.plane_off[t];
@@ -482,9 +510,9 @@ void build_items(pdg_ctx *c, std::vector<SweepItem> &items) {
               item.desc = fm.desc;
               item.tau0 = (int32_t)tau0;
               item.count = (int32_t)std::min<int64_t>(C, fm.ntc - tau0);
-              item.C = (int16_t)(fm.x_kind == 1 ? 0 : C);
+              item.C = (int16_t)(rows ? 0 : C);
               item.S = (int8_t)S;
-              item.xk = (int8_t)fm.x_kind;
+              item.xk = (int8_t)(rows ? 1 : (fm.x_kind == 2 ? 2 : 0));
               list.push_back({cost, item});
             }
           }
@@ -495,7 +523,10 @@ void build_items(pdg_ctx *c, std::vector<SweepItem> &items) {
                        });
       k.first = (int64_t)items.size();
       k.count = (int64_t)list.size();
-      for (const auto &ci : list) items.push_back(ci.second);
+      for (const auto &ci : list) {
+        items.push_back(ci.second);
+        c->item_cost.push_back(ci.first);
+      }
     }
     groups[g].count = (int64_t)items.size() - groups[g].first;
   }
@@ -572,10 +603,19 @@ static pdg_status setup_mesh_impl(const pdg_instance_desc *descs, int32_t n_inst
     if (d.dim < 2 || d.dim > 3) err = PDG_EINVAL;
     else if (d.degree < 1 || d.nv < 1 || d.nv > kMaxNV || d.m < 1 || d.m > kMaxM || !d.v) err = PDG_EINVAL;
     if (err == PDG_OK && d.degree > 4) err = PDG_EUNSUPPORTED;
+    // an affine lattice: some non-zero entry among the D x D cell edge vectors
+    bool affine = false;
+    for (int k = 0; k < d.dim && err == PDG_OK; ++k)
+      for (int i = 0; i < d.dim; ++i) affine = affine || d.axes[3 * k + i] != 0.0;
     if (err == PDG_OK) {
       for (int k = 0; k < d.dim; ++k) {
         if (d.n[k] < 1) {
           err = PDG_EINVAL;
+        } else if (affine) {
+          // lattice from the corner lo; no graded edges, finite vectors
+          if (d.edges[k] || !is_finite(d.lo[k])) err = PDG_EINVAL;
+          for (int i = 0; i < d.dim; ++i)
+            if (!is_finite(d.axes[3 * k + i])) err = PDG_EINVAL;
         } else if (d.edges[k]) {
           // graded axis: n[k] + 1 strictly increasing finite edges
           for (int i = 0; i <= d.n[k] && err == PDG_OK; ++i)
@@ -603,6 +643,59 @@ static pdg_status setup_mesh_impl(const pdg_instance_desc *descs, int32_t n_inst
       if (!is_finite(x)) {
                 return PDG_EINVAL;
       }
+    // transport frame (see Instance) and physical axes of the velocities
+    in.affine = affine;
+    double ainv[3][3] = {{1, 0, 0}, {0, 1, 0}, {0, 0, 1}};
+    if (affine) {
+      for (int k = 0; k < d.dim; ++k)
+        for (int i = 0; i < d.dim; ++i) in.A[i][k] = d.axes[3 * k + i];
+      const double det = d.dim == 2 ? in.A[0][0] * in.A[1][1] - in.A[0][1] * in.A[1][0]
+                                    : in.A[0][0] * (in.A[1][1] * in.A[2][2] - in.A[1][2] * in.A[2][1]) -
+                                          in.A[0][1] * (in.A[1][0] * in.A[2][2] - in.A[1][2] * in.A[2][0]) +
+                                          in.A[0][2] * (in.A[1][0] * in.A[2][1] - in.A[1][1] * in.A[2][0]);
+      if (!(det > 0.0) || !is_finite(det)) return PDG_EINVAL;
+      if (d.dim == 2) {
+        ainv[0][0] = in.A[1][1] / det;
+        ainv[0][1] = -in.A[0][1] / det;
+        ainv[1][0] = -in.A[1][0] / det;
+        ainv[1][1] = in.A[0][0] / det;
+      } else {
+        for (int i = 0; i < 3; ++i)
+          for (int j = 0; j < 3; ++j) {
+            // adjugate: cofactor of A[j][i]
+            const int r0 = (j + 1) % 3, r1 = (j + 2) % 3, c0 = (i + 1) % 3, c1 = (i + 2) % 3;
+            ainv[i][j] = (in.A[r0][c0] * in.A[r1][c1] - in.A[r0][c1] * in.A[r1][c0]) / det;
+          }
+      }
+    }
+    in.vt.assign(in.v.size(), 0.0);
+    in.paxis.assign(d.nv, -1);
+    in.psign.assign(d.nv, 0);
+    for (int v = 0; v < d.nv; ++v) {
+      int nzp = 0;
+      for (int k = 0; k < d.dim; ++k) {
+        double acc = 0.0;
+        for (int i = 0; i < d.dim; ++i) acc += ainv[k][i] * in.v[(size_t)v * d.dim + i];
+        in.vt[(size_t)v * d.dim + k] = affine ? acc : in.v[(size_t)v * d.dim + k];
+        if (in.v[(size_t)v * d.dim + k] != 0.0) {
+          ++nzp;
+          in.paxis[v] = k;
+          in.psign[v] = in.v[(size_t)v * d.dim + k] > 0 ? 1 : -1;
+        }
+      }
+      if (nzp != 1) {
+        in.paxis[v] = -1;
+        in.psign[v] = 0;
+      }
+      if (affine) {
+        // a component that is zero up to the rounding of A^{-1} v is zero: the
+        // velocity then runs along index lines and keeps the line path
+        double vmax = 0.0;
+        for (int k = 0; k < d.dim; ++k) vmax = std::max(vmax, std::fabs(in.vt[(size_t)v * d.dim + k]));
+        for (int k = 0; k < d.dim; ++k)
+          if (std::fabs(in.vt[(size_t)v * d.dim + k]) <= 1e-13 * vmax) in.vt[(size_t)v * d.dim + k] = 0.0;
+      }
+    }
     in.nw = d.m;
     if (d.feq == PDG_FEQ_D2Q9) {
       // the D2Q9 lattice of Sec. 5.1: lambda x {0, +-e_x, +-e_y, (+-1, +-1)}, any order
@@ -635,7 +728,8 @@ static pdg_status setup_mesh_impl(const pdg_instance_desc *descs, int32_t n_inst
     in.nc = 1;
     for (int k = 0; k < 3; ++k) {
       in.n[k] = k < d.dim ? d.n[k] : 1;
-      in.h[k] = k < d.dim ? (d.hi[k] - d.lo[k]) / d.n[k] : 1.0;
+      in.h[k] = k < d.dim && !affine ? (d.hi[k] - d.lo[k]) / d.n[k] : 1.0;
+      in.ht[k] = in.h[k];
     }
     for (int k = 0; k < d.dim; ++k) {
       in.nd *= in.np;
@@ -655,7 +749,7 @@ static pdg_status setup_mesh_impl(const pdg_instance_desc *descs, int32_t n_inst
     for (int v = 0; v < d.nv; ++v) {
       int nz = 0, ax = -1;
       for (int k = 0; k < d.dim; ++k) {
-        const double comp = in.v[(size_t)v * d.dim + k];
+        const double comp = in.vt[(size_t)v * d.dim + k];
         if (comp != 0.0) {
           nz++;
           ax = k;
@@ -727,21 +821,33 @@ static pdg_status node_coords_impl(const pdg_ctx *c, int32_t inst, double *vol_x
   const int np = (int)in.np;
   std::vector<double> x, w;
   gauss_lobatto(in.d.degree, x, w);
+  // box meshes: coordinate along axis k; affine lattice: the index-frame
+  // coordinate s_k (cell index plus the node's place in the cell), mapped to
+  // physical space by phys() below
   auto pos = [&](int k, int64_t cell, int node) {
+    if (in.affine) return (double)cell + 0.5 * (x[node] + 1.0);
     if (in.graded[k]) {
       const double a = in.edge[k][cell], b = in.edge[k][cell + 1];
       return a + 0.5 * (x[node] + 1.0) * (b - a);
     }
     return in.d.lo[k] + ((double)cell + 0.5 * (x[node] + 1.0)) * in.h[k];
   };
+  auto phys = [&](int i, const double (&sk)[3]) {
+    double acc = in.d.lo[i];
+    for (int k = 0; k < dim; ++k) acc += in.A[i][k] * sk[k];
+    return acc;
+  };
   if (vol_xyz) {
     for (int k = 0; k < dim; ++k)
       for (int64_t j = 0; j < in.nd; ++j) {
-        int jk = (int)((j / (int64_t)std::pow(np, k)) % np);
         for (int64_t cc = 0; cc < in.nc; ++cc) {
-          int64_t stride = k == 0 ? 1 : (k == 1 ? in.n[0] : in.n[0] * in.n[1]);
-          int64_t ck = (cc / stride) % in.n[k];
-          vol_xyz[((int64_t)k * in.nd + j) * in.nc + cc] = pos(k, ck, jk);
+          double sk[3] = {0, 0, 0};
+          for (int k2 = 0; k2 < dim; ++k2) {
+            const int jk = (int)((j / (int64_t)std::pow(np, k2)) % np);
+            const int64_t stride = k2 == 0 ? 1 : (k2 == 1 ? in.n[0] : in.n[0] * in.n[1]);
+            sk[k2] = pos(k2, (cc / stride) % in.n[k2], jk);
+          }
+          vol_xyz[((int64_t)k * in.nd + j) * in.nc + cc] = in.affine ? phys(k, sk) : sk[k];
         }
       }
   }
@@ -759,16 +865,20 @@ static pdg_status node_coords_impl(const pdg_ctx *c, int32_t inst, double *vol_x
       for (int k = 0; k < dim; ++k)
         for (int64_t t = 0; t < tnodes; ++t)
           for (int64_t tau = 0; tau < ntc; ++tau) {
-            double val;
-            if (k == ax) {
-              val = in.sgn[v][ax] > 0 ? in.d.lo[k] : in.d.hi[k];
-            } else {
-              const int slot = (k == other[0]) ? 0 : 1;
-              const int node = slot == 0 ? (int)(t % np) : (int)(t / np);
-              const int64_t cell = slot == 0 ? tau % in.n[other[0]] : tau / in.n[other[0]];
-              val = pos(k, cell, node);
+            double sk[3] = {0, 0, 0};
+            for (int k2 = 0; k2 < dim; ++k2) {
+              if (k2 == ax) {
+                // the domain face the velocity enters through
+                sk[k2] = in.affine ? (in.sgn[v][ax] > 0 ? 0.0 : (double)in.n[ax])
+                                   : (in.sgn[v][ax] > 0 ? in.d.lo[k2] : in.d.hi[k2]);
+              } else {
+                const int slot = (k2 == other[0]) ? 0 : 1;
+                const int node = slot == 0 ? (int)(t % np) : (int)(t / np);
+                const int64_t cell = slot == 0 ? tau % in.n[other[0]] : tau / in.n[other[0]];
+                sk[k2] = pos(k2, cell, node);
+              }
             }
-            inflow_xyz[off + ((int64_t)k * tnodes + t) * ntc + tau] = val;
+            inflow_xyz[off + ((int64_t)k * tnodes + t) * ntc + tau] = in.affine ? phys(k, sk) : sk[k];
           }
       off += (int64_t)dim * tnodes * ntc;
     }
@@ -795,12 +905,12 @@ pdg_status pdg_line_operator(const pdg_ctx *c, int32_t inst, int32_t vel, double
   if (ax < 0) return PDG_EUNSUPPORTED;
   std::vector<double> gam;
   // graded axis: the block of the chain's first (upwind-most) cell
-  double h = in.h[ax];
+  double h = in.ht[ax];
   if (in.graded[ax]) {
     const int64_t first = in.sign[vel] > 0 ? 0 : in.n[ax] - 1;
     h = in.edge[ax][first + 1] - in.edge[ax][first];
   }
-  line_block(in.d.degree, std::fabs(in.v[(size_t)vel * in.d.dim + ax]), h, gam, *kappa);
+  line_block(in.d.degree, std::fabs(in.vt[(size_t)vel * in.d.dim + ax]), h, gam, *kappa);
   std::memcpy(gamma, gam.data(), gam.size() * sizeof(double));
   return PDG_OK;
 }
@@ -810,10 +920,18 @@ pdg_status pdg_cell_operator(const pdg_ctx *c, int32_t inst, int32_t vel, double
   const Instance &in = c->inst[inst];
   if (vel < 0 || vel >= in.d.nv) return PDG_EINVAL;
   std::vector<double> gam;
-  dense_block(in.d.dim, in.d.degree, &in.v[(size_t)vel * in.d.dim], in.h, gam, kappa);
+  dense_block(in.d.dim, in.d.degree, &in.vt[(size_t)vel * in.d.dim], in.ht, gam, kappa);
   std::memcpy(gamma, gam.data(), gam.size() * sizeof(double));
   return PDG_OK;
 }
+
+}  // extern "C"
+
+namespace {
+pdg_status upload_items(pdg_ctx *c, const std::vector<SweepItem> &items);
+}  // namespace
+
+extern "C" {
 
 static pdg_status prepare_impl(pdg_ctx *c, double dt, double theta, double omega, pdg_scheme scheme, pdg_precision prec,
                        void *stream) {
@@ -859,7 +977,7 @@ static pdg_status prepare_impl(pdg_ctx *c, double dt, double theta, double omega
     for (int v = 0; v < in.d.nv; ++v) {
       if (in.ndep[v] != 1) continue;  // zero velocity: identity; two or more components: dense path
       const int ax = in.axis[v];
-      const double V = std::fabs(in.v[(size_t)v * dim + ax]);
+      const double V = std::fabs(in.vt[(size_t)v * dim + ax]);
       // one operator row per sub-step; on a graded axis one per sub-step
       // and downwind position (rows [dt_idx][l], l = 0 upwind-most)
       const bool graded = in.graded[ax];
@@ -867,7 +985,7 @@ static pdg_status prepare_impl(pdg_ctx *c, double dt, double theta, double omega
       const int op_index = (int)ops.size();  // + dt_idx (* n_a + l when graded)
       for (double ds : dts)
         for (int64_t l = 0; l < npos; ++l) {
-          double h = in.h[ax];
+          double h = in.ht[ax];
           if (graded) {
             const int64_t phys = in.sign[v] > 0 ? l : in.n[ax] - 1 - l;
             h = in.edge[ax][phys + 1] - in.edge[ax][phys];
@@ -1038,8 +1156,11 @@ static pdg_status prepare_impl(pdg_ctx *c, double dt, double theta, double omega
       // operator rows: one per transport sub-step
       std::vector<double> gam;
       double kappa[3];
-      dense_block(dim, in.d.degree, &in.v[(size_t)v * dim], in.h, gam, kappa);
-      const int64_t stride_row = 4LL * N * N + 3LL * N * F;
+      dense_block(dim, in.d.degree, &in.vt[(size_t)v * dim], in.ht, gam, kappa);
+      // 2D velocities with two non-zero components also keep the transfer
+      // operator of a full tile (2TF x 2TF, T = 8)
+      const int64_t nr = 2LL * 8 * F;
+      const int64_t stride_row = 4LL * N * N + 3LL * N * F + (dim == 2 ? nr * nr : 0);
       dd.op_off = (int64_t)dtable.size();
       dd.op_stride = stride_row;
       const int desc_index = (int)ddesc.size();
@@ -1077,6 +1198,10 @@ static pdg_status prepare_impl(pdg_ctx *c, double dt, double theta, double omega
           fmd.fb_base = in.fb_off + in.fb_vel_off[v] + (int64_t)k * per_comp;
           fmd.desc = desc_index;
           fmd.slice = sl;
+          fmd.tile0 = (int32_t)dtile.size();  // global for now; group-local after sorting
+          fmd.nt[0] = ntile[0];
+          fmd.nt[1] = ntile[1];
+          fmd.pad = 0;
           const int fam_index = (int)dfam.size();
           dfam.push_back(fmd);
           dshape.push_back({np, dim});
@@ -1110,6 +1235,7 @@ static pdg_status prepare_impl(pdg_ctx *c, double dt, double theta, double omega
   std::vector<DenseTile> dtile_sorted;
   std::vector<int32_t> dorder;
   std::vector<DenseGroup> dgroups;
+  std::vector<int32_t> tfam;  // families of transfer-eligible groups
   int64_t sync_total = 0;
   {
     std::map<std::pair<int, int>, std::vector<int64_t>> by_shape;
@@ -1148,6 +1274,33 @@ static pdg_status prepare_impl(pdg_ctx *c, double dt, double theta, double omega
       }
       g.level.push_back(g.count);
     }
+    // families: group-local first tile; transfer eligibility per group (every
+    // family two-dimensional with full 8 x 8 tiles and diagonals of at most
+    // kTransferMaxDiag tiles)
+    std::vector<int> fam_group(dfam.size(), -1);
+    for (size_t gi = 0; gi < dgroups.size(); ++gi) dgroups[gi].transfer_ok = dgroups[gi].dim == 2;
+    for (size_t fi = 0; fi < dfam.size(); ++fi) {
+      DenseFam &fmd = dfam[fi];
+      const int64_t t0 = fmd.tile0;
+      for (size_t gi = 0; gi < dgroups.size(); ++gi)
+        if (new_index[t0] >= 0 && dshape[fi] == std::make_pair(dgroups[gi].np, dgroups[gi].dim)) {
+          fam_group[fi] = (int)gi;
+          break;
+        }
+      fmd.tile0 = (int32_t)new_index[t0];
+      const DenseDesc &dd = ddesc[fmd.desc];
+      const int gi = fam_group[fi];
+      if (gi < 0) continue;
+      const bool full = dd.n[0] % 8 == 0 && dd.n[1] % 8 == 0 && dd.sgn[0] != 0 && dd.sgn[1] != 0;
+      if (!full || std::min(fmd.nt[0], fmd.nt[1]) > 64) dgroups[gi].transfer_ok = false;
+    }
+    for (size_t gi = 0; gi < dgroups.size(); ++gi) {
+      dgroups[gi].tfam_first = (int64_t)tfam.size();
+      if (dgroups[gi].transfer_ok)
+        for (size_t fi = 0; fi < dfam.size(); ++fi)
+          if (fam_group[fi] == (int)gi) tfam.push_back((int32_t)fi);
+      dgroups[gi].tfam_count = (int64_t)tfam.size() - dgroups[gi].tfam_first;
+    }
   }
 
   // ---- relax tables --------------------------------------------------------
@@ -1183,15 +1336,15 @@ static pdg_status prepare_impl(pdg_ctx *c, double dt, double theta, double omega
       // the equilibrium needs the full {+-lambda e_k} set
       ok = in.d.nv == 2 * in.d.dim;
       for (int v = 0; v < in.d.nv; ++v)
-        if (in.axis[v] < 0) ok = false;
-      const double lam = ok ? std::fabs(in.v[(size_t)0 * in.d.dim + in.axis[0]]) : 0.0;
+        if (in.paxis[v] < 0) ok = false;
+      const double lam = ok ? std::fabs(in.v[(size_t)0 * in.d.dim + in.paxis[0]]) : 0.0;
       int seen[3][2] = {{0, 0}, {0, 0}, {0, 0}};
       for (int v = 0; v < in.d.nv && ok; ++v) {
-        const double sp = std::fabs(in.v[(size_t)v * in.d.dim + in.axis[v]]);
+        const double sp = std::fabs(in.v[(size_t)v * in.d.dim + in.paxis[v]]);
         if (sp != lam) ok = false;
-        rd.axis[v] = (int8_t)in.axis[v];
-        rd.sign[v] = (int8_t)in.sign[v];
-        seen[in.axis[v]][in.sign[v] > 0]++;
+        rd.axis[v] = (int8_t)in.paxis[v];
+        rd.sign[v] = (int8_t)in.psign[v];
+        seen[in.paxis[v]][in.psign[v] > 0]++;
       }
       for (int k = 0; k < in.d.dim && ok; ++k)
         if (seen[k][0] != 1 || seen[k][1] != 1) ok = false;
@@ -1247,12 +1400,16 @@ static pdg_status prepare_impl(pdg_ctx *c, double dt, double theta, double omega
   }
   PREP_TRY(c->ops.upload(ops))
   PREP_TRY(c->sdesc.upload(sdesc))
-  PREP_TRY(c->sitems.upload(items))
   PREP_TRY(c->rdesc.upload(rdesc))
   PREP_TRY(c->ritems.upload(ritems))
   PREP_TRY(c->idesc.upload(idesc_all))
-  std::vector<double> zeros(std::max<size_t>(2, 2 * items.size()), 0.0);
-  PREP_TRY(c->stats.upload(zeros))
+  {
+    const pdg_status us = upload_items(c, items);  // items, the mixed launch's order, statistics
+    if (us != PDG_OK) {
+      c->release_device();
+      return us;
+    }
+  }
   PREP_TRY(launch_invert(c->ops.p, (int)ops.size(), st))
   PREP_TRY(hipStreamSynchronize(st))
   c->ops_h.resize(ops.size());
@@ -1267,6 +1424,7 @@ static pdg_status prepare_impl(pdg_ctx *c, double dt, double theta, double omega
   PREP_TRY(c->dfams.upload(dfam))
   PREP_TRY(c->dtiles.upload(dtile_sorted))
   PREP_TRY(c->dorder.upload(dorder))
+  PREP_TRY(c->dtfams.upload(tfam))
   PREP_TRY(c->dtable.upload(dtable))
   PREP_TRY(c->dtraces.upload(std::vector<uint64_t>((size_t)trace_total, kDenseTraceEmpty)))
   PREP_TRY(c->dsync.upload(std::vector<int32_t>((size_t)sync_total, 0)))
@@ -1318,6 +1476,10 @@ static pdg_status prepare_impl(pdg_ctx *c, double dt, double theta, double omega
       PREP_TRY(d_rc.upload(rc))
       PREP_TRY(d_fl.upload(std::vector<int32_t>(ro.size(), 0)))
       PREP_TRY(launch_dense_invert(c->dtable.p, d_ro.p, c->ddesc.p, d_rd.p, d_rc.p, d_fl.p, (int)ro.size(), n2, F2, st))
+      // transfer operators of full tiles (two-dimensional velocities), from
+      // the blocks just inverted
+      if (dim2 == 2)
+        PREP_TRY(launch_dense_transfer_operator(np2, c->dtable.p, d_ro.p, c->ddesc.p, d_rd.p, (int)ro.size(), st))
       PREP_TRY(hipStreamSynchronize(st))
       std::vector<int32_t> fl(ro.size());
       PREP_TRY(hipMemcpy(fl.data(), d_fl.p, fl.size() * sizeof(int32_t), hipMemcpyDeviceToHost))
@@ -1344,19 +1506,24 @@ static pdg_status prepare_impl(pdg_ctx *c, double dt, double theta, double omega
   c->tau = tau;
   c->scheme = scheme;
   c->prec = prec;
-  // Dense-tile schedule per kernel shape: claimed tiles (one launch, traces
-  // handed over between running tiles) except for the 8-node cells of 3D
-  // degree 1, whose 4 x 4 x 4 tiles finish faster than a hand-over through
-  // the device-scope atomics (measured on 2D and 3D meshes), so one launch
-  // per tile diagonal serves them better.  PDG_DENSE_SCHEDULE=level or claim
-  // forces one schedule for every shape.
+  // Dense-tile schedule per launch group: the transfer schedule (three
+  // launches that never wait: tiles with zero upwind inflow, the trace
+  // wavefront on MFMA, tiles with their exact inflow) for two-dimensional
+  // groups whose families all have full tiles; otherwise claimed tiles (one
+  // launch, traces handed over between running tiles) except for the 8-node
+  // cells of 3D degree 1, whose 4 x 4 x 4 tiles finish faster than a
+  // hand-over through the device-scope atomics (measured on 2D and 3D
+  // meshes), so one launch per tile diagonal serves them better.
+  // PDG_DENSE_SCHEDULE=level, claim or transfer forces one schedule (transfer
+  // only where a group allows it).
   {
     const char *ds = std::getenv("PDG_DENSE_SCHEDULE");
     const bool force_level = ds && std::strcmp(ds, "level") == 0;
     const bool force_claim = ds && std::strcmp(ds, "claim") == 0;
     c->dense_claim = false;
     for (DenseGroup &g : c->dgroups) {
-      g.claim = force_claim || (!force_level && !(g.dim == 3 && g.np == 2));
+      g.transfer = g.transfer_ok && !force_level && !force_claim;
+      g.claim = !g.transfer && (force_claim || (!force_level && !(g.dim == 3 && g.np == 2)));
       c->dense_claim = c->dense_claim || g.claim;
     }
   }
@@ -1392,7 +1559,13 @@ SweepScratch ctx_scratch(pdg_ctx *c) { return SweepScratch{c->stats.p, c->dtrace
 
 pdg_status do_sweep(pdg_ctx *c, void *f, const double *fb_old, const double *fb_new, int dt_idx,
                     hipStream_t st, const SweepScratch &sc) {
+  if (c->mixed) {
+    hipError_t e = launch_sweep_mixed(c->prec, c->smixed.p, (int)c->smixed.n, c->sdesc.p, c->ops.p, dt_idx,
+                                      StateBuf{f, c->f_elems}, fb_old, fb_new, sc.stats + 2 * c->sitems.n, st);
+    if (e != hipSuccess) return from_hip_at(e, "launch_sweep_mixed");
+  }
   for (const Group &g : c->groups) {
+    if (c->mixed && !g.graded) continue;
     hipError_t e = launch_sweep(c->prec, g.np, g.graded, g.wpos, c->sitems.p + g.first, (int)g.count, c->sdesc.p, c->ops.p, dt_idx, StateBuf{f, c->f_elems},
                                 fb_old, fb_new, sc.stats + 2 * g.first, st);
     if (e != hipSuccess) {
@@ -1409,10 +1582,27 @@ pdg_status do_sweep(pdg_ctx *c, void *f, const double *fb_old, const double *fb_
     if (e != hipSuccess) return from_hip_at(e, "dense sweep reset");
   }
   for (const DenseGroup &g : c->dgroups) {
+    if (g.transfer) {
+      // zero-inflow tiles (their outflow traces Z into the downwind slots), the
+      // trace wavefront (slots: Z -> exact traces), tiles with exact inflow
+      hipError_t e = launch_dense_sweep(c->prec, kDenseZero, g.np, g.dim, c->dtiles.p + g.first, c->dorder.p + g.first,
+                                        (int)g.count, c->dfams.p, c->ddesc.p, c->dtable.p, dt_idx,
+                                        StateBuf{f, c->f_elems}, fb_old, fb_new, sc.traces, sc.sync + g.sync_off,
+                                        dense_err(c), st);
+      if (e == hipSuccess)
+        e = launch_dense_transfer(g.np, c->dtiles.p + g.first, c->dfams.p, c->dtfams.p + g.tfam_first,
+                                  (int)g.tfam_count, c->ddesc.p, c->dtable.p, dt_idx, sc.traces, st);
+      if (e == hipSuccess)
+        e = launch_dense_sweep(c->prec, kDenseFinal, g.np, g.dim, c->dtiles.p + g.first, c->dorder.p + g.first,
+                               (int)g.count, c->dfams.p, c->ddesc.p, c->dtable.p, dt_idx, StateBuf{f, c->f_elems},
+                               fb_old, fb_new, sc.traces, sc.sync + g.sync_off, dense_err(c), st);
+      if (e != hipSuccess) return from_hip_at(e, "dense transfer schedule");
+      continue;
+    }
     if (!g.claim) {
       // one launch per tile diagonal: no tile ever waits
       for (size_t k = 0; k + 1 < g.level.size(); ++k) {
-        hipError_t e = launch_dense_sweep(c->prec, true, g.np, g.dim, c->dtiles.p + g.first,
+        hipError_t e = launch_dense_sweep(c->prec, kDenseLevel, g.np, g.dim, c->dtiles.p + g.first,
                                           c->dorder.p + g.first + g.level[k], (int)(g.level[k + 1] - g.level[k]),
                                           c->dfams.p, c->ddesc.p, c->dtable.p, dt_idx, StateBuf{f, c->f_elems}, fb_old, fb_new,
                                           sc.traces, sc.sync + g.sync_off, dense_err(c), st);
@@ -1420,7 +1610,7 @@ pdg_status do_sweep(pdg_ctx *c, void *f, const double *fb_old, const double *fb_
       }
       continue;
     }
-    hipError_t e = launch_dense_sweep(c->prec, false, g.np, g.dim, c->dtiles.p + g.first, c->dorder.p + g.first,
+    hipError_t e = launch_dense_sweep(c->prec, kDenseClaim, g.np, g.dim, c->dtiles.p + g.first, c->dorder.p + g.first,
                                       (int)g.count, c->dfams.p, c->ddesc.p, c->dtable.p, dt_idx, StateBuf{f, c->f_elems}, fb_old, fb_new,
                                       sc.traces, sc.sync + g.sync_off, dense_err(c), st);
     if (e != hipSuccess) return from_hip_at(e, "launch_dense_sweep");
@@ -1510,7 +1700,7 @@ pdg_status pdg_transport_sweep_static(pdg_ctx *c, void *f, const double *fb_old,
   }
   // [stats: 2 doubles per work item][trace slots][claim counters], 256-byte aligned parts
   auto up = [](size_t b) { return (b + 255) / 256 * 256; };
-  const size_t b_stats = up(2 * c->sitems.n * sizeof(double));
+  const size_t b_stats = up(2 * (c->sitems.n + c->smixed.n) * sizeof(double));
   const size_t b_traces = up(c->dtraces.n * sizeof(uint64_t));
   const size_t b_sync = up(c->dgroups.size() * sizeof(int32_t));
   if (b_stats + b_traces + b_sync > kStaticScratchBytes) {
@@ -1680,8 +1870,25 @@ namespace {
 pdg_status upload_items(pdg_ctx *c, const std::vector<SweepItem> &items) {
   hipError_t e = c->sitems.upload(items);
   if (e != hipSuccess) return from_hip_at(e, "upload items");
-  if (c->stats.n < 2 * items.size()) {
-    std::vector<double> zeros(2 * items.size(), 0.0);
+  // the mixed launch: every uniform-mesh item, longest first across node counts
+  int n_uniform_groups = 0;
+  for (const Group &g : c->groups) n_uniform_groups += g.graded ? 0 : 1;
+  const char *mx = std::getenv("PDG_SWEEP_MIXED");
+  c->mixed = n_uniform_groups >= 2 && !(mx && std::strcmp(mx, "0") == 0);
+  std::vector<SweepItem> mixed_items;
+  if (c->mixed) {
+    std::vector<std::pair<int, int64_t>> order;
+    for (const Group &g : c->groups)
+      if (!g.graded)
+        for (int64_t i = g.first; i < g.first + g.count; ++i) order.push_back({c->item_cost[i], i});
+    std::stable_sort(order.begin(), order.end(),
+                     [](const std::pair<int, int64_t> &a, const std::pair<int, int64_t> &b) { return a.first > b.first; });
+    for (const auto &o : order) mixed_items.push_back(items[o.second]);
+  }
+  e = c->smixed.upload(mixed_items);
+  if (e != hipSuccess) return from_hip_at(e, "upload mixed items");
+  if (c->stats.n < std::max<size_t>(2, 2 * (items.size() + mixed_items.size()))) {
+    std::vector<double> zeros(std::max<size_t>(2, 2 * (items.size() + mixed_items.size())), 0.0);
     e = c->stats.upload(zeros);
     if (e != hipSuccess) return from_hip_at(e, "upload stats");
   }
@@ -1694,7 +1901,7 @@ pdg_status upload_items(pdg_ctx *c, const std::vector<SweepItem> &items) {
 
 bool tile_valid(const LaunchClass &k, int C, int S) {
   if (C < 1 || C > kBlock || S < 1 || S > class_smax(k.np, k.x_kind)) return false;
-  if (k.x_kind == 1) return (int64_t)C * k.n_max < 65536 && S == 1;
+  if (k.x_kind == 1 && S == 1) return (int64_t)C * k.n_max < 65536;
   return kBlock % C == 0;
 }
 
@@ -1715,6 +1922,9 @@ static pdg_status autotune_impl(pdg_ctx *c, void *f, const double *fb, int32_t r
     std::vector<std::pair<int, int>> cands;
     if (k.x_kind == 1) {
       for (int C = 1; C <= 64; C <<= 1) cands.push_back({C, 1});
+      // the segment mapping too: rows of C lanes' chains, S cells per thread
+      for (int C = 8; C <= 64; C <<= 1)
+        for (int S = 2; S <= class_smax(k.np, k.x_kind); S <<= 1) cands.push_back({C, S});
     } else {
       for (int C = 8; C <= 64; C <<= 1)
         for (int S = 1; S <= class_smax(k.np, k.x_kind); S <<= 1) cands.push_back({C, S});
@@ -1802,7 +2012,7 @@ static pdg_status last_refine_correction_impl(const pdg_ctx *c, double *max_rel_
   if (!c->prepared || !c->stats_valid) return PDG_ESTATE;
   hipError_t e = hipStreamSynchronize(c->last_stream);
   if (e != hipSuccess) return from_hip(e);
-  std::vector<double> h(2 * c->sitems.n);
+  std::vector<double> h(2 * (c->sitems.n + c->smixed.n));
   e = hipMemcpy(h.data(), c->last_stats, h.size() * sizeof(double), hipMemcpyDeviceToHost);
   if (e != hipSuccess) return from_hip(e);
   double cm = 0.0, ym = 0.0;

@@ -145,6 +145,9 @@ struct DenseFam {
   int64_t fb_base;  // fb offset of (instance, v, k)
   int32_t desc;
   int32_t slice;    // cell index along trans_axis (0 if none)
+  int32_t tile0;    // launch-group index of the family's first tile (tiles follow with t0 fastest)
+  int32_t nt[2];    // tiles along the first two axes
+  int32_t pad;
 };
 
 // One tile of a dense sweep.
@@ -178,6 +181,12 @@ hipError_t launch_invert(OpEntry *ops, int n_ops, hipStream_t st);
 hipError_t launch_sweep(int prec, int np, bool graded, bool wpos, const SweepItem *items, int n_items,
                         const SweepDesc *descs, const OpEntry *ops, int dt_idx, StateBuf f, const double *fb_old,
                         const double *fb_new, double *stats, hipStream_t st);
+
+// One launch over uniform-mesh items of any node count (each workgroup
+// dispatches on its item's node count).
+hipError_t launch_sweep_mixed(int prec, const SweepItem *items, int n_items, const SweepDesc *descs,
+                              const OpEntry *ops, int dt_idx, StateBuf f, const double *fb_old,
+                              const double *fb_new, double *stats, hipStream_t st);
 
 // Relax / equilibrium launch for items whose instances share (nv, m).
 hipError_t launch_relax(int prec, int nv, int m, const RelaxItem *items, int n_items, const RelaxDesc *descs,
@@ -220,9 +229,25 @@ struct DenseErr {
   uint64_t wait_ticks;
 };
 
-// Dense sweep of n_tiles tiles (claim order `order`); counter and flags must be
-// zero on entry.
-hipError_t launch_dense_sweep(int prec, bool level, int np, int dim, const DenseTile *tiles, const int32_t *order,
+// Transfer operators R of full tiles (two-dimensional dense velocities), one
+// per operator row listed (row_off, row_desc), after launch_dense_invert.
+hipError_t launch_dense_transfer_operator(int np, double *table, const int64_t *row_off, const DenseDesc *descs,
+                                          const int32_t *row_desc, int n_rows, hipStream_t st);
+// Trace wavefront of the transfer schedule for the families fam_list[0..n)
+// of one launch group (tiles: the group's tile array).
+hipError_t launch_dense_transfer(int np, const DenseTile *tiles, const DenseFam *fams, const int32_t *fam_list,
+                                 int n_fams, const DenseDesc *descs, const double *table, int dt_idx,
+                                 uint64_t *traces, hipStream_t st);
+
+// Modes of the dense tile kernel (see pdg_dense.hip): claimed tiles in one
+// launch, one launch per tile diagonal, and the two tile passes of the
+// transfer schedule (tiles with zero upwind-tile inflow storing only their
+// outflow traces; tiles with their exact inflow storing only their cells).
+enum DenseMode { kDenseClaim = 0, kDenseLevel = 1, kDenseZero = 2, kDenseFinal = 3 };
+
+// Dense sweep of n_tiles tiles (claim order `order`) in the given mode; for
+// kDenseClaim the counter and the trace slots must be reset on entry.
+hipError_t launch_dense_sweep(int prec, int mode, int np, int dim, const DenseTile *tiles, const int32_t *order,
                               int n_tiles, const DenseFam *fams, const DenseDesc *descs, const double *table,
                               int dt_idx, StateBuf f, const double *fb_old, const double *fb_new, uint64_t *traces,
                               int32_t *counter, DenseErr err, hipStream_t st);

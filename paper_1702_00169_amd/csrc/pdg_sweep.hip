@@ -256,18 +256,16 @@ __device__ __forceinline__ void sweep_rows(const SweepItem &it, const SweepDesc 
   }
 }
 
+// One work item of the uniform-mesh sweep (chains of one family); the LDS
+// buffers belong to the calling kernel, stats to this workgroup (2 doubles).
 template <int PREC, int NP, int SMAX>
-__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(3))) void sweep_kernel(const SweepItem *__restrict__ items,
-                                                      const SweepDesc *__restrict__ descs,
-                                                      const OpEntry *__restrict__ ops, int dt_idx,
-                                                      const State<PREC> f,
-                                                      const double *__restrict__ fb_old,
-                                                      const double *__restrict__ fb_new,
-                                                      double *__restrict__ stats) {
+__device__ __forceinline__ void sweep_item(const SweepItem &it, const SweepDesc *__restrict__ descs,
+                                           const OpEntry *__restrict__ ops, int dt_idx, const State<PREC> f,
+                                           const double *__restrict__ fb_old, const double *__restrict__ fb_new,
+                                           double *__restrict__ stats, typename Pol<PREC>::Rt (*xa)[kBlock],
+                                           typename Pol<PREC>::Rt (*xb)[kBlock], typename Pol<PREC>::Rt (*wtot)[4],
+                                           int (*wopen)[4]) {
   using Rt = typename Pol<PREC>::Rt;
-  __shared__ Rt xa[2][kBlock];
-  __shared__ Rt xb[2][kBlock];
-  const SweepItem it = items[blockIdx.x];
   const SweepDesc d = descs[it.desc];
   CellOp<PREC, NP> op;
   op.load(ops[d.op + dt_idx]);
@@ -278,8 +276,6 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(3))) voi
   double cmax = 0.0, ymax = 0.0;
 
   if (it.xk) {
-    __shared__ Rt wtot[2][4];
-    __shared__ int wopen[2][4];
     sweep_rows<PREC, NP>(it, d, op, f, fb_old, fb_new, wtot, wopen, cmax, ymax);
   } else {
   // chains along a strided axis: thread (c, p) owns segment p of chain c
@@ -370,9 +366,46 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(3))) voi
       __syncthreads();
     }
     if (t == 0) {
-      stats[2 * (int64_t)blockIdx.x] = red[0];
-      stats[2 * (int64_t)blockIdx.x + 1] = red[kBlock];
+      stats[0] = red[0];
+      stats[1] = red[kBlock];
     }
+  }
+}
+
+template <int PREC, int NP, int SMAX>
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(3))) void sweep_kernel(
+    const SweepItem *__restrict__ items, const SweepDesc *__restrict__ descs, const OpEntry *__restrict__ ops,
+    int dt_idx, const State<PREC> f, const double *__restrict__ fb_old, const double *__restrict__ fb_new,
+    double *__restrict__ stats) {
+  using Rt = typename Pol<PREC>::Rt;
+  __shared__ Rt xa[2][kBlock];
+  __shared__ Rt xb[2][kBlock];
+  __shared__ Rt wtot[2][4];
+  __shared__ int wopen[2][4];
+  sweep_item<PREC, NP, SMAX>(items[blockIdx.x], descs, ops, dt_idx, f, fb_old, fb_new, stats + 2 * (int64_t)blockIdx.x,
+                             xa, xb, wtot, wopen);
+}
+
+// The items of every node count in one launch (batches of instances of
+// different degrees): each workgroup dispatches on its item's node count, so
+// the launch has one tail instead of one per node count.
+template <int PREC>
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(3))) void sweep_mixed_kernel(
+    const SweepItem *__restrict__ items, const SweepDesc *__restrict__ descs, const OpEntry *__restrict__ ops,
+    int dt_idx, const State<PREC> f, const double *__restrict__ fb_old, const double *__restrict__ fb_new,
+    double *__restrict__ stats) {
+  using Rt = typename Pol<PREC>::Rt;
+  __shared__ Rt xa[2][kBlock];
+  __shared__ Rt xb[2][kBlock];
+  __shared__ Rt wtot[2][4];
+  __shared__ int wopen[2][4];
+  const SweepItem it = items[blockIdx.x];
+  double *st = stats + 2 * (int64_t)blockIdx.x;
+  switch (ops[descs[it.desc].op].np) {
+    case 2: sweep_item<PREC, 2, sweep_smax(2)>(it, descs, ops, dt_idx, f, fb_old, fb_new, st, xa, xb, wtot, wopen); break;
+    case 3: sweep_item<PREC, 3, sweep_smax(3)>(it, descs, ops, dt_idx, f, fb_old, fb_new, st, xa, xb, wtot, wopen); break;
+    case 4: sweep_item<PREC, 4, sweep_smax(4)>(it, descs, ops, dt_idx, f, fb_old, fb_new, st, xa, xb, wtot, wopen); break;
+    default: sweep_item<PREC, 5, sweep_smax(5)>(it, descs, ops, dt_idx, f, fb_old, fb_new, st, xa, xb, wtot, wopen); break;
   }
 }
 
@@ -603,6 +636,26 @@ hipError_t go_sweep_np(bool graded, bool wpos, int np, const SweepItem *items, i
 hipError_t launch_invert(OpEntry *ops, int n_ops, hipStream_t st) {
   if (n_ops <= 0) return hipSuccess;
   hipLaunchKernelGGL(invert_kernel, dim3((n_ops + 63) / 64), dim3(64), 0, st, ops, n_ops);
+  return hipGetLastError();
+}
+
+hipError_t launch_sweep_mixed(int prec, const SweepItem *items, int n_items, const SweepDesc *descs,
+                              const OpEntry *ops, int dt_idx, StateBuf f, const double *fb_old,
+                              const double *fb_new, double *stats, hipStream_t st) {
+  if (n_items <= 0) return hipSuccess;
+#define PDG_MIXED_CASE(PR)                                                                                   \
+  case PR:                                                                                                   \
+    hipLaunchKernelGGL(sweep_mixed_kernel<PR>, dim3(n_items), dim3(kBlock), 0, st, items, descs, ops, dt_idx, \
+                       State<PR>::make(f), fb_old, fb_new, stats);                                           \
+    break;
+  switch (prec) {
+    PDG_MIXED_CASE(kF64)
+    PDG_MIXED_CASE(kF32)
+    PDG_MIXED_CASE(kRefine)
+    PDG_MIXED_CASE(kP48)
+    default: return hipErrorInvalidValue;
+  }
+#undef PDG_MIXED_CASE
   return hipGetLastError();
 }
 

@@ -20,7 +20,7 @@ def inst_dict(inst):
         par = [inst.feq_param["gamma"]]
     return dict(dim=inst.dim, n=list(inst.n), degree=inst.degree, v=np.asarray(inst.vel, float), m=inst.m,
                 lo=list(inst.lo), hi=list(inst.hi), feq=inst.feq_kind, feq_param=par,
-                edges=getattr(inst, "edges", None))
+                edges=getattr(inst, "edges", None), axes=getattr(inst, "axes", None))
 
 
 def oracle_problem(inst):
@@ -29,7 +29,7 @@ def oracle_problem(inst):
         edges = [np.asarray(e, float) if e is not None else np.linspace(inst.lo[k], inst.hi[k], inst.n[k] + 1)
                  for k, e in enumerate(edges)]
     return ost.Problem(inst.n, inst.lo, inst.hi, inst.degree, inst.vel, inst.m, inst.feq_kind, inst.feq_param,
-                       edges)
+                       edges, getattr(inst, "axes", None))
 
 
 def sizes(inst):
@@ -38,12 +38,24 @@ def sizes(inst):
     return nc, nd
 
 
+def index_velocity(inst, v):
+    """Velocity v in the frame of the cell index axes: A^{-1} v on an affine
+    lattice of edge vectors A (columns), v itself on a box mesh."""
+    axes = getattr(inst, "axes", None)
+    vel = np.asarray(inst.vel[v], float)
+    if axes is None:
+        return vel
+    vt = np.linalg.solve(np.asarray(axes, float), vel)
+    return np.where(np.abs(vt) <= 1e-13 * np.max(np.abs(vt)), 0.0, vt)   # rounding-level components are zero
+
+
 def inflow_faces(inst, v):
     """[(axis, tnodes, ntc)] of the inflow face blocks of velocity v (one per
-    non-zero component, increasing axis)."""
+    non-zero component in the index frame, increasing axis)."""
     nc, _ = sizes(inst)
     tn = (inst.degree + 1) ** (inst.dim - 1)
-    return [(a, tn, nc // inst.n[a]) for a in range(inst.dim) if inst.vel[v][a] != 0]
+    vt = index_velocity(inst, v)
+    return [(a, tn, nc // inst.n[a]) for a in range(inst.dim) if vt[a] != 0]
 
 
 def gpu_inflow_points(prob, i, inst):

@@ -403,3 +403,87 @@ def test_dense_velocity_on_a_graded_axis_is_unsupported(lib):
     prob = lib.Problem([_desc(n=[5, 3], v=[[1.0, 1.0], [1.0, 0.0]], edges=edges)])
     assert lib._lib.pdg_prepare(prob.ctx, 0.01, 0.5, 2.0, 2, 0, None) == lib.PDG_EUNSUPPORTED
     prob.close()
+
+
+# ---- uniform affine lattices (every cell the same parallelogram / parallelepiped)
+AFFINE = [
+    (2, (4, 3), 2, [[0.25, 0.10], [0.0, 0.30]]),
+    (2, (3, 4), 3, [[0.30, 0.0], [-0.08, 0.25]]),
+    (3, (3, 2, 3), 1, [[0.3, 0.1, 0.0], [0.0, 0.4, 0.05], [0.0, 0.0, 0.3]]),
+]
+
+
+@pytest.mark.parametrize("dim,n,degree,axes", AFFINE)
+def test_affine_coordinates_and_levels_match_oracle(lib, dim, n, degree, axes):
+    axes = np.array(axes)
+    lo = np.array([0.1, -0.2, 0.3][:dim])
+    vel = np.vstack([np.eye(dim), -np.eye(dim), [[0.6, -0.8, 0.3][:dim]]])
+    prob = lib.Problem([_desc(dim=dim, n=list(n), degree=degree, v=vel, lo=list(lo), hi=[0.0] * dim, axes=axes)])
+    m = omesh.Mesh(n, lo, None, degree, axes=axes)
+    vol, inflow = prob.node_coords(0)
+    np.testing.assert_allclose(np.transpose(vol, (2, 1, 0)), m.node_coords(), atol=1e-14)
+    off = 0
+    for v in range(vel.shape[0]):
+        ent = otr.inflow_entries(m, vel[v])
+        # one block [D][t][tau] per index axis along which A^{-1} v is non-zero
+        vt = np.linalg.solve(axes, vel[v])
+        blocks = []
+        for a in range(dim):
+            if vt[a] == 0:
+                continue
+            npts = (degree + 1) ** (dim - 1) * (m.nc // n[a])
+            blocks.append(inflow[off:off + dim * npts].reshape(dim, npts).T)
+            off += dim * npts
+        pts = np.concatenate(blocks)
+        a = pts[np.lexsort(np.round(pts, 12).T[::-1])]
+        b = ent["coords"][np.lexsort(np.round(ent["coords"], 12).T[::-1])]
+        np.testing.assert_allclose(a, b, atol=1e-14)
+        lev = np.zeros(m.nc, np.int32)
+        lib.pdg_levels(prob.ctx, 0, v, lev)
+        assert np.array_equal(lev, otr.topological_levels(m, vel[v]))
+    prob.close()
+
+
+@pytest.mark.parametrize("dim,n,degree,axes", AFFINE)
+@pytest.mark.parametrize("vel", [(1.0, 0.0, 0.0), (0.0, -1.0, 0.0), (0.7, 0.7, -0.2)])
+def test_affine_cell_operator_is_the_oracle_block(lib, dim, n, degree, axes, vel):
+    """The block of the index frame (velocity A^{-1} v on unit cells), in
+    downwind-local order, equals the oracle's block of the affine cell."""
+    axes = np.array(axes)
+    v = np.array(vel[:dim])
+    prob = lib.Problem([_desc(dim=dim, n=list(n), degree=degree, v=[list(v)], lo=[0.0] * dim, hi=[0.0] * dim,
+                              axes=axes)])
+    npn = degree + 1
+    nd = npn ** dim
+    gam = np.zeros(nd * nd)
+    kap = np.zeros(3)
+    lib.pdg_cell_operator(prob.ctx, 0, 0, gam, kap)
+    m = omesh.Mesh(n, np.zeros(dim), None, degree, axes=axes)
+    blk = otr.cell_blocks(m, v, np.array([1]))
+    vt = np.linalg.solve(axes, v)
+    idx = m.node_idx
+    q = np.zeros(nd, dtype=np.int64)
+    for i in range(nd):
+        for a in range(dim):
+            qa = idx[i, a] if vt[a] >= 0 else degree - idx[i, a]
+            q[i] += qa * npn ** a
+    np.testing.assert_allclose(gam.reshape(nd, nd)[np.ix_(q, q)], blk.gll[0], rtol=1e-12,
+                               atol=1e-12 * np.abs(blk.gll[0]).max())
+    for fc in blk.faces:
+        a = fc["axis"]
+        if vt[a] == 0 or fc["side"] != (-1 if vt[a] > 0 else 1):
+            continue
+        np.testing.assert_allclose(fc["coef"][0], -kap[a], rtol=1e-12)
+    prob.close()
+
+
+@pytest.mark.parametrize("kw", [
+    dict(axes=[[0.0, 1.0], [1.0, 0.0]]),                         # negative determinant
+    dict(axes=[[1.0, 2.0], [0.5, 1.0]]),                         # singular
+    dict(axes=[[float("nan"), 0.0], [0.0, 1.0]]),
+    dict(axes=[[1.0, 0.0], [0.0, 1.0]], edges=[[0.0, 0.5, 1.0, 2.0, 3.0], None]),   # with graded edges
+])
+def test_affine_lattice_is_validated(lib, kw):
+    with pytest.raises(lib.PdgError) as ei:
+        lib.pdg_setup_mesh([_desc(**kw)])
+    assert ei.value.status == lib.PDG_EINVAL

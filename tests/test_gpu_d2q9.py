@@ -218,14 +218,15 @@ def test_hydrostatic_run_matches_oracle_and_converges_at_second_order(lib):
     assert 1.8 <= rate <= 2.3
 
 
-@pytest.mark.parametrize("schedule", ["level", "claim"])
+@pytest.mark.parametrize("schedule", ["level", "claim", "transfer"])
 def test_gravity_graph_replay_equals_eager(lib, monkeypatch, schedule):
-    """The captured step (dense tiles with their fill kernels, chains, the
-    S C S node kernel) replays to the same bits as the eager launches."""
+    """The captured step (dense tiles with their fill kernels, or the three
+    launches of the transfer schedule; chains; the S C S node kernel) replays
+    to the same bits as the eager launches."""
     torch = pytest.importorskip("torch")
     print(f"d2q9 graph replay schedule={schedule}", flush=True)
     monkeypatch.setenv("PDG_DENSE_SCHEDULE", schedule)
-    inst = _inst(n=(20, 13), degree=2)
+    inst = _inst(n=(24, 16) if schedule == "transfer" else (20, 13), degree=2)
     outs = []
     for no_graph in (False, True):
         if no_graph:

@@ -26,6 +26,13 @@ CASES = [
     ("d3q27_9x7x5_d1", 3, (9, 7, 5), 1, D3Q27, 1),
     ("d3q27_6x5x7_d2_m2", 3, (6, 5, 7), 2, D3Q27 * 0.8, 2),
     ("d3q27_12x9x10_d2", 3, (12, 9, 10), 2, D3Q27, 1),
+    # full 8 x 8 tiles (the transfer schedule applies): every degree, and a
+    # diagonal longer than 16 tiles (two column blocks of the trace wavefront)
+    ("d2q9_32x24_d1_m2", 2, (32, 24), 1, D2Q9 * 1.1, 2),
+    ("d2q9_16x40_d2", 2, (16, 40), 2, D2Q9, 1),
+    ("d2q9_24x16_d3", 2, (24, 16), 3, D2Q9 * 0.9, 1),
+    ("d2q9_16x16_d4_m2", 2, (16, 16), 4, D2Q9, 2),
+    ("d2q9_144x136_d1", 2, (144, 136), 1, D2Q9, 1),
 ]
 BARS = {0: 1e-12, 2: 1e-10, 1: 2e-5}
 
@@ -77,11 +84,14 @@ def _run(lib, torch, case, prec, theta=0.5, half=False, seed=0):
     return rel_errors(got, want), per_v
 
 
-@pytest.fixture(params=["level", "claim"])
+@pytest.fixture(params=["level", "claim", "transfer"])
 def schedule(request, monkeypatch):
-    """Dense-tile schedule: one launch per tile diagonal, or one launch whose
+    """Dense-tile schedule: one launch per tile diagonal; one launch whose
     tiles are claimed in dependency order and hand traces over through
-    atomics.  Read by the library when a problem is prepared."""
+    atomics; or the transfer schedule (zero-inflow tiles, trace wavefront on
+    MFMA, final tiles), which applies to 2D meshes of full 8 x 8 tiles and
+    leaves the others to the default schedule.  Read by the library when a
+    problem is prepared."""
     monkeypatch.setenv("PDG_DENSE_SCHEDULE", request.param)
     return request.param
 

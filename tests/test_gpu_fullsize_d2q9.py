@@ -3,9 +3,9 @@
 
 Transport: one sweep of every velocity on the whole domain is compared with
 the oracle's level sweep of the whole domain, cell by cell: the dense tiled
-sweep of the four diagonal velocities (1024 tiles each, under the claimed
-schedule that hands traces between running tiles, and under the levelled
-one), the chain kernel of the four axis velocities and the identity of the
+sweep of the four diagonal velocities (1024 tiles each, under the transfer
+schedule that the library picks for this mesh, the claimed schedule that
+hands traces between running tiles, and the levelled one), the chain kernel of the four axis velocities and the identity of the
 rest velocity.
 
 Node-local step: S(dt/2) C S(dt/2) is compared on every node.
@@ -43,9 +43,10 @@ def oracle_sweep():
     return out
 
 
-@pytest.mark.parametrize("prec,schedule", [(0, "claim"), (2, "claim"), (3, "claim"), (0, "level"), (3, "level")],
-                         ids=["fp64-claim", "fp32refine-claim", "fp32refine48-claim", "fp64-level",
-                              "fp32refine48-level"])
+@pytest.mark.parametrize("prec,schedule", [(0, "transfer"), (2, "transfer"), (3, "transfer"), (1, "transfer"),
+                                           (0, "claim"), (3, "claim"), (0, "level")],
+                         ids=["fp64-transfer", "fp32refine-transfer", "fp32refine48-transfer", "fp32-transfer",
+                              "fp64-claim", "fp32refine48-claim", "fp64-level"])
 def test_gravity2d_256_whole_domain_sweep(lib, oracle_sweep, monkeypatch, prec, schedule):
     torch = pytest.importorskip("torch")
     monkeypatch.setenv("PDG_DENSE_SCHEDULE", schedule)
@@ -58,7 +59,7 @@ def test_gravity2d_256_whole_domain_sweep(lib, oracle_sweep, monkeypatch, prec, 
     prob.transport_sweep(f, fb, fb, wl.dt / 2)
     prob.sync_status()
     got = gpu_to_oracle(gpu_state_values(prob, f), inst)     # (9, 1, nc, nd)
-    bar = 1e-12 if prec == 0 else 1e-10
+    bar = {0: 1e-12, 1: 2e-5, 2: 1e-10, 3: 1e-10}[prec]
     for v in range(inst.vel.shape[0]):
         l2, mx = rel_errors(got[v], oracle_sweep[v])
         print(f"  velocity {inst.vel[v]}: rel L2 {l2:.3e} max {mx:.3e}")

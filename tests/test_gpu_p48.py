@@ -154,7 +154,7 @@ def test_dense_sweep_matches_oracle(lib, case, schedule):
     assert l2 <= 1e-10 and mx <= 1e-9
 
 
-@pytest.fixture(params=["level", "claim"])
+@pytest.fixture(params=["level", "claim", "transfer"])
 def schedule(request, monkeypatch):
     monkeypatch.setenv("PDG_DENSE_SCHEDULE", request.param)
     return request.param

@@ -38,10 +38,10 @@ def _uneven_batch(seed=0):
 def _run(lib, torch, wl, prec, scheme, steps):
     prob = lib.Problem([inst_dict(i) for i in wl.instances])
     prob.prepare(wl.dt, theta=wl.theta, omega=wl.omega, scheme=scheme, precision=prec)
-    f, fb = gpu_initial_state(prob, wl.instances, torch, torch.float32 if prec == 1 else torch.float64)
+    f, fb = gpu_initial_state(prob, wl.instances, torch, None)
     prob.step(f, fb, steps)
     torch.cuda.synchronize()
-    out = f.double().cpu().numpy()
+    out = prob.state_to_f64(f).cpu().numpy()
     res = []
     for i, inst in enumerate(wl.instances):
         got = gpu_to_oracle(out, inst, prob.layout["f_off"][i])
@@ -49,7 +49,7 @@ def _run(lib, torch, wl, prec, scheme, steps):
         f0, fb0 = oracle_initial_state(oprob, inst)
         want = ost.run(oprob, f0, fb0, wl.dt, wl.theta, wl.omega, scheme, steps)
         res.append(rel_errors(got, want))
-    corr = prob.last_refine_correction() if prec == 2 else None
+    corr = prob.last_refine_correction() if prec in (2, 3) else None
     prob.close()
     return res, corr
 
@@ -96,17 +96,26 @@ def test_step_reduced_workloads(lib, name, prec):
     assert err[0] <= bar and err[1] <= 10 * bar
 
 
-@pytest.mark.parametrize("prec", [0, 2], ids=["fp64", "fp32refine"])
-def test_step_uneven_batch(lib, prec):
+@pytest.fixture(params=["per-degree", "mixed"])
+def sweep_launch(request, monkeypatch):
+    """Uniform-mesh sweep items in one launch per node count, or in one
+    launch over every node count (the default; read at prepare)."""
+    monkeypatch.setenv("PDG_SWEEP_MIXED", "1" if request.param == "mixed" else "0")
+    return request.param
+
+
+@pytest.mark.parametrize("prec", [0, 2, 3], ids=["fp64", "fp32refine", "fp32refine48"])
+def test_step_uneven_batch(lib, prec, sweep_launch):
     torch = pytest.importorskip("torch")
+    print(f"uneven batch prec={prec} launch={sweep_launch}", flush=True)
     wl = _uneven_batch()
     errs, _ = _run(lib, torch, wl, prec, 2, wl.steps)
-    bar = {0: 1e-12, 2: 1e-10}[prec]
+    bar = {0: 1e-12, 2: 1e-10, 3: 1e-10}[prec]
     for e in errs:
         assert e[0] <= bar and e[1] <= 10 * bar
 
 
-def test_batched_instance_equals_instance_alone(lib):
+def test_batched_instance_equals_instance_alone(lib, sweep_launch):
     torch = pytest.importorskip("torch")
     wl = _uneven_batch(seed=3)
     prob = lib.Problem([inst_dict(i) for i in wl.instances])
@@ -124,9 +133,10 @@ def test_batched_instance_equals_instance_alone(lib):
     prob.close()
 
 
-def test_graph_replay_equals_eager(lib, monkeypatch):
+@pytest.mark.parametrize("name", ["euler2d_256", "batch"])
+def test_graph_replay_equals_eager(lib, monkeypatch, name, sweep_launch):
     torch = pytest.importorskip("torch")
-    wl = _small("euler2d_256")
+    wl = _small("euler2d_256") if name == "euler2d_256" else _uneven_batch(seed=5)
     outs = []
     for no_graph in (False, True):
         if no_graph:

@@ -20,7 +20,7 @@ class Desc(ctypes.Structure):
                 ("nv", ctypes.c_int32), ("m", ctypes.c_int32), ("lo", ctypes.c_double * 3),
                 ("hi", ctypes.c_double * 3), ("v", ctypes.POINTER(ctypes.c_double)),
                 ("feq", ctypes.c_int32), ("feq_param", ctypes.c_double * 4),
-                ("edges", ctypes.POINTER(ctypes.c_double) * 3)]
+                ("edges", ctypes.POINTER(ctypes.c_double) * 3), ("axes", ctypes.c_double * 9)]
 
 v = (ctypes.c_double * 2)(1.0, 1.0)
 d = Desc()
