@@ -278,82 +278,169 @@ __global__ __launch_bounds__(128) void dense_transfer_operator_kernel(double *ta
 // The trace wavefront of one family (velocity, component) over its tile
 // diagonals, after the zero-inflow tile pass has left each tile's Z in the
 // slots of its downwind tiles.  Tile (I, J) of diagonal s = I + J takes its
-// inflow from the outputs of (I - 1, J) and (I, J - 1) on diagonal s - 1,
-// held in LDS; the outputs of a diagonal are one matrix product
-// OUT = Z + R IN over its tiles (columns), computed as 16 x 16 blocks of
-// binary64 MFMA: wave w owns the row blocks w, w + 4, .. of R, whose A
-// operands stay in registers for the whole sweep.  The outputs replace Z in
-// the slots, where the final tile pass reads them as exact inflow traces.
+// inflow from the outputs of (I - 1, J) and (I, J - 1) on diagonal s - 1;
+// the outputs of a diagonal are one matrix product OUT = Z + R IN over its
+// tiles (columns), computed as 16 x 16 blocks of binary64 MFMA: product wave
+// w < 4 owns the row blocks w, w + 4, .. of R, whose A operands stay in
+// registers for the whole sweep.  The outputs replace Z in the slots, where
+// the final tile pass reads them as exact inflow traces.
+//
+// Diagonals live in three LDS buffers: diagonal s in buffer s % 3 holds Z(s)
+// before its product and OUT(s) after.  The product waves touch no global
+// memory in the loop.  Three loader waves take turns (diagonal t by loader
+// t % 3): they issue the loads of Z(t) three diagonals ahead and write them
+// to LDS one diagonal ahead, into the buffer that diagonal t - 3 left (with
+// diagonals of up to 64 tiles, two loaders per residue split the rows); the
+// store wave writes OUT(s - 1) to the slots while diagonal s is computed.  On
+// this architecture loads and stores share one wait counter, so keeping each
+// wave to one kind keeps every wait to the wave's own oldest requests.
 typedef double transfer_d4 __attribute__((ext_vector_type(4)));
+// four product waves, the store wave and 3 MD / 32 loader waves
+__host__ __device__ constexpr int transfer_threads(int md) { return (5 + 3 * (md / 32)) * 64; }
+// The values loaded for Z where a tile column has no downwind slot.
+__device__ uint64_t kTransferZero[128] = {};  // never written; more than any NR
 
-template <int F>
-__global__ __launch_bounds__(256) void dense_transfer_kernel(const DenseTile *__restrict__ tiles,
-                                                             const DenseFam *__restrict__ fams,
-                                                             const int32_t *__restrict__ fam_list,
-                                                             const DenseDesc *__restrict__ descs,
-                                                             const double *__restrict__ table, int dt_idx,
-                                                             uint64_t *__restrict__ traces) {
+// Workgroup barrier that orders LDS only: global stores in flight are not
+// drained (nothing in the wavefront reads a slot that is written in the same
+// launch).  The empty asm keeps the compiler from moving loads across it.
+__device__ __forceinline__ void lds_barrier() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+  __asm__ __volatile__("" ::: "memory");
+  __builtin_amdgcn_s_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
+}
+
+template <int F, int MD>
+__global__ __launch_bounds__(transfer_threads(MD)) void dense_transfer_kernel(const DenseTile *__restrict__ tiles,
+                                                                          const DenseFam *__restrict__ fams,
+                                                                          const int32_t *__restrict__ fam_list,
+                                                                          const DenseDesc *__restrict__ descs,
+                                                                          const double *__restrict__ table,
+                                                                          int dt_idx, uint64_t *__restrict__ traces) {
   constexpr int N = F * F, T = kTransferT, TF = T * F, NR = 2 * TF, KS = NR / 4, NRB = NR / 16;
-  constexpr int NPW = (NRB + 3) / 4;               // row blocks per wave
-  constexpr int NCB = (kTransferMaxDiag + 15) / 16;  // column blocks of the longest diagonal
-  constexpr int LS = kTransferMaxDiag + 16;        // LDS row stride (doubles)
-  __shared__ double ob[2][NR][LS];                 // outputs of the previous and current diagonal: [row][column]
+  constexpr int NPW = (NRB + 3) / 4;               // row blocks per product wave
+  constexpr int NCB = MD / 16;                     // column blocks of the longest diagonal
+  constexpr int LS = MD + 16;                      // LDS row stride (doubles): 16 mod 32 keeps reads conflict-free
+  constexpr int NLP = MD / 32;                     // loaders per diagonal residue mod 3
+  constexpr int OQL = NR / 4 / NLP;                // row quads per loader
+  __shared__ double ob[3][NR][LS];                 // [diagonal % 3][row][tile column]
   const DenseFam fm = fams[fam_list[blockIdx.x]];
   const DenseDesc &d = descs[fm.desc];
   const DenseRowLayout L{N, F};
   const double *R = table + d.op_off + (int64_t)dt_idx * d.op_stride + L.r_off();
   const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
   const int nt0 = fm.nt[0], nt1 = fm.nt[1];
+  const int ndiag = nt0 + nt1 - 1;
+  // A family's tiles were given their trace slots in order (t0 fastest), 3
+  // axis slots each: tile (I, J)'s slots start at tbase + (I + nt0 J) 3 slot.
+  const int slot = tiles[fm.tile0].slot;
+  const int64_t tbase = tiles[fm.tile0].trace_off;
+  auto diag_len = [&](int s) { return min(s, nt0 - 1) - max(0, s - nt1 + 1) + 1; };
+  // slot rows fed by the tile in column j of diagonal s: the axis-0 slot of
+  // (I + 1, J) takes its east outputs (rows o < TF), the axis-1 slot of
+  // (I, J + 1) its north outputs (rows TF + ..); null where the tile has no
+  // such downwind neighbour or j is past the diagonal's end.  Computed once
+  // per tile column, so each row is one fixed offset from its base.
+  auto out_rows = [&](int s, int j, uint64_t *&east, uint64_t *&north) {
+    const int ilo = max(0, s - nt1 + 1), ihi = min(s, nt0 - 1);
+    const int I = ilo + j, J = s - I;
+    const bool in = I <= ihi;
+    east = in && I + 1 < nt0 ? traces + tbase + (int64_t)((I + 1) + nt0 * J) * (3 * slot) : nullptr;
+    north = in && J + 1 < nt1 ? traces + tbase + (int64_t)(I + nt0 * (J + 1)) * (3 * slot) + slot : nullptr;
+  };
+  if (w >= 4) {
+    // memory waves: lane l covers rows 4 oq + l / 16 and tile columns
+    // 16 jq + l % 16 of a diagonal (conflict-free in LDS, 32-byte runs in the slots)
+    const int jl = l & 15, ol = l >> 4;
+    if (w == 4) {
+      auto store_diag = [&](int s) {
+        const int n = diag_len(s), buf = s % 3;
+#pragma unroll
+        for (int jq = 0; jq < NCB; ++jq) {
+          if (jq * 16 >= n) break;  // wave-uniform
+          const int j = 16 * jq + jl;
+          uint64_t *east, *north;
+          out_rows(s, j, east, north);
+#pragma unroll
+          for (int oq = 0; oq < NR / 4; ++oq) {
+            const int o = 4 * oq + ol;
+            uint64_t *row = oq < TF / 4 ? east : north;
+            if (row) row[oq < TF / 4 ? o : o - TF] = (uint64_t)__double_as_longlong(ob[buf][o][j]);
+          }
+        }
+      };
+      for (int p = -1; p < ndiag; ++p) {
+        if (p >= 1) store_diag(p - 1);
+        lds_barrier();
+      }
+      store_diag(ndiag - 1);
+      return;
+    }
+    const int k = (w - 5) % 3;             // this loader's diagonals: t % 3 == k
+    const int oq0 = ((w - 5) / 3) * OQL;   // and its row quads
+    double zr[OQL][NCB];
+    auto issue = [&](int t) {
+      const int n = diag_len(t);
+#pragma unroll
+      for (int jq = 0; jq < NCB; ++jq) {
+        if (jq * 16 >= n) break;  // wave-uniform
+        uint64_t *east, *north;
+        out_rows(t, 16 * jq + jl, east, north);
+        // rows without a slot read zeros (row index 4 oq < NR)
+        const uint64_t *eb = east ? east + ol : kTransferZero;
+        const uint64_t *nb = north ? north + ol - TF : kTransferZero;
+#pragma unroll
+        for (int q = 0; q < OQL; ++q) {
+          const int oq = oq0 + q;
+          const uint64_t *row = oq < TF / 4 ? eb : nb;
+          zr[q][jq] = __longlong_as_double((long long)row[4 * oq]);
+        }
+      }
+    };
+    auto write = [&](int t) {
+      const int n = diag_len(t), buf = t % 3;
+#pragma unroll
+      for (int jq = 0; jq < NCB; ++jq) {
+        if (jq * 16 >= n) break;  // wave-uniform
+#pragma unroll
+        for (int q = 0; q < OQL; ++q) ob[buf][4 * (oq0 + q) + ol][16 * jq + jl] = zr[q][jq];
+      }
+    };
+    // Z(t) is loaded during phases t - 3 .. t - 1 (from the prologue for
+    // t < 3) and written to LDS in phase t - 1
+    for (int p = -1; p < ndiag; ++p) {
+      const int tw = p + 1, tl = p + 3;
+      if (tw < ndiag && tw % 3 == k) {
+        if (tw == 0) issue(0);
+        write(tw);
+      }
+      if (p == -1 && k == 1 && 1 < ndiag) issue(1);
+      if (tl < ndiag && tl % 3 == k) issue(tl);
+      lds_barrier();
+    }
+    return;
+  }
   double A[NPW][KS];
 #pragma unroll
   for (int r = 0; r < NPW; ++r)
 #pragma unroll
     for (int ks = 0; ks < KS; ++ks) A[r][ks] = (w + 4 * r < NRB) ? R[((w + 4 * r) * KS + ks) * 64 + l] : 0.0;
-  // A family's tiles were given their trace slots in order (t0 fastest), 3
-  // axis slots each: tile (I, J)'s slots start at tbase + (I + nt0 J) 3 slot.
-  const int slot = tiles[fm.tile0].slot;
-  const int64_t tbase = tiles[fm.tile0].trace_off;
   // B operand: lane l holds row kq = l / 16, column jj = l % 16 of a 4 x 16
-  // block; D: register i of lane l holds row 4 i + kq, column jj
+  // block; C and D: register i of lane l holds row 4 i + kq, column jj
   const int jj = l & 15, kq = l >> 4;
-  // offset of output row o of tile column j of diagonal s in the slots of the
-  // downwind tile it feeds (east edge: axis-0 slot of (I + 1, J); north edge:
-  // axis-1 slot of (I, J + 1)), or -1 when the tile is on the downwind border
-  auto out_slot = [&](int s, int j, int o) -> int64_t {
-    const int ilo = max(0, s - nt1 + 1), ihi = min(s, nt0 - 1);
-    const int I = ilo + j, J = s - I;
-    if (I > ihi) return -1;
-    if (o < TF) return I + 1 < nt0 ? tbase + ((int64_t)(I + 1) + (int64_t)nt0 * J) * 3 * slot + o : -1;
-    return J + 1 < nt1 ? tbase + ((int64_t)I + (int64_t)nt0 * (J + 1)) * 3 * slot + slot + (o - TF) : -1;
-  };
-  // Z of the next diagonal's tiles is loaded one diagonal ahead, so the loads
-  // are in flight while the current product runs
-  auto load_z = [&](int s, double (&zz)[NPW][NCB][4]) {
-    const int ntl = min(s, nt0 - 1) - max(0, s - nt1 + 1) + 1;
-#pragma unroll
-    for (int r = 0; r < NPW; ++r)
-#pragma unroll
-      for (int cb = 0; cb < NCB; ++cb)
-#pragma unroll
-        for (int i = 0; i < 4; ++i) {
-          const int64_t src = (w + 4 * r < NRB && cb * 16 < ntl) ? out_slot(s, cb * 16 + jj, (w + 4 * r) * 16 + 4 * i + kq) : -1;
-          zz[r][cb][i] = src >= 0 ? __longlong_as_double((long long)traces[src]) : 0.0;
-        }
-  };
-  const int ndiag = nt0 + nt1 - 1;
-  int cur = 0;
-  // diagonal s with its Z in zc, loading the next diagonal's Z into zn.  The
-  // column blocks run in pairs: every B operand of a pair is read from LDS
-  // (unconditionally, from an in-range column, then masked) before the two
-  // independent MFMA chains are issued interleaved.
-  auto step = [&](int s, double (&zc)[NPW][NCB][4], double (&zn)[NPW][NCB][4]) {
-    if (s + 1 < ndiag) load_z(s + 1, zn);
+  lds_barrier();  // Z(0) in LDS
+  for (int s = 0; s < ndiag; ++s) {
+    const int cur = s % 3, prv = (s + 2) % 3;
     const int ilo = max(0, s - nt1 + 1), ihi = min(s, nt0 - 1);
     const int plo = max(0, s - nt1);  // first tile column I of diagonal s - 1
     const int ncb = (ihi - ilo) / 16 + 1;
+    // column blocks in pairs: every B operand of a pair is read (from an
+    // in-range column, then masked) before the two MFMA chains are issued
+    // interleaved; the second chain is skipped past the diagonal's end
 #pragma unroll
     for (int cp = 0; cp < NCB; cp += 2) {
       if (cp >= ncb) break;  // wave-uniform
+      const bool two = cp + 1 < ncb;
       double b[2][KS];
       int jcol[2];
       bool valid[2];
@@ -368,9 +455,9 @@ __global__ __launch_bounds__(256) void dense_transfer_kernel(const DenseTile *__
         const int cw = west ? I - 1 - plo : 0, cs = south ? I - plo : 0;
 #pragma unroll
         for (int ks = 0; ks < KS; ++ks) {
-          const int k = 4 * ks + kq;  // input index
-          const bool use = k < TF ? west : south;
-          const double x = ob[cur ^ 1][k][k < TF ? cw : cs];
+          const int kk = 4 * ks + kq;  // input index
+          const bool use = kk < TF ? west : south;
+          const double x = ob[prv][kk][kk < TF ? cw : cs];
           b[h][ks] = use ? x : 0.0;
         }
       }
@@ -381,36 +468,29 @@ __global__ __launch_bounds__(256) void dense_transfer_kernel(const DenseTile *__
         transfer_d4 acc0, acc1;
 #pragma unroll
         for (int i = 0; i < 4; ++i) {
-          acc0[i] = zc[r][cp][i];
-          acc1[i] = cp + 1 < NCB ? zc[r][cp + 1 < NCB ? cp + 1 : cp][i] : 0.0;
+          acc0[i] = ob[cur][rb * 16 + 4 * i + kq][jcol[0]];
+          acc1[i] = ob[cur][rb * 16 + 4 * i + kq][jcol[1]];
         }
+        if (two) {
 #pragma unroll
-        for (int ks = 0; ks < KS; ++ks) {
-          acc0 = __builtin_amdgcn_mfma_f64_16x16x4f64(A[r][ks], b[0][ks], acc0, 0, 0, 0);
-          acc1 = __builtin_amdgcn_mfma_f64_16x16x4f64(A[r][ks], b[1][ks], acc1, 0, 0, 0);
+          for (int ks = 0; ks < KS; ++ks) {
+            acc0 = __builtin_amdgcn_mfma_f64_16x16x4f64(A[r][ks], b[0][ks], acc0, 0, 0, 0);
+            acc1 = __builtin_amdgcn_mfma_f64_16x16x4f64(A[r][ks], b[1][ks], acc1, 0, 0, 0);
+          }
+        } else {
+#pragma unroll
+          for (int ks = 0; ks < KS; ++ks)
+            acc0 = __builtin_amdgcn_mfma_f64_16x16x4f64(A[r][ks], b[0][ks], acc0, 0, 0, 0);
         }
 #pragma unroll
         for (int h = 0; h < 2; ++h) {
           if (!valid[h]) continue;
 #pragma unroll
-          for (int i = 0; i < 4; ++i) {
-            const int o = rb * 16 + 4 * i + kq;
-            const double y = h == 0 ? acc0[i] : acc1[i];
-            ob[cur][o][jcol[h]] = y;
-            const int64_t dst = out_slot(s, jcol[h], o);
-            if (dst >= 0) traces[dst] = (uint64_t)__double_as_longlong(y);
-          }
+          for (int i = 0; i < 4; ++i) ob[cur][rb * 16 + 4 * i + kq][jcol[h]] = h == 0 ? acc0[i] : acc1[i];
         }
       }
     }
-    __syncthreads();
-    cur ^= 1;
-  };
-  double z0[NPW][NCB][4], z1[NPW][NCB][4];
-  load_z(0, z0);
-  for (int s = 0; s < ndiag; s += 2) {
-    step(s, z0, z1);
-    if (s + 1 < ndiag) step(s + 1, z1, z0);
+    lds_barrier();
   }
 }
 
@@ -864,15 +944,21 @@ hipError_t launch_dense_transfer_operator(int np, double *table, const int64_t *
   return hipGetLastError();
 }
 
-hipError_t launch_dense_transfer(int np, const DenseTile *tiles, const DenseFam *fams, const int32_t *fam_list,
-                                 int n_fams, const DenseDesc *descs, const double *table, int dt_idx,
-                                 uint64_t *traces, hipStream_t st) {
+hipError_t launch_dense_transfer(int np, int max_diag, const DenseTile *tiles, const DenseFam *fams,
+                                 const int32_t *fam_list, int n_fams, const DenseDesc *descs, const double *table,
+                                 int dt_idx, uint64_t *traces, hipStream_t st) {
   if (n_fams <= 0) return hipSuccess;
+  if (max_diag < 1 || max_diag > kTransferMaxDiag) return hipErrorInvalidValue;
+  const bool wide = max_diag > 32;
   switch (np) {
-#define PDG_TR_CASE(NPV)                                                                                       \
-  case NPV:                                                                                                    \
-    hipLaunchKernelGGL(dense_transfer_kernel<NPV>, dim3(n_fams), dim3(256), 0, st, tiles, fams, fam_list, descs, \
-                       table, dt_idx, traces);                                                                 \
+#define PDG_TR_CASE(NPV)                                                                                        \
+  case NPV:                                                                                                     \
+    if (wide)                                                                                                   \
+      hipLaunchKernelGGL((dense_transfer_kernel<NPV, 64>), dim3(n_fams), dim3(transfer_threads(64)), 0, st,    \
+                         tiles, fams, fam_list, descs, table, dt_idx, traces);                                  \
+    else                                                                                                        \
+      hipLaunchKernelGGL((dense_transfer_kernel<NPV, 32>), dim3(n_fams), dim3(transfer_threads(32)), 0, st,    \
+                         tiles, fams, fam_list, descs, table, dt_idx, traces);                                  \
     break;
     PDG_TR_CASE(2)
     PDG_TR_CASE(3)

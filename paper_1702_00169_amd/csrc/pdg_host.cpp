@@ -98,6 +98,7 @@ struct DenseGroup {
   bool transfer_ok = false;    // two-dimensional, full tiles only, diagonals within the LDS limit
   bool transfer = false;       // transfer schedule: zero-inflow tiles, trace wavefront, final tiles
   int64_t tfam_first = 0, tfam_count = 0;  // its families in the transfer family list
+  int tmax_diag = 0;                       // longest tile diagonal of those families
 };
 
 // One (instance, velocity) family of chains and its launch class.
@@ -1293,6 +1294,7 @@ static pdg_status prepare_impl(pdg_ctx *c, double dt, double theta, double omega
       if (gi < 0) continue;
       const bool full = dd.n[0] % 8 == 0 && dd.n[1] % 8 == 0 && dd.sgn[0] != 0 && dd.sgn[1] != 0;
       if (!full || std::min(fmd.nt[0], fmd.nt[1]) > 64) dgroups[gi].transfer_ok = false;
+      dgroups[gi].tmax_diag = std::max(dgroups[gi].tmax_diag, std::min(fmd.nt[0], fmd.nt[1]));
     }
     for (size_t gi = 0; gi < dgroups.size(); ++gi) {
       dgroups[gi].tfam_first = (int64_t)tfam.size();
@@ -1590,7 +1592,7 @@ pdg_status do_sweep(pdg_ctx *c, void *f, const double *fb_old, const double *fb_
                                         StateBuf{f, c->f_elems}, fb_old, fb_new, sc.traces, sc.sync + g.sync_off,
                                         dense_err(c), st);
       if (e == hipSuccess)
-        e = launch_dense_transfer(g.np, c->dtiles.p + g.first, c->dfams.p, c->dtfams.p + g.tfam_first,
+        e = launch_dense_transfer(g.np, g.tmax_diag, c->dtiles.p + g.first, c->dfams.p, c->dtfams.p + g.tfam_first,
                                   (int)g.tfam_count, c->ddesc.p, c->dtable.p, dt_idx, sc.traces, st);
       if (e == hipSuccess)
         e = launch_dense_sweep(c->prec, kDenseFinal, g.np, g.dim, c->dtiles.p + g.first, c->dorder.p + g.first,

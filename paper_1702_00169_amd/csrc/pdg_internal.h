@@ -234,10 +234,11 @@ struct DenseErr {
 hipError_t launch_dense_transfer_operator(int np, double *table, const int64_t *row_off, const DenseDesc *descs,
                                           const int32_t *row_desc, int n_rows, hipStream_t st);
 // Trace wavefront of the transfer schedule for the families fam_list[0..n)
-// of one launch group (tiles: the group's tile array).
-hipError_t launch_dense_transfer(int np, const DenseTile *tiles, const DenseFam *fams, const int32_t *fam_list,
-                                 int n_fams, const DenseDesc *descs, const double *table, int dt_idx,
-                                 uint64_t *traces, hipStream_t st);
+// of one launch group (tiles: the group's tile array); max_diag (1..64) is the
+// longest tile diagonal among them.
+hipError_t launch_dense_transfer(int np, int max_diag, const DenseTile *tiles, const DenseFam *fams,
+                                 const int32_t *fam_list, int n_fams, const DenseDesc *descs, const double *table,
+                                 int dt_idx, uint64_t *traces, hipStream_t st);
 
 // Modes of the dense tile kernel (see pdg_dense.hip): claimed tiles in one
 // launch, one launch per tile diagonal, and the two tile passes of the

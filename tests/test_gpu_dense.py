@@ -125,3 +125,18 @@ def test_zero_velocity_is_identity(lib):
     prob.sync_status()
     assert torch.equal(f, g)
     prob.close()
+
+
+DIAG = np.array([[1, 1], [-1, 1], [-1, -1], [1, -1]], float)
+
+
+@pytest.mark.parametrize("prec", [0, 2], ids=["fp64", "fp32refine"])
+def test_dense_transfer_wide_diagonals(lib, prec, monkeypatch):
+    """Tile diagonals longer than 32 tiles (34 x 33 tiles of 8 x 8 cells):
+    the trace wavefront's wide variant (four column blocks, split loaders)."""
+    torch = pytest.importorskip("torch")
+    monkeypatch.setenv("PDG_DENSE_SCHEDULE", "transfer")
+    case = ("diag4_272x264_d1", 2, (272, 264), 1, DIAG * 0.9, 1)
+    (l2, mx), per_v = _run(lib, torch, case, prec)
+    print(f"  rel L2 {l2:.3e} max {mx:.3e}; worst velocity {max(per_v):.3e}")
+    assert l2 <= BARS[prec] and mx <= 10 * BARS[prec] and max(per_v) <= 10 * BARS[prec]
