@@ -85,11 +85,12 @@ def initial_state(pdg, prob, insts, torch):
 
 def kernel_source_hash():
     """Hash of the sources that define the axis-aligned sweep kernel: its
-    translation unit, the device helpers, and the part of the internal header
-    that holds its item and operator layouts (up to the node-local structs)."""
+    translation unit, its cell solves, the device helpers, and the part of the
+    internal header that holds its item and operator layouts (up to the
+    node-local structs)."""
     csrc = os.path.join(ROOT, "paper_1702_00169_amd", "csrc")
     h = hashlib.sha256()
-    for name in ("pdg_sweep.hip", "pdg_device.h"):
+    for name in ("pdg_sweep.hip", "pdg_cellop.h", "pdg_device.h"):
         with open(os.path.join(csrc, name), "rb") as fh:
             h.update(fh.read())
     with open(os.path.join(csrc, "pdg_internal.h"), "rb") as fh:

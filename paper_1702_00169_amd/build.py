@@ -12,7 +12,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIBDIR = os.path.join(HERE, "_lib")
 LIB = os.path.join(LIBDIR, "libpdg.so")
-SOURCES = ["pdg_host.cpp", "pdg_sweep.hip", "pdg_local.hip", "pdg_dense.hip"]
+SOURCES = ["pdg_host.cpp", "pdg_sweep.hip", "pdg_local.hip", "pdg_dense.hip", "pdg_fused.hip"]
 
 # Packed-FP32 VALU forms are kept out of the generated code on purpose.
 HIP_FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",

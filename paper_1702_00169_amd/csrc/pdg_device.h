@@ -71,6 +71,11 @@ struct State {
   __device__ __forceinline__ Rt dec(Raw r) const { return (Rt)r; }
   __device__ __forceinline__ Rt ld(int64_t i) const { return (Rt)ld_state(p + i); }
   __device__ __forceinline__ void st(int64_t i, Rt v) const { st_state(p + i, (St)v); }
+  // The state from element off on (off uniform across the workgroup), indexed
+  // by a 32-bit offset: the base stays in scalar registers.
+  __device__ __forceinline__ State at(int64_t off) const { return State{p + off}; }
+  __device__ __forceinline__ Raw ldr32(uint32_t i) const { return ld_state(p + i); }
+  __device__ __forceinline__ void st32(uint32_t i, Rt v) const { st_state(p + i, (St)v); }
 };
 
 // 48-bit state: value x is kept as h = x rounded to binary32 (nearest) and
@@ -117,6 +122,15 @@ struct State<kP48> {
   __device__ __forceinline__ double dec(Raw r) const { return p48_decode(r.h, r.l); }
   __device__ __forceinline__ double ld(int64_t i) const { return p48_decode(ld_state(hi + i), ld_state(lo + i)); }
   __device__ __forceinline__ void st(int64_t i, double v) const {
+    float h;
+    int16_t l;
+    p48_encode(v, h, l);
+    st_state(hi + i, h);
+    st_state(lo + i, l);
+  }
+  __device__ __forceinline__ State at(int64_t off) const { return State{hi + off, lo + off}; }
+  __device__ __forceinline__ Raw ldr32(uint32_t i) const { return Raw{ld_state(hi + i), ld_state(lo + i)}; }
+  __device__ __forceinline__ void st32(uint32_t i, double v) const {
     float h;
     int16_t l;
     p48_encode(v, h, l);

@@ -82,6 +82,12 @@ struct Group {
   bool wpos = false;     // graded, and every tile width C a multiple of 64
 };
 
+// Fused collision + x transport launch group: items of one (d+1, nv, m, nx).
+struct FusedGroup {
+  int np, nv, m, nx;
+  int64_t first, count;
+};
+
 struct RelaxGroup {
   int nv, m;
   int64_t first, count;
@@ -189,6 +195,13 @@ struct pdg_ctx {
   std::vector<int> item_cost;       // per item: its relative running time (longest first within a launch)
   bool mixed = false;               // one launch for the items of every node count (uniform meshes)
   DevBuf<SweepItem> smixed;         // those items, longest first
+  // fused collision + x transport (the collapsed Strang step's C T pairs)
+  bool fused = false;
+  std::vector<FusedGroup> fgroups;  // (d+1, nv, m, nx, first, count) over fitems
+  DevBuf<FusedDesc> fdesc;
+  DevBuf<FusedItem> fitems;
+  std::vector<int8_t> desc_x;       // per SweepDesc: chains along x (run in the fused pass)
+  DevBuf<SweepItem> syz;            // sweep items of the other families, longest first
   const double *last_stats = nullptr;  // statistics written by the most recent sweep
   hipStream_t cap_stream = nullptr;
   // graph cache of the interior step
@@ -226,6 +239,12 @@ struct pdg_ctx {
     smixed.release();
     item_cost.clear();
     mixed = false;
+    fused = false;
+    fgroups.clear();
+    fdesc.release();
+    fitems.release();
+    desc_x.clear();
+    syz.release();
     if (cap_stream) (void)hipStreamDestroy(cap_stream);
     cap_stream = nullptr;
     groups.clear();
@@ -969,6 +988,7 @@ static pdg_status prepare_impl(pdg_ctx *c, double dt, double theta, double omega
   // ---- operator table: (instance, velocity, dt_sub in dts) ---------------
   std::vector<OpEntry> ops;
   std::vector<SweepDesc> sdesc;
+  std::vector<std::vector<int>> vel_desc(c->inst.size());  // (instance, velocity) -> SweepDesc, -1 if none
   std::vector<Family> fams;
   std::vector<LaunchClass> classes;
   for (size_t ii = 0; ii < c->inst.size(); ++ii) {
@@ -1034,6 +1054,8 @@ static pdg_status prepare_impl(pdg_ctx *c, double dt, double theta, double omega
       }
       const int desc_index = (int)sdesc.size();
       sdesc.push_back(sd);
+      if (vel_desc[ii].empty()) vel_desc[ii].assign(in.d.nv, -1);
+      vel_desc[ii][v] = desc_index;
       Family fm;
       fm.desc = desc_index;
       fm.np = np;
@@ -1393,6 +1415,72 @@ static pdg_status prepare_impl(pdg_ctx *c, double dt, double theta, double omega
     }
   }
 
+  // ---- fused collision + x transport -------------------------------------
+  // Opt-in (PDG_FUSED=1 at prepare): measured slower than the separate
+  // collision and sweep passes on the 3D Euler workload (the pass holds a
+  // row's d+1 nodes and all n_v m values per node, so fewer waves fit a CU).
+  // Every instance: the {+-lambda e_k} velocity set of the relaxation on a
+  // box mesh with uniform cells, rows short enough for one workgroup, node
+  // offsets within 32 bits; otherwise the step keeps separate passes.
+  std::vector<FusedDesc> fdesc_h;
+  std::vector<FusedItem> fitems_h;
+  std::vector<FusedGroup> fgroups_h;
+  const char *fenv = std::getenv("PDG_FUSED");
+  bool fused = relax_ok && dgroups.empty() && fenv && std::strcmp(fenv, "1") == 0;
+  for (size_t ii = 0; ii < c->inst.size() && fused; ++ii) {
+    const Instance &in = c->inst[ii];
+    const int dim = in.d.dim;
+    bool ok = in.d.feq != PDG_FEQ_D2Q9 && !in.affine && (int)vel_desc[ii].size() == in.d.nv &&
+              fused_supported((int)in.np, in.d.nv, in.d.m, (int)in.n[0]) && in.nd * in.nc < ((int64_t)1 << 31);
+    for (int a = 0; a < dim && ok; ++a) ok = !in.graded[a];
+    int vx[2] = {-1, -1};
+    for (int v = 0; v < in.d.nv && ok; ++v) {
+      if (in.ndep[v] != 1 || vel_desc[ii][v] < 0) ok = false;
+      else if (in.axis[v] == 0) vx[in.sign[v] > 0 ? 0 : 1] = v;
+    }
+    if (!ok || vx[0] < 0 || vx[1] < 0) {
+      fused = false;
+      break;
+    }
+    FusedDesc fd;
+    std::memset(&fd, 0, sizeof(fd));
+    fd.nc = in.nc;
+    fd.rdesc = (int32_t)ii;
+    fd.nx = (int32_t)in.n[0];
+    fd.ntau = (int32_t)(in.nc / in.n[0]);
+    fd.tnodes = 1;
+    for (int k = 0; k < dim - 1; ++k) fd.tnodes *= (int32_t)in.np;
+    for (int h = 0; h < 2; ++h) {
+      fd.vx[h] = vx[h];
+      fd.fb[h] = in.fb_off + in.fb_vel_off[vx[h]];
+      fd.op[h] = sdesc[vel_desc[ii][vx[h]]].op;
+    }
+    fdesc_h.push_back(fd);
+  }
+  if (fused) {
+    std::map<std::array<int, 4>, std::vector<FusedItem>> fby;
+    for (size_t ii = 0; ii < c->inst.size(); ++ii) {
+      const Instance &in = c->inst[ii];
+      const FusedDesc &fd = fdesc_h[ii];
+      const std::array<int, 4> key{(int)in.np, in.d.nv, in.d.m, fd.nx};
+      for (int64_t r = 0; r < (int64_t)fd.tnodes * fd.ntau; ++r) {
+        FusedItem fi;
+        fi.desc = (int32_t)ii;
+        fi.row0 = (int32_t)r;
+        fby[key].push_back(fi);
+      }
+    }
+    for (auto &kv : fby) {
+      fgroups_h.push_back(FusedGroup{kv.first[0], kv.first[1], kv.first[2], kv.first[3], (int64_t)fitems_h.size(),
+                                     (int64_t)kv.second.size()});
+      fitems_h.insert(fitems_h.end(), kv.second.begin(), kv.second.end());
+    }
+  }
+  c->fused = fused;
+  c->fgroups = fgroups_h;
+  c->desc_x.assign(sdesc.size(), 0);
+  for (size_t k = 0; k < sdesc.size(); ++k) c->desc_x[k] = sdesc[k].x_kind == 1 ? 1 : 0;
+
   // ---- upload + device inversion ----------------------------------------
   hipError_t e;
 #define PREP_TRY(call)                      \
@@ -1405,6 +1493,8 @@ static pdg_status prepare_impl(pdg_ctx *c, double dt, double theta, double omega
   PREP_TRY(c->rdesc.upload(rdesc))
   PREP_TRY(c->ritems.upload(ritems))
   PREP_TRY(c->idesc.upload(idesc_all))
+  PREP_TRY(c->fdesc.upload(fdesc_h))
+  PREP_TRY(c->fitems.upload(fitems_h))
   {
     const pdg_status us = upload_items(c, items);  // items, the mixed launch's order, statistics
     if (us != PDG_OK) {
@@ -1644,8 +1734,30 @@ pdg_status do_local(pdg_ctx *c, void *f, double *w_out, double omega, double h_p
   return PDG_OK;
 }
 
+// The collision with factor omega followed by the transport sweep of
+// sub-step dt_idx, as the fused pass (collision + chains along x) and the
+// sweep of the other families.
+pdg_status do_fused(pdg_ctx *c, void *f, const double *fb, int dt_idx, double omega, hipStream_t st) {
+  const size_t off_yz = 2 * (c->sitems.n + c->smixed.n);
+  const size_t off_f = off_yz + 2 * c->syz.n;
+  for (const FusedGroup &g : c->fgroups) {
+    hipError_t e = launch_relax_xsweep(c->prec, g.np, g.nv, g.m, g.nx, c->fitems.p + g.first, (int)g.count, c->fdesc.p,
+                                       c->rdesc.p, c->ops.p, dt_idx, StateBuf{f, c->f_elems}, fb, fb, omega,
+                                       c->stats.p + off_f + 2 * g.first, st);
+    if (e != hipSuccess) return from_hip_at(e, "launch_relax_xsweep");
+  }
+  hipError_t e = launch_sweep_mixed(c->prec, c->syz.p, (int)c->syz.n, c->sdesc.p, c->ops.p, dt_idx,
+                                    StateBuf{f, c->f_elems}, fb, fb, c->stats.p + off_yz, st);
+  if (e != hipSuccess) return from_hip_at(e, "launch_sweep_mixed (fused step)");
+  c->stats_valid = c->prec == PDG_FP32_REFINE || c->prec == PDG_FP32_REFINE_P48;
+  c->last_stats = c->stats.p;
+  c->last_stream = st;
+  return PDG_OK;
+}
+
 struct StepOp {
-  int kind;       // 0: transport sweep, 1: node-local step S(h_pre) C(omega) S(h_post)
+  int kind;       // 0: transport sweep, 1: node-local step S(h_pre) C(omega) S(h_post), 2: C(omega) then
+                  // the sweep (fused pass)
   int dt_idx;     // sweep: index into the prepared sub-steps
   double omega;   // relaxation factor
   double h_pre;   // source sub-steps around the collision
@@ -1654,8 +1766,9 @@ struct StepOp {
 
 pdg_status run_ops(pdg_ctx *c, const std::vector<StepOp> &ops, void *f, const double *fb, hipStream_t st) {
   for (const StepOp &o : ops) {
-    const pdg_status s = o.kind == 0 ? do_sweep(c, f, fb, fb, o.dt_idx, st, ctx_scratch(c))
-                                     : do_local(c, f, nullptr, o.omega, o.h_pre, o.h_post, false, st);
+    const pdg_status s = o.kind == 0   ? do_sweep(c, f, fb, fb, o.dt_idx, st, ctx_scratch(c))
+                         : o.kind == 2 ? do_fused(c, f, fb, o.dt_idx, o.omega, st)
+                                       : do_local(c, f, nullptr, o.omega, o.h_pre, o.h_post, false, st);
     if (s != PDG_OK) return s;
   }
   return PDG_OK;
@@ -1796,10 +1909,17 @@ static pdg_status step_impl(pdg_ctx *c, void *f, const double *fb, int32_t n_ste
     case PDG_LIE: body = {{0, 0, 0.0, 0.0, 0.0}, {1, 0, w, dt, 0.0}}; break;
     case PDG_STRANG: body = {{0, 1, 0.0, 0.0, 0.0}, {1, 0, w, 0.5 * dt, 0.5 * dt}, {0, 1, 0.0, 0.0, 0.0}}; break;
     case PDG_STRANG_COLLAPSED:
-      // T(dt/2) C [T(dt) C]^(N-1) T(dt/2)
-      pro = {{0, 1, 0.0, 0.0, 0.0}, {1, 0, w, 0.5 * dt, 0.5 * dt}};
-      body = {{0, 0, 0.0, 0.0, 0.0}, {1, 0, w, 0.5 * dt, 0.5 * dt}};
-      epi = {{0, 1, 0.0, 0.0, 0.0}};
+      // T(dt/2) C [T(dt) C]^(N-1) T(dt/2), or with the fused passes
+      // T(dt/2) [C T(dt)]^(N-1) C T(dt/2)
+      if (c->fused) {
+        pro = {{0, 1, 0.0, 0.0, 0.0}};
+        body = {{2, 0, w, 0.0, 0.0}};
+        epi = {{2, 1, w, 0.0, 0.0}};
+      } else {
+        pro = {{0, 1, 0.0, 0.0, 0.0}, {1, 0, w, 0.5 * dt, 0.5 * dt}};
+        body = {{0, 0, 0.0, 0.0, 0.0}, {1, 0, w, 0.5 * dt, 0.5 * dt}};
+        epi = {{0, 1, 0.0, 0.0, 0.0}};
+      }
       reps = n_steps - 1;
       break;
     case PDG_KIN: {
@@ -1889,8 +2009,22 @@ pdg_status upload_items(pdg_ctx *c, const std::vector<SweepItem> &items) {
   }
   e = c->smixed.upload(mixed_items);
   if (e != hipSuccess) return from_hip_at(e, "upload mixed items");
-  if (c->stats.n < std::max<size_t>(2, 2 * (items.size() + mixed_items.size()))) {
-    std::vector<double> zeros(std::max<size_t>(2, 2 * (items.size() + mixed_items.size())), 0.0);
+  // the fused step's sweep: every family not along x in one launch, longest first
+  std::vector<SweepItem> yz_items;
+  if (c->fused) {
+    std::vector<std::pair<int, int64_t>> order;
+    for (size_t i = 0; i < items.size(); ++i)
+      if (!c->desc_x[items[i].desc]) order.push_back({c->item_cost[i], (int64_t)i});
+    std::stable_sort(order.begin(), order.end(),
+                     [](const std::pair<int, int64_t> &a, const std::pair<int, int64_t> &b) { return a.first > b.first; });
+    for (const auto &o : order) yz_items.push_back(items[o.second]);
+  }
+  e = c->syz.upload(yz_items);
+  if (e != hipSuccess) return from_hip_at(e, "upload fused-step sweep items");
+  // statistics: [items | mixed items | fused-step sweep items | fused items]
+  const size_t n_stats = 2 * (items.size() + mixed_items.size() + yz_items.size() + c->fitems.n);
+  if (c->stats.n < std::max<size_t>(2, n_stats)) {
+    std::vector<double> zeros(std::max<size_t>(2, n_stats), 0.0);
     e = c->stats.upload(zeros);
     if (e != hipSuccess) return from_hip_at(e, "upload stats");
   }
@@ -2014,7 +2148,8 @@ static pdg_status last_refine_correction_impl(const pdg_ctx *c, double *max_rel_
   if (!c->prepared || !c->stats_valid) return PDG_ESTATE;
   hipError_t e = hipStreamSynchronize(c->last_stream);
   if (e != hipSuccess) return from_hip(e);
-  std::vector<double> h(2 * (c->sitems.n + c->smixed.n));
+  const size_t n = c->last_stats == c->stats.p ? c->stats.n : 2 * (c->sitems.n + c->smixed.n);
+  std::vector<double> h(n);
   e = hipMemcpy(h.data(), c->last_stats, h.size() * sizeof(double), hipMemcpyDeviceToHost);
   if (e != hipSuccess) return from_hip(e);
   double cm = 0.0, ym = 0.0;

@@ -109,6 +109,26 @@ struct InflowDesc {
   int32_t vel;
 };
 
+// Fused collision + x transport (instances whose velocities are the set
+// {+-lambda e_k} on a uniform box mesh).
+struct FusedDesc {
+  int64_t nc;        // cells
+  int64_t fb[2];     // fb offset of (+x / -x velocity, k = 0, t = 0, tau = 0)
+  int32_t rdesc;     // RelaxDesc of the instance
+  int32_t vx[2];     // indices of the +x and -x velocities
+  int32_t op[2];     // operator-table rows (dt_sub = dt) of the +x and -x velocities
+  int32_t nx;        // cells per row
+  int32_t ntau;      // rows of cells (nc / nx)
+  int32_t tnodes;    // transverse nodes (d+1)^(D-1)
+};
+
+// One workgroup's row: row0 = jt ntau + tau (transverse node jt, row of
+// cells tau).
+struct FusedItem {
+  int32_t desc;
+  int32_t row0;
+};
+
 // ---- velocities with two or three non-zero components ---------------------
 // The cell block is dense and the dependency graph is a k-dimensional
 // wavefront over the axes with non-zero components.  Cells are grouped in
@@ -191,6 +211,17 @@ hipError_t launch_sweep_mixed(int prec, const SweepItem *items, int n_items, con
 // Relax / equilibrium launch for items whose instances share (nv, m).
 hipError_t launch_relax(int prec, int nv, int m, const RelaxItem *items, int n_items, const RelaxDesc *descs,
                         StateBuf f, double *w_out, const double *w_in, double omega, int mode, hipStream_t st);
+
+// Node counts, (nv, m) and row lengths the fused kernel handles
+// ((d+1) ceil(nx / 64) 64 <= 512 threads per row).
+bool fused_supported(int np, int nv, int m, int nx);
+// Fused collision (factor omega) + transport of the +x and -x chains for
+// the items (one row each) of one (d+1, nv, m, nx) group; stats: 2 doubles
+// per item.
+hipError_t launch_relax_xsweep(int prec, int np, int nv, int m, int nx, const FusedItem *items, int n_items,
+                               const FusedDesc *fdescs, const RelaxDesc *rdescs, const OpEntry *ops, int dt_idx,
+                               StateBuf f, const double *fb_old, const double *fb_new, double omega, double *stats,
+                               hipStream_t st);
 
 hipError_t launch_inflow_eq(int nv, int m, const InflowDesc *items, int n_items, const RelaxDesc *descs,
                             const double *w_inflow, double *fb, hipStream_t st);

@@ -7,6 +7,7 @@
 // f^eq(w) and applies f += omega (f^eq - f).
 
 #include "pdg_device.h"
+#include "pdg_relax.h"
 
 namespace pdg {
 namespace {
@@ -14,31 +15,6 @@ namespace {
 // ---------------------------------------------------------------------------
 // equilibrium and relaxation
 // ---------------------------------------------------------------------------
-// f^eq_{i,k}(w) = w_k / nv + s_i q^{a_i}_k(w) / (2 lambda) for v_i = s_i lambda e_{a_i}.
-template <int M>
-__device__ inline void flux_dir(const RelaxDesc &d, const double (&w)[M], int axis, double (&q)[M]) {
-  if (d.feq == 0) {
-#pragma unroll
-    for (int k = 0; k < M; ++k) q[k] = d.param[axis] * w[k];
-  } else {
-    // compressible Euler, w = (rho, rho u_1..D, E), M = D + 2
-    const double gam = d.param[0];
-    const int dim = M - 2;
-    const double rho = w[0];
-    const double rinv = 1.0 / rho;
-    double ke = 0.0;
-#pragma unroll
-    for (int l = 0; l < M - 2; ++l) ke = fma(w[1 + l], w[1 + l] * rinv, ke);
-    const double pr = (gam - 1.0) * (w[M - 1] - 0.5 * ke);
-    const double ua = w[1 + axis] * rinv;
-    q[0] = w[1 + axis];
-#pragma unroll
-    for (int l = 0; l < M - 2; ++l) q[1 + l] = w[1 + axis] * (w[1 + l] * rinv) + (l == axis ? pr : 0.0);
-    q[M - 1] = (w[M - 1] + pr) * ua;
-    (void)dim;
-  }
-}
-
 template <int NV, int M>
 __device__ inline void equilibrium(const RelaxDesc &d, const double (&w)[M], double (&fe)[NV][M]) {
   double qd[3][M];
@@ -86,19 +62,7 @@ __global__ __launch_bounds__(kBlock) void relax_kernel(const RelaxItem *__restri
       for (int i = 0; i < NV; ++i)
 #pragma unroll
         for (int k = 0; k < M; ++k) fv[i][k] = (double)f.ld(fi + (int64_t)(i * M + k) * nodes + node);
-#pragma unroll
-      for (int k = 0; k < M; ++k) {
-        // Neumaier compensated sum over velocities, fixed order
-        double s = fv[0][k], comp = 0.0;
-#pragma unroll
-        for (int i = 1; i < NV; ++i) {
-          const double x = fv[i][k];
-          const double tt = s + x;
-          comp += (fabs(s) >= fabs(x)) ? ((s - tt) + x) : ((x - tt) + s);
-          s = tt;
-        }
-        w[k] = s + comp;
-      }
+      moments<NV, M>(fv, w);
     } else {
 #pragma unroll
       for (int k = 0; k < M; ++k) w[k] = w_in[d.w_base + (int64_t)k * nodes + node];
