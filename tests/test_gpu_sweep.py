@@ -109,7 +109,7 @@ def test_sweep_tile_shapes_agree(lib, monkeypatch):
     torch = pytest.importorskip("torch")
     case = ("2d_70x130_d1_m2", 2, (70, 130), 1, 1.0, 2)
     base, _ = _run_case(lib, torch, case, 0, 0.5, False, seed=5)
-    for tile in ["8,1", "16,2", "32,4", "64,8", "4,8"]:
+    for tile in ["8,1", "16,2", "32,4", "64,8", "4,8", "1,2", "2,4", "8,8"]:
         monkeypatch.setenv("PDG_TILE", tile)
         (l2, mx), _ = _run_case(lib, torch, case, 0, 0.5, False, seed=5)
         assert l2 <= 1e-12 and mx <= 1e-11, tile
