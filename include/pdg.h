@@ -137,9 +137,10 @@ typedef struct {
   const double *edges[3]; /* optional, host: cell edges along axis k (n[k] + 1 strictly increasing
                              finite values; copied), a tensor-product graded mesh of box cells;
                              NULL: uniform cells on [lo[k], hi[k]].  Given edges replace lo/hi.
-                             Velocities with two or three non-zero components along a graded
-                             axis are PDG_EUNSUPPORTED at prepare (their dense cell blocks would
-                             differ from cell to cell). */
+                             Velocities with two or three non-zero components along graded
+                             axes keep one dense cell block per combination of distinct cell
+                             sizes along those axes (prepared on the device like the others;
+                             the transfer schedule is for uniform cells only). */
   double axes[9];       /* optional uniform affine lattice (Sec. 3.1, affine cell maps): axes[3 k + i]
                            is component i of the edge vector a_k shared by every cell, for k, i < D;
                            cell (c_0, .., c_{D-1}) is lo + sum_k (c_k + [0, 1]) a_k, every cell the
@@ -200,7 +201,8 @@ pdg_status pdg_line_operator(const pdg_ctx *c, int32_t inst, int32_t vel, double
  * each non-zero component); kappa[a] (3 values) is the inflow coupling
  * magnitude of axis a (Gamma_{L<-R} = -kappa[a] at the inflow face nodes; 0 if
  * v_a = 0).  On uniform Cartesian cells the block is the Kronecker sum of the
- * one-dimensional blocks of the non-zero components.  Host only. */
+ * one-dimensional blocks of the non-zero components; on graded axes it is the
+ * block of the upwind-most cell.  Host only. */
 pdg_status pdg_cell_operator(const pdg_ctx *c, int32_t inst, int32_t vel, double *gamma, double *kappa);
 
 /* Prepare the time step (Sec. 3.2): for every instance, velocity and

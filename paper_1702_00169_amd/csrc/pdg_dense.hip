@@ -231,6 +231,7 @@ __global__ __launch_bounds__(128) void dense_transfer_operator_kernel(double *ta
   if (c >= NR) return;
   double *row = table + row_off[blockIdx.x];
   const DenseDesc &d = descs[row_desc[blockIdx.x]];
+  if (d.nshape > 1) return;  // graded cells: rows without a transfer operator
   const DenseRowLayout L{N, F};
   const double th = d.theta;
   const double *g0 = row + L.g(0);
@@ -666,14 +667,29 @@ __global__ __launch_bounds__(kDenseThreads) void dense_sweep_kernel(
     }
   }
   const int64_t cell = x[0] + (int64_t)d.n[0] * (x[1] + (int64_t)d.n[1] * x[2]);
-  const double *row = table + d.op_off + (int64_t)dt_idx * d.op_stride;
+  // the operator row of this cell's size class (one class on uniform cells)
+  const bool graded = d.nshape > 1;  // wave-uniform
+  int64_t shape = 0;
+  if (graded) {
+#pragma unroll
+    for (int a = 0; a < DIM; ++a)
+      if (d.rank_off[a] >= 0) {
+        const int xa = min(max(x[a], 0), d.n[a] - 1);  // lanes past the mesh read a valid class
+        shape += (int64_t)table[d.rank_off[a] + xa] * d.rank_stride[a];
+      }
+  }
+  const double *row = table + d.op_off + ((int64_t)dt_idx * d.nshape + shape) * d.op_stride;
   const DenseRowLayout L{N, F};
 
-  // Stage the coupling blocks G_a in LDS (vector loads, all lanes), load the
-  // cell and apply the local block.
+  // Stage the coupling blocks G_a in LDS (vector loads, all lanes; graded
+  // meshes read each cell's own from its row), load the cell and apply the
+  // local block.
+  if (!graded) {
 #pragma unroll
-  for (int a = 0; a < DIM; ++a)
-    for (int e = t; e < N * F; e += kDenseThreads) gl[a][e / F][e % F] = (Rt)row[L.g(a) + e];
+    for (int a = 0; a < DIM; ++a)
+      for (int e = t; e < N * F; e += kDenseThreads) gl[a][e / F][e % F] = (Rt)row[L.g(a) + e];
+  }
+  auto G = [&](int a, int q, int tt) -> Rt { return graded ? (Rt)row[L.g(a) + q * F + tt] : gl[a][q][tt]; };
   Rt fv[N], y[N];
 #pragma unroll
   for (int q = 0; q < N; ++q) fv[q] = active ? f.ld(fm.f_base + d.plane_off[q] + cell) : (Rt)0;
@@ -774,7 +790,7 @@ __global__ __launch_bounds__(kDenseThreads) void dense_sweep_kernel(
       for (int q = 0; q < N; ++q)
         if (on_out_face<NP, DIM>(q))
 #pragma unroll
-          for (int tt = 0; tt < F; ++tt) gr[a][q][tt] = gl[a][q][tt];
+          for (int tt = 0; tt < F; ++tt) gr[a][q][tt] = G(a, q, tt);
   }
 
   // Claimed schedule: a cell's traces from upwind tiles are requested AHEAD
@@ -864,7 +880,7 @@ __global__ __launch_bounds__(kDenseThreads) void dense_sweep_kernel(
         for (int q = 0; q < N; ++q) {
           if (!on_out_face<NP, DIM>(q)) continue;
 #pragma unroll
-          for (int tt = 0; tt < F; ++tt) yo[q] = fma(kRegG ? gr[a][q][tt] : gl[a][q][tt], uin[a][tt], yo[q]);
+          for (int tt = 0; tt < F; ++tt) yo[q] = fma(kRegG ? gr[a][q][tt] : G(a, q, tt), uin[a][tt], yo[q]);
         }
       }
       // outflow traces: theta x + (1 - theta) f^n on each downwind face
@@ -907,7 +923,7 @@ __global__ __launch_bounds__(kDenseThreads) void dense_sweep_kernel(
 #pragma unroll
     for (int q = 0; q < N; ++q)
 #pragma unroll
-      for (int tt = 0; tt < F; ++tt) y[q] = fma(gl[a][q][tt], uin[a][tt], y[q]);
+      for (int tt = 0; tt < F; ++tt) y[q] = fma(G(a, q, tt), uin[a][tt], y[q]);
   }
 #pragma unroll
   for (int q = 0; q < N; ++q) f.st(fm.f_base + d.plane_off[q] + cell, y[q]);

@@ -940,7 +940,14 @@ pdg_status pdg_cell_operator(const pdg_ctx *c, int32_t inst, int32_t vel, double
   const Instance &in = c->inst[inst];
   if (vel < 0 || vel >= in.d.nv) return PDG_EINVAL;
   std::vector<double> gam;
-  dense_block(in.d.dim, in.d.degree, &in.vt[(size_t)vel * in.d.dim], in.ht, gam, kappa);
+  // graded axes: the sizes of the upwind-most cell
+  double h[3] = {in.ht[0], in.ht[1], in.ht[2]};
+  for (int a = 0; a < in.d.dim; ++a)
+    if (in.graded[a]) {
+      const int64_t first = in.sgn[vel][a] >= 0 ? 0 : in.n[a] - 1;
+      h[a] = in.edge[a][(size_t)first + 1] - in.edge[a][(size_t)first];
+    }
+  dense_block(in.d.dim, in.d.degree, &in.vt[(size_t)vel * in.d.dim], h, gam, kappa);
   std::memcpy(gamma, gam.data(), gam.size() * sizeof(double));
   return PDG_OK;
 }
@@ -963,9 +970,6 @@ static pdg_status prepare_impl(pdg_ctx *c, double dt, double theta, double omega
   for (const Instance &in : c->inst)
     for (int v = 0; v < in.d.nv; ++v) {
       if (in.ndep[v] >= 2 && in.nd > kDenseMaxN) return PDG_EUNSUPPORTED;
-      // dense blocks on graded axes would differ from cell to cell
-      for (int k = 0; k < in.d.dim; ++k)
-        if (in.ndep[v] >= 2 && in.sgn[v][k] != 0 && in.graded[k]) return PDG_EUNSUPPORTED;
     }
   hipStream_t st = static_cast<hipStream_t>(stream);
   c->release_device();
@@ -1176,30 +1180,69 @@ static pdg_status prepare_impl(pdg_ctx *c, double dt, double theta, double omega
           dd.face_q[a][t] = q;
           dd.fb_t[a][t] = tphys;
         }
-      // operator rows: one per transport sub-step
-      std::vector<double> gam;
-      double kappa[3];
-      dense_block(dim, in.d.degree, &in.vt[(size_t)v * dim], in.ht, gam, kappa);
-      // 2D velocities with two non-zero components also keep the transfer
-      // operator of a full tile (2TF x 2TF, T = 8)
+      // operator rows: one per transport sub-step and cell-size class.  On a
+      // graded axis with a non-zero component the block depends on the cell
+      // size, so the distinct sizes of that axis are classes and a row is kept
+      // for every combination of classes (nshape rows per sub-step).
+      std::vector<double> hcls[3];
+      std::vector<int32_t> cls_of[3];
+      double hcell[3] = {in.ht[0], in.ht[1], in.ht[2]};
+      int nshape = 1;
+      for (int a = 0; a < 3; ++a) {
+        dd.rank_off[a] = -1;
+        dd.rank_stride[a] = 0;
+        if (a >= dim || dd.sgn[a] == 0 || !in.graded[a]) continue;
+        std::vector<double> hs((size_t)in.n[a]);
+        for (int64_t i = 0; i < in.n[a]; ++i) hs[(size_t)i] = in.edge[a][(size_t)i + 1] - in.edge[a][(size_t)i];
+        std::vector<double> u = hs;
+        std::sort(u.begin(), u.end());
+        u.erase(std::unique(u.begin(), u.end()), u.end());
+        hcell[a] = u[0];
+        if (u.size() == 1) continue;  // evenly spaced edges: one class
+        cls_of[a].resize(hs.size());
+        for (size_t i = 0; i < hs.size(); ++i)
+          cls_of[a][i] = (int32_t)(std::lower_bound(u.begin(), u.end(), hs[i]) - u.begin());
+        hcls[a] = u;
+        dd.rank_stride[a] = nshape;
+        nshape *= (int)u.size();
+      }
+      dd.nshape = nshape;
+      std::vector<std::vector<double>> gams((size_t)nshape);
+      std::vector<std::array<double, 3>> kaps((size_t)nshape);
+      for (int sh = 0; sh < nshape; ++sh) {
+        double h[3] = {hcell[0], hcell[1], hcell[2]};
+        for (int a = 0; a < 3; ++a)
+          if (!hcls[a].empty()) h[a] = hcls[a][(size_t)(sh / dd.rank_stride[a]) % hcls[a].size()];
+        dense_block(dim, in.d.degree, &in.vt[(size_t)v * dim], h, gams[(size_t)sh], kaps[(size_t)sh].data());
+      }
+      // 2D velocities with two non-zero components on uniform cells also keep
+      // the transfer operator of a full tile (2TF x 2TF, T = 8)
       const int64_t nr = 2LL * 8 * F;
-      const int64_t stride_row = 4LL * N * N + 3LL * N * F + (dim == 2 ? nr * nr : 0);
+      const int64_t stride_row = 4LL * N * N + 3LL * N * F + (dim == 2 && nshape == 1 ? nr * nr : 0);
       dd.op_off = (int64_t)dtable.size();
       dd.op_stride = stride_row;
       const int desc_index = (int)ddesc.size();
-      for (double ds : dts) {
-        const int64_t off = (int64_t)dtable.size();
-        dtable.resize(dtable.size() + stride_row, 0.0);
-        for (int i = 0; i < N; ++i)
-          for (int j = 0; j < N; ++j) {
-            const double id = i == j ? 1.0 : 0.0;
-            dtable[off + (int64_t)N * N + 3LL * N * F + i * N + j] = id + theta * ds * gam[(size_t)i * N + j];
-            dtable[off + 2LL * N * N + 3LL * N * F + i * N + j] = id - (1.0 - theta) * ds * gam[(size_t)i * N + j];
-          }
-        drow_off.push_back(off);
-        drow_desc.push_back(desc_index);
-        for (int a = 0; a < 3; ++a) drow_c0.push_back(ds * kappa[a]);
-      }
+      for (double ds : dts)
+        for (int sh = 0; sh < nshape; ++sh) {
+          const std::vector<double> &gam = gams[(size_t)sh];
+          const int64_t off = (int64_t)dtable.size();
+          dtable.resize(dtable.size() + stride_row, 0.0);
+          for (int i = 0; i < N; ++i)
+            for (int j = 0; j < N; ++j) {
+              const double id = i == j ? 1.0 : 0.0;
+              dtable[off + (int64_t)N * N + 3LL * N * F + i * N + j] = id + theta * ds * gam[(size_t)i * N + j];
+              dtable[off + 2LL * N * N + 3LL * N * F + i * N + j] = id - (1.0 - theta) * ds * gam[(size_t)i * N + j];
+            }
+          drow_off.push_back(off);
+          drow_desc.push_back(desc_index);
+          for (int a = 0; a < 3; ++a) drow_c0.push_back(ds * kaps[(size_t)sh][a]);
+        }
+      // size class of every cell coordinate along the graded axes
+      for (int a = 0; a < 3; ++a)
+        if (!cls_of[a].empty()) {
+          dd.rank_off[a] = (int64_t)dtable.size();
+          for (int32_t k : cls_of[a]) dtable.push_back((double)k);
+        }
       ddesc.push_back(dd);
       ddshape.push_back({np, dim});
       // families (component x transverse slice) and their tiles
@@ -1315,7 +1358,8 @@ static pdg_status prepare_impl(pdg_ctx *c, double dt, double theta, double omega
       const int gi = fam_group[fi];
       if (gi < 0) continue;
       const bool full = dd.n[0] % 8 == 0 && dd.n[1] % 8 == 0 && dd.sgn[0] != 0 && dd.sgn[1] != 0;
-      if (!full || std::min(fmd.nt[0], fmd.nt[1]) > 64) dgroups[gi].transfer_ok = false;
+      // one transfer operator per (velocity, sub-step): uniform cells only
+      if (!full || dd.nshape > 1 || std::min(fmd.nt[0], fmd.nt[1]) > 64) dgroups[gi].transfer_ok = false;
       dgroups[gi].tmax_diag = std::max(dgroups[gi].tmax_diag, std::min(fmd.nt[0], fmd.nt[1]));
     }
     for (size_t gi = 0; gi < dgroups.size(); ++gi) {

@@ -156,6 +156,14 @@ struct DenseDesc {
   int32_t out_q[3][kDenseMaxF];      // local node of outflow-face node t of axis a (q_a = NP-1)
   int32_t fb_t[3][kDenseMaxF];       // physical face-node index (fb layout) of face node t
   int32_t trans_axis;                // zero-component axis whose cells are independent, or -1
+  // Graded meshes: the block depends on the cell sizes along the non-zero
+  // components, so there is one operator row per size class (shape) and
+  // sub-step: row (dt_idx nshape + shape), shape = sum_a class_a rank_stride[a],
+  // class_a = table[rank_off[a] + x_a] (a small integer stored as a double)
+  // for the cell coordinate x_a; rank_off[a] = -1 where axis a has one class.
+  int64_t rank_off[3];
+  int32_t rank_stride[3];
+  int32_t nshape;                    // operator rows per sub-step (1: uniform cells)
   double theta;
 };
 

@@ -398,10 +398,34 @@ def test_graded_edges_are_validated(lib, edges):
     assert e.value.status == lib.PDG_EINVAL
 
 
-def test_dense_velocity_on_a_graded_axis_is_unsupported(lib):
-    edges = [W.graded_edges(5, 0.0, 1.0, 1.0), None]
-    prob = lib.Problem([_desc(n=[5, 3], v=[[1.0, 1.0], [1.0, 0.0]], edges=edges)])
-    assert lib._lib.pdg_prepare(prob.ctx, 0.01, 0.5, 2.0, 2, 0, None) == lib.PDG_EUNSUPPORTED
+@pytest.mark.parametrize("dim,degree,vel", [
+    (2, 2, (1.0, 1.0)), (2, 3, (-0.7, 0.4)), (2, 1, (0.3, -1.1)), (3, 2, (1.0, -1.0, 0.5)), (3, 1, (0.0, 0.8, -0.3)),
+])
+def test_graded_dense_cell_operator_is_the_oracle_block_of_the_first_cell(lib, dim, degree, vel):
+    """Dense velocities on graded meshes: the block of the upwind-most cell
+    (cell sizes of that cell along every graded axis)."""
+    n = [4, 3, 3][:dim]
+    hi = [1.0, 1.7, 0.6][:dim]
+    edges = _graded_edges(n, hi, tuple(range(dim)))
+    prob = lib.Problem([_desc(dim=dim, n=n, degree=degree, v=[list(vel)], hi=hi, lo=[0.0] * dim, edges=edges)])
+    npn = degree + 1
+    nd = npn ** dim
+    gam = np.zeros(nd * nd)
+    kap = np.zeros(3)
+    lib.pdg_cell_operator(prob.ctx, 0, 0, gam, kap)
+    gam = gam.reshape(nd, nd)
+    m = omesh.Mesh(tuple(n), None, None, degree, edges)
+    multi = [0 if vel[a] >= 0 else n[a] - 1 for a in range(dim)]
+    cell = int(m.cell_flat(np.array([multi]))[0])
+    blk = otr.cell_blocks(m, np.array(vel), np.array([cell]))
+    idx = m.node_idx
+    q = np.zeros(nd, dtype=np.int64)
+    for i in range(nd):
+        for a in range(dim):
+            qa = idx[i, a] if vel[a] >= 0 else degree - idx[i, a]
+            q[i] += qa * npn ** a
+    np.testing.assert_allclose(gam[np.ix_(q, q)], blk.gll[0], rtol=1e-13,
+                               atol=1e-13 * max(1.0, np.abs(blk.gll[0]).max()))
     prob.close()
 
 

@@ -140,3 +140,62 @@ def test_dense_transfer_wide_diagonals(lib, prec, monkeypatch):
     (l2, mx), per_v = _run(lib, torch, case, prec)
     print(f"  rel L2 {l2:.3e} max {mx:.3e}; worst velocity {max(per_v):.3e}")
     assert l2 <= BARS[prec] and mx <= 10 * BARS[prec] and max(per_v) <= 10 * BARS[prec]
+
+
+GRADED = [
+    # name, dim, n, degree, velocities, m, graded axes
+    ("d2q9_20x13_d2_gx", 2, (20, 13), 2, D2Q9, 1, (0,)),
+    ("d2q9_17x24_d1_gxy_m2", 2, (17, 24), 1, D2Q9 * 0.8, 2, (0, 1)),
+    ("d2q9_16x16_d3_gxy", 2, (16, 16), 3, D2Q9, 1, (0, 1)),
+    ("d3q27_7x6x5_d1_gxyz", 3, (7, 6, 5), 1, D3Q27, 1, (0, 1, 2)),
+    ("d3q27_6x5x6_d2_gz", 3, (6, 5, 6), 2, D3Q27 * 0.9, 1, (2,)),
+]
+
+
+def _graded_run(lib, torch, case, prec, seed=0):
+    name, dim, n, degree, vel, m, gaxes = case
+    inst = _instance((name, dim, n, degree, vel, m))
+    inst.edges = [W.graded_edges(n[k], inst.lo[k], inst.hi[k], 1.5, 0.3, seed=k) if k in gaxes else None
+                  for k in range(dim)]
+    print(f"graded dense case={name} prec={prec}", flush=True)
+    prob = lib.Problem([inst_dict(inst)])
+    nc, nd = sizes(inst)
+    hmin = min(np.min(np.diff(e)) if e is not None else (inst.hi[k] - inst.lo[k]) / n[k]
+               for k, e in enumerate(inst.edges))
+    dt = 0.77 * hmin / np.max(np.abs(inst.vel))
+    prob.prepare(dt, theta=0.5, omega=2.0, precision=prec)
+    nv = inst.vel.shape[0]
+    f_or = W.random_state(seed, (nv, m, nc, nd))
+    if prec == 1:
+        f_or = f_or.astype(np.float32).astype(np.float64)
+    fo = W.smooth_field(seed + 1, dim, m)
+    fn = W.smooth_field(seed + 2, dim, m)
+    fbo = torch.tensor(gpu_fb_from_function(prob, [inst], lambda i, v, p: fo(p)), device="cuda")
+    fbn = torch.tensor(gpu_fb_from_function(prob, [inst], lambda i, v, p: fn(p)), device="cuda")
+    f = torch.tensor(oracle_to_gpu(f_or), dtype=torch.float32 if prec == 1 else torch.float64, device="cuda")
+    prob.transport_sweep(f, fbo, fbn, dt)
+    prob.sync_status()
+    got = gpu_to_oracle(f.double().cpu().numpy(), inst)
+    oprob = oracle_problem(inst)
+    ofo = oracle_fb_from_function(oprob, 0, lambda i, v, p: fo(p))
+    ofn = oracle_fb_from_function(oprob, 0, lambda i, v, p: fn(p))
+    want = np.empty_like(f_or)
+    for v in range(nv):
+        want[v] = otr.theta_step_sweep(oprob.mesh, inst.vel[v], f_or[v], ofo[v], ofn[v], dt, 0.5,
+                                       levels=oprob.levels(v))
+    per_v = [rel_errors(got[v], want[v])[0] for v in range(nv)]
+    prob.close()
+    return rel_errors(got, want), per_v
+
+
+@pytest.mark.parametrize("case", GRADED, ids=[c[0] for c in GRADED])
+@pytest.mark.parametrize("prec", [0, 2, 1], ids=["fp64", "fp32refine", "fp32"])
+def test_dense_sweep_on_graded_meshes_matches_oracle(lib, case, prec, schedule):
+    """Velocities with two or three non-zero components on graded meshes: one
+    dense block per combination of cell sizes (the transfer schedule does not
+    apply; its fixture value leaves the default schedule)."""
+    torch = pytest.importorskip("torch")
+    print(f"schedule={schedule}", flush=True)
+    (l2, mx), per_v = _graded_run(lib, torch, case, prec)
+    print(f"  rel L2 {l2:.3e} max {mx:.3e}; worst velocity {max(per_v):.3e}")
+    assert l2 <= BARS[prec] and mx <= 10 * BARS[prec] and max(per_v) <= 10 * BARS[prec]
