@@ -615,7 +615,7 @@ __device__ inline void dense_put_trace(uint64_t *p, double v) {
 // cells are solved diagonal by diagonal; the inflow traces of a cell come from
 // the previous diagonal through LDS, from an upwind tile through the trace
 // slots, or from the domain inflow data.
-template <int PREC, int NP, int DIM, int MODE>
+template <int PREC, int NP, int DIM, int MODE, bool GRADED>
 __global__ __launch_bounds__(kDenseThreads) void dense_sweep_kernel(
     const DenseTile *__restrict__ tiles, const int32_t *__restrict__ order, const DenseFam *__restrict__ fams,
     const DenseDesc *__restrict__ descs, const double *__restrict__ table, int dt_idx,
@@ -668,7 +668,7 @@ __global__ __launch_bounds__(kDenseThreads) void dense_sweep_kernel(
   }
   const int64_t cell = x[0] + (int64_t)d.n[0] * (x[1] + (int64_t)d.n[1] * x[2]);
   // the operator row of this cell's size class (one class on uniform cells)
-  const bool graded = d.nshape > 1;  // wave-uniform
+  const bool graded = GRADED && d.nshape > 1;  // wave-uniform
   int64_t shape = 0;
   if (graded) {
 #pragma unroll
@@ -990,20 +990,22 @@ template <int PREC, int NP, int DIM>
 hipError_t go_dense(int mode, const DenseTile *tiles, const int32_t *order, int n_tiles, const DenseFam *fams,
                     const DenseDesc *descs, const double *table, int dt_idx, StateBuf f, const double *fb_old,
                     const double *fb_new, uint64_t *traces, int32_t *counter, DenseErr err, hipStream_t st) {
-#define PDG_DENSE_MODE(M)                                                                                      \
-  hipLaunchKernelGGL((dense_sweep_kernel<PREC, NP, DIM, M>), dim3(n_tiles), dim3(kDenseThreads), 0, st, tiles, \
-                     order, fams, descs, table, dt_idx, State<PREC>::make(f), fb_old, fb_new, traces, counter, err, \
+#define PDG_DENSE_MODE(M, G)                                                                                    \
+  hipLaunchKernelGGL((dense_sweep_kernel<PREC, NP, DIM, M, G>), dim3(n_tiles), dim3(kDenseThreads), 0, st, tiles, \
+                     order, fams, descs, table, dt_idx, State<PREC>::make(f), fb_old, fb_new, traces, counter, err,  \
                      n_tiles)
   switch (mode) {
-    case kDenseClaim: PDG_DENSE_MODE(kDenseClaim); break;
-    case kDenseLevel: PDG_DENSE_MODE(kDenseLevel); break;
+    case kDenseClaim: PDG_DENSE_MODE(kDenseClaim, false); break;
+    case kDenseLevel: PDG_DENSE_MODE(kDenseLevel, false); break;
+    case kDenseClaim | kDenseGraded: PDG_DENSE_MODE(kDenseClaim, true); break;
+    case kDenseLevel | kDenseGraded: PDG_DENSE_MODE(kDenseLevel, true); break;
     case kDenseZero:
       if constexpr (DIM != 2) return hipErrorInvalidValue;  // the transfer schedule is two-dimensional
-      else PDG_DENSE_MODE(kDenseZero);
+      else PDG_DENSE_MODE(kDenseZero, false);
       break;
     case kDenseFinal:
       if constexpr (DIM != 2) return hipErrorInvalidValue;
-      else PDG_DENSE_MODE(kDenseFinal);
+      else PDG_DENSE_MODE(kDenseFinal, false);
       break;
     default: return hipErrorInvalidValue;
   }

@@ -105,6 +105,7 @@ struct DenseGroup {
   bool transfer = false;       // transfer schedule: zero-inflow tiles, trace wavefront, final tiles
   int64_t tfam_first = 0, tfam_count = 0;  // its families in the transfer family list
   int tmax_diag = 0;                       // longest tile diagonal of those families
+  bool graded = false;                     // some family has one operator row per cell-size class
 };
 
 // One (instance, velocity) family of chains and its launch class.
@@ -1360,6 +1361,7 @@ static pdg_status prepare_impl(pdg_ctx *c, double dt, double theta, double omega
       const bool full = dd.n[0] % 8 == 0 && dd.n[1] % 8 == 0 && dd.sgn[0] != 0 && dd.sgn[1] != 0;
       // one transfer operator per (velocity, sub-step): uniform cells only
       if (!full || dd.nshape > 1 || std::min(fmd.nt[0], fmd.nt[1]) > 64) dgroups[gi].transfer_ok = false;
+      if (dd.nshape > 1) dgroups[gi].graded = true;
       dgroups[gi].tmax_diag = std::max(dgroups[gi].tmax_diag, std::min(fmd.nt[0], fmd.nt[1]));
     }
     for (size_t gi = 0; gi < dgroups.size(); ++gi) {
@@ -1738,7 +1740,8 @@ pdg_status do_sweep(pdg_ctx *c, void *f, const double *fb_old, const double *fb_
     if (!g.claim) {
       // one launch per tile diagonal: no tile ever waits
       for (size_t k = 0; k + 1 < g.level.size(); ++k) {
-        hipError_t e = launch_dense_sweep(c->prec, kDenseLevel, g.np, g.dim, c->dtiles.p + g.first,
+        hipError_t e = launch_dense_sweep(c->prec, kDenseLevel | (g.graded ? kDenseGraded : 0), g.np, g.dim,
+                                          c->dtiles.p + g.first,
                                           c->dorder.p + g.first + g.level[k], (int)(g.level[k + 1] - g.level[k]),
                                           c->dfams.p, c->ddesc.p, c->dtable.p, dt_idx, StateBuf{f, c->f_elems}, fb_old, fb_new,
                                           sc.traces, sc.sync + g.sync_off, dense_err(c), st);
@@ -1746,7 +1749,8 @@ pdg_status do_sweep(pdg_ctx *c, void *f, const double *fb_old, const double *fb_
       }
       continue;
     }
-    hipError_t e = launch_dense_sweep(c->prec, kDenseClaim, g.np, g.dim, c->dtiles.p + g.first, c->dorder.p + g.first,
+    hipError_t e = launch_dense_sweep(c->prec, kDenseClaim | (g.graded ? kDenseGraded : 0), g.np, g.dim,
+                                      c->dtiles.p + g.first, c->dorder.p + g.first,
                                       (int)g.count, c->dfams.p, c->ddesc.p, c->dtable.p, dt_idx, StateBuf{f, c->f_elems}, fb_old, fb_new,
                                       sc.traces, sc.sync + g.sync_off, dense_err(c), st);
     if (e != hipSuccess) return from_hip_at(e, "launch_dense_sweep");

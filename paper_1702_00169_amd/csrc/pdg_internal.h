@@ -1,7 +1,7 @@
 // Internal data structures shared by the host runtime (pdg_host.cpp) and the
 // gfx950 kernels (pdg_sweep.hip: axis-aligned transport; pdg_local.hip:
-// node-local steps; pdg_dense.hip: dense transport).  Not part of the public
-// ABI.
+// node-local steps; pdg_dense.hip: dense transport; pdg_fused.hip: the fused
+// collision + x transport).  Not part of the public ABI.
 #pragma once
 
 #include <stdint.h>
@@ -284,6 +284,9 @@ hipError_t launch_dense_transfer(int np, int max_diag, const DenseTile *tiles, c
 // transfer schedule (tiles with zero upwind-tile inflow storing only their
 // outflow traces; tiles with their exact inflow storing only their cells).
 enum DenseMode { kDenseClaim = 0, kDenseLevel = 1, kDenseZero = 2, kDenseFinal = 3 };
+// Launch-mode flag: some family of the group has graded cells (an operator
+// row per cell-size class); claimed and levelled modes only.
+constexpr int kDenseGraded = 8;
 
 // Dense sweep of n_tiles tiles (claim order `order`) in the given mode; for
 // kDenseClaim the counter and the trace slots must be reset on entry.
