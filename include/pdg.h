@@ -297,9 +297,14 @@ pdg_status pdg_step(pdg_ctx *c, void *f, const double *fb, int32_t n_steps, void
  * 2..8; strided chains: chains per workgroup 8..64 x cells per thread
  * segment 1..8) with `reps`
  * launches of the class alone on `stream`, keeps the fastest, and uses it
- * from then on.  f is used as scratch and overwritten; fb is read.  Every tile
- * solves the same system; only the rounding order of the segment combine
- * differs.  Drops the cached step graph. */
+ * from then on.  Then, for every launch group of the dense path (velocities
+ * with two or three non-zero components), it times whole sweeps under each
+ * tile schedule the group allows (levelled, claimed and, for 2D meshes of
+ * full 8 x 8 uniform tiles, the transfer schedule) and keeps the fastest,
+ * unless PDG_DENSE_SCHEDULE was set at prepare.  f is used as scratch and
+ * overwritten; fb is read.  Every tile and schedule solves the same system;
+ * only the rounding order differs.  PDG_EDEVICE if a claimed wait gave up
+ * while timing.  Drops the cached step graph. */
 pdg_status pdg_autotune(pdg_ctx *c, void *f_scratch, const double *fb, int32_t reps, void *stream);
 
 /* Current tiles: *n_classes receives the number of launch classes; if

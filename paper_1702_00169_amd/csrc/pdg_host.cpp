@@ -2146,11 +2146,68 @@ static pdg_status autotune_impl(pdg_ctx *c, void *f, const double *fb, int32_t r
     k.C = bestC;
     k.S = bestS;
   }
+  if (status == PDG_OK) {
+    build_items(c, items);
+    status = upload_items(c, items);
+  }
+  // dense launch groups: time every schedule a group allows (levelled,
+  // claimed, transfer) over whole sweeps and keep the fastest;
+  // PDG_DENSE_SCHEDULE, when set, keeps the prepared choice
+  if (status == PDG_OK && !std::getenv("PDG_DENSE_SCHEDULE")) {
+    auto set_claim_flag = [c]() {
+      c->dense_claim = false;
+      for (const DenseGroup &h : c->dgroups) c->dense_claim = c->dense_claim || h.claim;
+    };
+    for (DenseGroup &g : c->dgroups) {
+      std::vector<int> cands = {0, 1};  // levelled, claimed
+      if (g.transfer_ok) cands.push_back(2);
+      int best_s = g.transfer ? 2 : (g.claim ? 1 : 0);
+      float best = 1e30f;
+      for (int sch : cands) {
+        g.claim = sch == 1;
+        g.transfer = sch == 2;
+        set_claim_flag();
+        hipError_t e = hipSuccess;
+        pdg_status ss = PDG_OK;
+        for (int r = 0; r <= reps && ss == PDG_OK && e == hipSuccess; ++r) {
+          if (r == 1) e = hipEventRecord(e0, st);
+          if (e == hipSuccess) ss = do_sweep(c, f, fb, fb, 0, st, ctx_scratch(c));
+        }
+        if (ss != PDG_OK) {
+          status = ss;
+          break;
+        }
+        if (e == hipSuccess) e = hipEventRecord(e1, st);
+        if (e == hipSuccess) e = hipEventSynchronize(e1);
+        float ms = 0.f;
+        if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+        if (e != hipSuccess) {
+          status = from_hip_at(e, "autotune timing (dense schedules)");
+          break;
+        }
+        if (dense_failed(c)) {  // a claimed wait gave up: the timing is invalid
+          status = PDG_EDEVICE;
+          break;
+        }
+        if (ms < best) {
+          best = ms;
+          best_s = sch;
+        }
+      }
+      g.claim = best_s == 1;
+      g.transfer = best_s == 2;
+      set_claim_flag();
+      if (status != PDG_OK) break;
+    }
+  }
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
-  build_items(c, items);
-  pdg_status s2 = upload_items(c, items);
-  return status != PDG_OK ? status : s2;
+  c->stats_valid = false;
+  if (c->gexec) (void)hipGraphExecDestroy(c->gexec);  // the step graph holds the old schedules
+  c->gexec = nullptr;
+  c->g_f = nullptr;
+  c->g_fb = nullptr;
+  return status;
 }
 
 pdg_status pdg_get_tiles(const pdg_ctx *c, int32_t *n_classes, int32_t *tiles) {

@@ -51,14 +51,22 @@ def _instance(case):
     return inst
 
 
-def _run(lib, torch, case, prec, theta=0.5, half=False, seed=0):
+def _run(lib, torch, case, prec, theta=0.5, half=False, seed=0, autotune=False):
     inst = _instance(case)
-    print(f"dense case={case[0]} prec={prec} theta={theta} half={half}", flush=True)
+    print(f"dense case={case[0]} prec={prec} theta={theta} half={half} autotune={autotune}", flush=True)
     prob = lib.Problem([inst_dict(inst)])
     nc, nd = sizes(inst)
     h = np.min((inst.hi - inst.lo) / np.array(inst.n))
     dt = 0.77 * h / np.max(np.abs(inst.vel))
     prob.prepare(dt, theta=theta, omega=2.0, precision=prec)
+    if autotune:
+        # tile and dense-schedule search on a scratch state (the sweep below
+        # then runs the chosen schedules)
+        scratch = torch.zeros(prob.layout["f_elems"], dtype=torch.float32 if prec == 1 else torch.float64,
+                              device="cuda")
+        fbz = torch.zeros(max(1, prob.layout["fb_elems"]), dtype=torch.float64, device="cuda")
+        prob.autotune(scratch, fbz, reps=1)
+        prob.sync_status()
     nv, m = inst.vel.shape[0], inst.m
     f_or = W.random_state(seed, (nv, m, nc, nd))
     if prec == 1:
@@ -199,3 +207,14 @@ def test_dense_sweep_on_graded_meshes_matches_oracle(lib, case, prec, schedule):
     (l2, mx), per_v = _graded_run(lib, torch, case, prec)
     print(f"  rel L2 {l2:.3e} max {mx:.3e}; worst velocity {max(per_v):.3e}")
     assert l2 <= BARS[prec] and mx <= 10 * BARS[prec] and max(per_v) <= 10 * BARS[prec]
+
+
+@pytest.mark.parametrize("case", [CASES[7], CASES[4], CASES[11]], ids=[CASES[7][0], CASES[4][0], CASES[11][0]])
+def test_autotuned_dense_schedule_matches_oracle(lib, case, monkeypatch):
+    """pdg_autotune also picks the dense schedule of every launch group by
+    timing; whatever it picks solves the same system."""
+    torch = pytest.importorskip("torch")
+    monkeypatch.delenv("PDG_DENSE_SCHEDULE", raising=False)
+    (l2, mx), per_v = _run(lib, torch, case, 0, autotune=True)
+    print(f"  rel L2 {l2:.3e} max {mx:.3e}; worst velocity {max(per_v):.3e}")
+    assert l2 <= 1e-12 and mx <= 1e-11 and max(per_v) <= 1e-11
