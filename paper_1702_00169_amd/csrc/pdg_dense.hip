@@ -19,8 +19,11 @@ struct DenseRowLayout {
   __host__ __device__ int64_t a_off() const { return n * n + 3 * n * f; }
   __host__ __device__ int64_t b_off() const { return 2 * n * n + 3 * n * f; }
   __host__ __device__ int64_t ai_off() const { return 3 * n * n + 3 * n * f; }
+  // A^{-1} rounded to binary32 (n^2 floats in (n^2 + 1) / 2 doubles): the
+  // refined solve reads its binary32 operands as they are
+  __host__ __device__ int64_t ai32_off() const { return 4 * n * n + 3 * n * f; }
   // transfer operator of a full tile (two-dimensional velocities only)
-  __host__ __device__ int64_t r_off() const { return 4 * n * n + 3 * n * f; }
+  __host__ __device__ int64_t r_off() const { return 4 * n * n + 3 * n * f + (n * n + 1) / 2; }
 };
 
 __global__ __launch_bounds__(kDenseThreads) void dense_invert_kernel(double *table, const int64_t *row_off,
@@ -97,6 +100,7 @@ __global__ __launch_bounds__(kDenseThreads) void dense_invert_kernel(double *tab
     for (int k = 0; k < n; ++k) acc = fma(inv[i][k], row[L.b_off() + (int64_t)k * n + j], acc);
     row[e] = acc;                       // M = Ainv B
     row[L.ai_off() + e] = inv[i][j];    // Ainv
+    reinterpret_cast<float *>(row + L.ai32_off())[e] = (float)inv[i][j];
   }
   for (int e = t; e < 3 * n * F; e += kDenseThreads) {
     const int ax = e / (n * F);
@@ -155,6 +159,7 @@ __device__ __forceinline__ void dense_local_solve(const double *row, const typen
   using Rt = typename Pol<PREC>::Rt;
   const DenseRowLayout L{N, F};
   if (refine_prec(PREC)) {
+    const float *ai32 = reinterpret_cast<const float *>(row + L.ai32_off());
     double r[N];
     float r32[N], y1[N];
 #pragma unroll
@@ -169,7 +174,7 @@ __device__ __forceinline__ void dense_local_solve(const double *row, const typen
     for (int i = 0; i < N; ++i) {
       float acc = 0.f;
 #pragma unroll
-      for (int j = 0; j < N; ++j) acc = fmaf((float)row[L.ai_off() + i * N + j], r32[j], acc);
+      for (int j = 0; j < N; ++j) acc = fmaf(ai32[i * N + j], r32[j], acc);
       y1[i] = acc;
     }
 #pragma unroll
@@ -183,7 +188,7 @@ __device__ __forceinline__ void dense_local_solve(const double *row, const typen
     for (int i = 0; i < N; ++i) {
       float acc = 0.f;
 #pragma unroll
-      for (int j = 0; j < N; ++j) acc = fmaf((float)row[L.ai_off() + i * N + j], r32[j], acc);
+      for (int j = 0; j < N; ++j) acc = fmaf(ai32[i * N + j], r32[j], acc);
       y[i] = (Rt)((double)y1[i] + (double)acc);
     }
   } else {

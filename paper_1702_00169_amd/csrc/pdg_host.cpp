@@ -1219,7 +1219,8 @@ static pdg_status prepare_impl(pdg_ctx *c, double dt, double theta, double omega
       // 2D velocities with two non-zero components on uniform cells also keep
       // the transfer operator of a full tile (2TF x 2TF, T = 8)
       const int64_t nr = 2LL * 8 * F;
-      const int64_t stride_row = 4LL * N * N + 3LL * N * F + (dim == 2 && nshape == 1 ? nr * nr : 0);
+      const int64_t stride_row =
+          4LL * N * N + 3LL * N * F + (N * N + 1) / 2 + (dim == 2 && nshape == 1 ? nr * nr : 0);
       dd.op_off = (int64_t)dtable.size();
       dd.op_stride = stride_row;
       const int desc_index = (int)ddesc.size();
