@@ -1,7 +1,7 @@
 // Internal data structures shared by the host runtime (pdg_host.cpp) and the
 // gfx950 kernels (pdg_sweep.hip: axis-aligned transport; pdg_local.hip:
-// node-local steps; pdg_dense.hip: dense transport; pdg_fused.hip: the fused
-// collision + x transport).  Not part of the public ABI.
+// node-local steps; pdg_dense.hip: dense transport).  Not part of the public
+// ABI.
 #pragma once
 
 #include <stdint.h>
@@ -109,8 +109,8 @@ struct InflowDesc {
   int32_t vel;
 };
 
-// Fused collision + x transport (instances whose velocities are the set
-// {+-lambda e_k} on a uniform box mesh).
+// Fused collision + x transport (pdg_fused.hip; instances whose velocities
+// are the set {+-lambda e_k} on a uniform box mesh).
 struct FusedDesc {
   int64_t nc;        // cells
   int64_t fb[2];     // fb offset of (+x / -x velocity, k = 0, t = 0, tau = 0)
