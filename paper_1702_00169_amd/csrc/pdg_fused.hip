@@ -27,45 +27,61 @@ namespace {
 // for all n_v m values of its node.
 constexpr int kFusedMaxThreads = 512;
 
-// Inclusive scan of I_l = a I_{l-1} + beta_l along one row held by the
-// threads of a block (one cell per thread, NW waves, cell x at lane x of the
-// block).  DIR = +1 scans with increasing x (chain position l = x), DIR = -1
-// with decreasing x (l = nx - 1 - x); padding lanes past the row's end carry
-// l = 0 and beta = 0, so they never feed a cell of the row.  apow[s] =
-// a^(2^s), alane = a^(k + 1) with k the thread's distance from the wave edge
-// it scans from.  Returns I; prev receives the I of the upwind neighbour (or
-// the carry into the wave for the wave's first element).  Every thread of
-// the workgroup calls it (it synchronises the workgroup once).
-template <class Rt, int DIR>
-__device__ __forceinline__ Rt row_scan(Rt beta, int l, const Rt (&apow)[7], Rt alane, Rt (*wtot)[kFusedMaxThreads / 64], int nwb,
-                                       int par, Rt &prev) {
+// Component passes of one direction at most: ceil(m / (d+1)) over the
+// supported (d+1, m).
+constexpr int kFusedKB = 3;
+
+// Inclusive scans of I_l = a I_{l-1} + beta_l along one row, KB of them at
+// once (the component passes of one direction: their shuffles interleave and
+// they share one barrier), held by the threads of a block (one cell per
+// thread, NW waves, cell x at lane x of the block).  DIR = +1 scans with
+// increasing x (chain position l = x), DIR = -1 with decreasing x
+// (l = nx - 1 - x); padding lanes past the row's end carry l = 0 and
+// beta = 0, so they never feed a cell of the row.  apow[s] = a^(2^s),
+// alane = a^(k + 1) with k the thread's distance from the wave edge it scans
+// from.  I receives the scans of beta; prev the I of the upwind neighbour
+// (or the carry into the wave for the wave's first element).  Every thread
+// of the workgroup calls it (it synchronises the workgroup once).
+template <class Rt, int DIR, int KB>
+__device__ __forceinline__ void row_scan(const Rt (&beta)[KB], int l, const Rt (&apow)[7], Rt alane,
+                                         Rt (*wtot)[kFusedKB][kFusedMaxThreads / 64], int nwb, int par,
+                                         Rt (&I)[KB], Rt (&prev)[KB]) {
   const int t = threadIdx.x;
   const int lane = t & 63, wv = t >> 6;
   const int b0 = (wv / nwb) * nwb;           // first wave of this thread's block
   const int k = DIR > 0 ? lane : 63 - lane;  // elements before this one in scan order within the wave
   const int kw = l < k ? l : k;              // of them, those in the row
-  Rt I = beta;
+#pragma unroll
+  for (int j = 0; j < KB; ++j) I[j] = beta[j];
 #pragma unroll
   for (int s = 0; s < 6; ++s) {
     const int dd = 1 << s;
-    const Rt up = DIR > 0 ? __shfl_up(I, dd, 64) : __shfl_down(I, dd, 64);
-    if (kw >= dd) I = fma(apow[s], up, I);
+#pragma unroll
+    for (int j = 0; j < KB; ++j) {
+      const Rt up = DIR > 0 ? __shfl_up(I[j], dd, 64) : __shfl_down(I[j], dd, 64);
+      if (kw >= dd) I[j] = fma(apow[s], up, I[j]);
+    }
   }
-  if (k == 63) wtot[par][wv] = I;  // the wave's total (a full wave of the row: l >= 63 here)
+  if (k == 63) {  // the wave's totals (a full wave of the row: l >= 63 here)
+#pragma unroll
+    for (int j = 0; j < KB; ++j) wtot[par][j][wv] = I[j];
+  }
   __syncthreads();
   // carry into this wave: the totals of the block's waves before it in scan
   // order, each a full wave of the row
-  Rt cin = 0;
   const int wi = wv - b0;
   const int nbefore = DIR > 0 ? wi : nwb - 1 - wi;
-  for (int i = 0; i < nbefore; ++i) {
-    const int w = DIR > 0 ? b0 + i : b0 + nwb - 1 - i;
-    cin = fma(apow[6], cin, wtot[par][w]);
+#pragma unroll
+  for (int j = 0; j < KB; ++j) {
+    Rt cin = 0;
+    for (int i = 0; i < nbefore; ++i) {
+      const int w = DIR > 0 ? b0 + i : b0 + nwb - 1 - i;
+      cin = fma(apow[6], cin, wtot[par][j][w]);
+    }
+    if (l > k) I[j] = fma(alane, cin, I[j]);
+    const Rt nb = DIR > 0 ? __shfl_up(I[j], 1, 64) : __shfl_down(I[j], 1, 64);
+    prev[j] = k > 0 ? nb : cin;
   }
-  if (l > k) I = fma(alane, cin, I);
-  const Rt nb = DIR > 0 ? __shfl_up(I, 1, 64) : __shfl_down(I, 1, 64);
-  prev = k > 0 ? nb : cin;
-  return I;
 }
 
 // One workgroup per row of cells (instance, transverse node jt, row tau) and
@@ -81,7 +97,7 @@ __global__ __launch_bounds__(kFusedMaxThreads) void relax_xsweep_kernel(
     double *__restrict__ stats) {
   using Rt = typename Pol<PREC>::Rt;
   extern __shared__ __align__(16) unsigned char fused_lds[];
-  __shared__ Rt wtot[2][kFusedMaxThreads / 64];
+  __shared__ Rt wtot[2][kFusedKB][kFusedMaxThreads / 64];
   __shared__ double red[2][kFusedMaxThreads / 64];
   const FusedItem it = items[blockIdx.x];
   const FusedDesc fd = fdescs[it.desc];
@@ -107,7 +123,7 @@ __global__ __launch_bounds__(kFusedMaxThreads) void relax_xsweep_kernel(
   // ---- collision at node (jx = b, jt) of cell x ----
   {
     // planes of the instance from scalar bases, nodes by 32-bit offsets
-    const uint32_t node = (uint32_t)((int64_t)(b + NP * jt) * fd.nc + cell);
+    uint32_t node = (uint32_t)((int64_t)(b + NP * jt) * fd.nc + cell);
     typename State<PREC>::Raw fr[NV][M];
 #pragma unroll
     for (int i = 0; i < NV; ++i)
@@ -120,6 +136,10 @@ __global__ __launch_bounds__(kFusedMaxThreads) void relax_xsweep_kernel(
       for (int k = 0; k < M; ++k) fv[i][k] = (double)f.dec(fr[i][k]);
     double w[M];
     moments<NV, M>(fv, w);
+    // The stores below recompute their addresses from here on: without this
+    // the compiler keeps the 64-bit address of every load live until the
+    // store to the same place, 2 n_v m registers more per thread.
+    asm volatile("" : "+v"(node));
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
       if (a >= rd.dim) break;
@@ -145,7 +165,6 @@ __global__ __launch_bounds__(kFusedMaxThreads) void relax_xsweep_kernel(
 
   // ---- the chains of +x and -x along the row ----
   double cmax = 0.0, ymax = 0.0;
-  int par = 0;
 #pragma unroll
   for (int h = 0; h < 2; ++h) {
     CellOp<PREC, NP> op;
@@ -164,34 +183,40 @@ __global__ __launch_bounds__(kFusedMaxThreads) void relax_xsweep_kernel(
       if ((kk + 1) & (1 << s)) alane *= apow[s];
     const int l = cell_ok ? (h == 0 ? x : nx - 1 - x) : 0;  // chain position; padding lanes start nothing
     const int v = fd.vx[h];
+    constexpr int KB = (M + NP - 1) / NP;
+    static_assert(KB <= kFusedKB, "component passes per direction");
+    Rt y[KB][NP], beta[KB], ub[KB];
 #pragma unroll
-    for (int kb = 0; kb < (M + NP - 1) / NP; ++kb, par ^= 1) {
+    for (int kb = 0; kb < KB; ++kb) {
       const int k = kb * NP + b;
       const bool on = cell_ok && k < M;
       Rt fl[NP];  // downwind-local order: node 0 receives the inflow
 #pragma unroll
       for (int q = 0; q < NP; ++q) fl[q] = on ? fx_at(h, k, h == 0 ? q : NP - 1 - q) : (Rt)0;
-      Rt y[NP];
-      op.solve(fl, y, cmax, ymax);
-      Rt beta = on ? theta * y[NP - 1] + omt * fl[NP - 1] : (Rt)0;
-      Rt ub = 0;
+      op.solve(fl, y[kb], cmax, ymax);
+      beta[kb] = on ? theta * y[kb][NP - 1] + omt * fl[NP - 1] : (Rt)0;
+      ub[kb] = 0;
       if (on && l == 0) {
         const int64_t bo = fd.fb[h] + ((int64_t)k * fd.tnodes + jt) * fd.ntau + tau;
-        ub = theta * (Rt)fb_new[bo] + omt * (Rt)fb_old[bo];
-        beta = fma(a, ub, beta);
+        ub[kb] = theta * (Rt)fb_new[bo] + omt * (Rt)fb_old[bo];
+        beta[kb] = fma(a, ub[kb], beta[kb]);
       }
-      Rt prev;
-      if (h == 0)
-        row_scan<Rt, 1>(beta, l, apow, alane, wtot, nwb, par, prev);
-      else
-        row_scan<Rt, -1>(beta, l, apow, alane, wtot, nwb, par, prev);
-      const Rt u = l == 0 ? ub : prev;
-      if (on) {
+    }
+    Rt I[KB], prev[KB];
+    if (h == 0)
+      row_scan<Rt, 1, KB>(beta, l, apow, alane, wtot, nwb, h, I, prev);
+    else
+      row_scan<Rt, -1, KB>(beta, l, apow, alane, wtot, nwb, h, I, prev);
+#pragma unroll
+    for (int kb = 0; kb < KB; ++kb) {
+      const int k = kb * NP + b;
+      if (cell_ok && k < M) {
+        const Rt u = l == 0 ? ub[kb] : prev[kb];
         const State<PREC> pv = f.at(fi + (int64_t)(v * M + k) * nodes);
 #pragma unroll
         for (int q = 0; q < NP; ++q) {
           const int jx = h == 0 ? q : NP - 1 - q;
-          pv.st32((uint32_t)((int64_t)(jx + NP * jt) * fd.nc + cell), fma(op.g[q], u, y[q]));
+          pv.st32((uint32_t)((int64_t)(jx + NP * jt) * fd.nc + cell), fma(op.g[q], u, y[kb][q]));
         }
       }
     }

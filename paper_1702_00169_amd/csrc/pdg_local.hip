@@ -54,7 +54,8 @@ __global__ __launch_bounds__(kBlock) void relax_kernel(const RelaxItem *__restri
   const int64_t fi = d.f_base;
   const double inv_nv = 1.0 / NV;
   const double h2l = 0.5 / d.lambda;
-  for (int64_t node = it.node0 + threadIdx.x; node < it.node0 + it.count; node += kBlock) {
+  for (int64_t node0 = it.node0 + threadIdx.x; node0 < it.node0 + it.count; node0 += kBlock) {
+    int64_t node = node0;
     double w[M];
     double fv[NV][M];
     if (mode == 0) {
@@ -63,6 +64,11 @@ __global__ __launch_bounds__(kBlock) void relax_kernel(const RelaxItem *__restri
 #pragma unroll
         for (int k = 0; k < M; ++k) fv[i][k] = (double)f.ld(fi + (int64_t)(i * M + k) * nodes + node);
       moments<NV, M>(fv, w);
+      // 48-bit state: make the stores recompute their addresses, or the
+      // compiler keeps the two 64-bit plane addresses of every load live
+      // until the store to the same place (measured: fewer registers for
+      // n_v m <= 20, more for the larger sets, so those keep the default)
+      if constexpr (PREC == kP48 && NV * M <= 20) asm volatile("" : "+v"(node));
     } else {
 #pragma unroll
       for (int k = 0; k < M; ++k) w[k] = w_in[d.w_base + (int64_t)k * nodes + node];
