@@ -216,7 +216,15 @@ pdg_status pdg_cell_operator(const pdg_ctx *c, int32_t inst, int32_t vel, double
  * omega is the collision factor of eq. collision_cn over dt (2 dt/(2 tau + dt);
  * 2 is tau = 0); collisions over other sub-steps h use 2h/(2 tau + h).
  * Allocates the context's device tables; synchronises `stream`.
- * theta in (0, 1], dt finite and non-zero (negative dt runs time backwards). */
+ * theta in (0, 1], dt finite and non-zero (negative dt runs time backwards).
+ * Environment read here: PDG_FUSED=1 makes pdg_step run each collision of
+ * the collapsed Strang scheme together with the transport of the velocities
+ * along x, in one pass over the state (instances whose velocities are
+ * {+-lambda e_k} on a uniform box mesh, m = 1 or the Euler m, and
+ * (d+1) * (n_x rounded up to 64) <= 512; the others keep separate passes;
+ * the results agree to rounding); PDG_SWEEP_MIXED=0 gives each node count of a batch its own
+ * sweep launch; PDG_DENSE_SCHEDULE=level|claim|transfer fixes the dense tile
+ * schedule. */
 pdg_status pdg_prepare(pdg_ctx *c, double dt, double theta, double omega, pdg_scheme scheme,
                        pdg_precision prec, void *stream);
 
