@@ -283,6 +283,8 @@ def main():
     ap.add_argument("--no-compare", action="store_true", help="skip the other precisions")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-autotune", action="store_true", help="keep the default tiles")
+    ap.add_argument("--no-fused", action="store_true",
+                    help="skip the steps with the opt-in fused collision + x transport (PDG_FUSED=1)")
     ap.add_argument("--tiles", default=None,
                     help="JSON list of tiles ({np, x_kind, C, S}) to apply instead of autotuning (main precision)")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
@@ -319,6 +321,31 @@ def main():
         print(f"[bench]   {results[p]['value']:.4e} DoF/s, sweep {results[p]['sweep_us']:.1f} us "
               f"({results[p]['sweep_gbs']:.0f} GB/s), relax {results[p]['relax_us']:.1f} us", file=sys.stderr,
               flush=True)
+    # the same steps with the opt-in fused collision + x transport (read at
+    # prepare), on the tiles chosen above; reported beside the headline
+    fused_report = None
+    if compare and not args.no_fused:
+        fused_report = {}
+        old_env = os.environ.get("PDG_FUSED")
+        os.environ["PDG_FUSED"] = "1"
+        try:
+            for p in dict.fromkeys((prec_main, 0)):
+                print(f"[bench] {args.workload} {PREC_NAMES[p]} with PDG_FUSED=1: {args.warmup} warm-up + "
+                      f"{args.steps} timed steps", file=sys.stderr, flush=True)
+                r, _ = measure(pdg, torch, wl, p, args.steps, args.warmup, args.reps, autotune=False,
+                               tiles=results[p]["tiles"])
+                fused_report[PREC_NAMES[p]] = {"value": r["value"], "ms_per_step": r["ms_per_step"],
+                                               "vs_separate_passes": r["value"] / results[p]["value"]}
+                print(f"[bench]   {r['value']:.4e} DoF/s ({r['value'] / results[p]['value']:.3f} x separate passes)",
+                      file=sys.stderr, flush=True)
+        finally:
+            if old_env is None:
+                os.environ.pop("PDG_FUSED", None)
+            else:
+                os.environ["PDG_FUSED"] = old_env
+        fused_report["note"] = ("opt-in (PDG_FUSED=1, read at prepare): each collision of the collapsed step runs "
+                                "with the x transport in one pass over the state where the instance allows it; "
+                                "value above is without it")
     # a plain device copy of the state's size: the practical streaming ceiling
     copy_mib = args.copy_probe_mib or max(256, min(4096, results[prec_main]["bytes_per_sweep"] // 2 // 2 ** 20))
     x = torch.empty(copy_mib * 2 ** 20 // 8, dtype=torch.float64, device="cuda")
@@ -377,6 +404,8 @@ def main():
            "steps": args.steps, "warmup": args.warmup, "ms_per_step": main_res["ms_per_step"],
            "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": DTYPE_NAMES[prec_main],
            "data": "synthetic", "config": config, "roofline": roof, "precisions": prec_report}
+    if fused_report is not None:
+        out["fused"] = fused_report
     if not args.no_cpu:
         print("[bench] cpu baseline (oracle)", file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline(args.workload if args.workload != "batch96" else "adv2d_16", args.seed,
